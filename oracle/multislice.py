@@ -1,0 +1,332 @@
+"""CPU FP64 oracle of the multislice ptychography forward model and its gradient.
+
+TEST INFRASTRUCTURE ONLY.  This module is the independent reference that the
+GPU library is checked against.  Only ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` may import it; the product path
+never does.  It shares no code with the HIP kernels (FFTs come from
+``scipy.fft``/pocketfft, everything else is plain NumPy in float64).
+
+Conventions (the paper leaves these open; the reading taken here is stated
+once and used everywhere):
+
+* ``F`` is the unitary 2D DFT with NumPy's sign, ``fft2(norm="ortho")``, and
+  ``F^-1`` its inverse.  The paper's Fraunhofer transform has a positive
+  exponent (Eq. fraunhofer, Sec. S1.C), so in the negative-phase convention it
+  is NumPy's ``ifft2``; the detector image is ``fftshift``-ed so the zero
+  frequency sits at index (N/2, N/2).
+* Frequencies: ``f = fftfreq(N)`` in cycles/pixel for the Fourier shift,
+  ``nu = fftfreq(N, dx)`` in 1/m for the Fresnel kernel.
+* A position r (float, top-left chunk corner, (y, x), object pixels) splits
+  into the integer corner ``c = floor(r + 0.5)`` and the residual shift
+  ``s = r - c``; the probe is moved by s with the Fourier shift theorem
+  (Eq. fourier_shift) so that ``p_s(x) = p(x - s)`` (circularly).
+* S slices give S - 1 inter-slice Fresnel propagations (Eq. multislice
+  product, Sec. S1.C): the wave is modulated by slice j, propagated to slice
+  j+1, ..., and the exit wave after the last modulation goes to the far field.
+* Loss normalisation: the mean over all B*N^2 pixels of a minibatch.  The
+  small constant eps sits inside both square roots of the LSQ loss
+  (Eq. lsq_loss) and inside the logarithm of the Poisson loss (Eq.
+  poisson_loss).
+* Complex gradients follow dL/dRe + i dL/dIm.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import scipy.fft as sfft
+
+_WORKERS = os.cpu_count() or 1
+
+
+# ---------------------------------------------------------------------------
+# Transforms (Sec. S1.C, Eq. fraunhofer and the sign-convention paragraph)
+# ---------------------------------------------------------------------------
+
+def fft2u(a):
+    """Unitary forward 2D DFT over the last two axes (NumPy sign)."""
+    return sfft.fft2(a, norm="ortho", workers=_WORKERS)
+
+
+def ifft2u(a):
+    """Unitary inverse 2D DFT over the last two axes."""
+    return sfft.ifft2(a, norm="ortho", workers=_WORKERS)
+
+
+def far_field(exit_wave):
+    """Fraunhofer propagation to the detector, Eq. fraunhofer.
+
+    The transform has a positive exponent in the negative-phase convention,
+    i.e. the inverse DFT; the result is centred with ``fftshift``.
+    """
+    return np.fft.fftshift(ifft2u(exit_wave), axes=(-2, -1))
+
+
+def far_field_adjoint(g_det):
+    """Adjoint of ``far_field``: un-centre, then the forward unitary DFT."""
+    return fft2u(np.fft.ifftshift(g_det, axes=(-2, -1)))
+
+
+# ---------------------------------------------------------------------------
+# Fresnel propagation (Eqs. fresnel_prop and paraxial_kernel)
+# ---------------------------------------------------------------------------
+
+def fresnel_kernel(n, wavelength_m, pixel_m, dist_m):
+    """Paraxial transfer function H1(nu, d) = exp(i pi lambda d |nu|^2)."""
+    nu = np.fft.fftfreq(n, d=pixel_m)
+    nu2 = nu[:, None] ** 2 + nu[None, :] ** 2
+    return np.exp(1j * np.pi * wavelength_m * dist_m * nu2)
+
+
+def fresnel_propagate(psi, h):
+    """Fresnel propagation F^-1{ F[psi] H }, Eq. fresnel_prop."""
+    return ifft2u(fft2u(psi) * h)
+
+
+def fresnel_propagate_adjoint(g, h):
+    """Adjoint of ``fresnel_propagate``: F^-1{ F[g] conj(H) }."""
+    return ifft2u(fft2u(g) * np.conj(h))
+
+
+# ---------------------------------------------------------------------------
+# Probe placement (Eq. fourier_shift; position split, Sec. S1.D)
+# ---------------------------------------------------------------------------
+
+def split_position(r):
+    """Integer corner floor(r + 0.5) and subpixel residual r - corner."""
+    r = np.asarray(r, dtype=np.float64)
+    c = np.floor(r + 0.5)
+    return c.astype(np.int64), r - c
+
+
+def shift_ramp(n, shift):
+    """exp(-2 pi i (s_y f_y + s_x f_x)) for shifts ``[..., 2]`` (cycles/px freq)."""
+    f = np.fft.fftfreq(n)
+    s = np.asarray(shift, dtype=np.float64)
+    return np.exp(-2j * np.pi * (s[..., 0, None, None] * f[:, None] + s[..., 1, None, None] * f[None, :]))
+
+
+def fourier_shift(probe, shift):
+    """Shift the probe by ``shift`` pixels: F^-1{ F[p] exp(-2 pi i s.f) }."""
+    return ifft2u(fft2u(probe) * shift_ramp(probe.shape[-1], shift))
+
+
+# ---------------------------------------------------------------------------
+# Object modulation (Eqs. complex_modulation and ri_modulation)
+# ---------------------------------------------------------------------------
+
+def k_dz(wavelength_m, dz_m):
+    """k * dz with k = 2 pi / lambda (Eq. ri_modulation)."""
+    return 2.0 * np.pi / wavelength_m * dz_m
+
+
+def transmission(a, b, obj_repr, kdz):
+    """Per-slice transmission t.
+
+    ``delta_beta``: t = exp(-k beta dz) exp(i k delta dz)  (Eq. ri_modulation).
+    ``real_imag``:  t = Re O + i Im O                    (Eq. complex_modulation).
+    """
+    if obj_repr == "delta_beta":
+        return np.exp(1j * kdz * a - kdz * b)
+    if obj_repr == "real_imag":
+        return a + 1j * b
+    raise ValueError(obj_repr)
+
+
+def take_chunks(obj, corners, n):
+    """Object chunks on each beam path (Alg. 1, TakeObjectChunk).
+
+    ``obj`` is [S][Ly][Lx]; returns [B][S][N][N].  Raises if a chunk leaves
+    the object (the paper pads the object instead; this library treats it as
+    an error).
+    """
+    s, ly, lx = obj.shape
+    out = np.empty((len(corners), s, n, n), dtype=obj.dtype)
+    for b, (cy, cx) in enumerate(np.asarray(corners)):
+        if cy < 0 or cx < 0 or cy + n > ly or cx + n > lx:
+            raise IndexError(f"chunk {b} at ({cy},{cx}) leaves the {ly}x{lx} object")
+        out[b] = obj[:, cy:cy + n, cx:cx + n]
+    return out
+
+
+def scatter_chunks(g_chunks, corners, obj_shape):
+    """Transpose of ``take_chunks``: add chunk gradients into the object."""
+    g = np.zeros(obj_shape, dtype=g_chunks.dtype)
+    n = g_chunks.shape[-1]
+    for b, (cy, cx) in enumerate(np.asarray(corners)):
+        g[:, cy:cy + n, cx:cx + n] += g_chunks[b]
+    return g
+
+
+# ---------------------------------------------------------------------------
+# Forward model (Alg. 1; multislice, Sec. S1.C)
+# ---------------------------------------------------------------------------
+
+class Geometry:
+    """Physical parameters of one scan."""
+
+    def __init__(self, n, n_slices, wavelength_m, pixel_m, slice_dz_m, obj_repr="delta_beta",
+                 loss="gaussian", eps=1e-6):
+        self.n = int(n)
+        self.n_slices = int(n_slices)
+        self.wavelength_m = float(wavelength_m)
+        self.pixel_m = float(pixel_m)
+        self.slice_dz_m = float(slice_dz_m)
+        self.obj_repr = obj_repr
+        self.loss = loss
+        self.eps = float(eps)
+
+    @property
+    def kdz(self):
+        return k_dz(self.wavelength_m, self.slice_dz_m)
+
+    @property
+    def h(self):
+        return fresnel_kernel(self.n, self.wavelength_m, self.pixel_m, self.slice_dz_m)
+
+    @classmethod
+    def from_scan(cls, scan):
+        return cls(scan.n, scan.n_slices, scan.wavelength_m, scan.pixel_m, scan.slice_dz_m,
+                   scan.obj_repr, scan.loss, scan.eps)
+
+
+def exit_waves(geom, obj_a, obj_b, probe, positions, keep_slices=False):
+    """Exit waves for every position of a batch (Alg. 1 up to MultislicePropagate).
+
+    For position b: p_b = FourierShift(p, s_b); psi_0 = p_b; for each slice
+    j: phi_j = psi_j * t_j, and for j < S-1 psi_{j+1} = Fresnel(phi_j).
+    Returns phi_{S-1} [B][N][N]; with ``keep_slices`` also every psi_j and
+    phi_j, each [B][S][N][N].
+    """
+    corners, shifts = split_position(positions)
+    n, s = geom.n, geom.n_slices
+    ta = take_chunks(obj_a, corners, n)
+    tb = take_chunks(obj_b, corners, n)
+    t = transmission(ta, tb, geom.obj_repr, geom.kdz)          # [B][S][N][N]
+    psi = fourier_shift(probe, shifts)                          # [B][N][N]
+    h = geom.h
+    if keep_slices:
+        psis = np.empty((len(corners), s, n, n), dtype=np.complex128)
+        phis = np.empty_like(psis)
+    phi = None
+    for j in range(s):
+        phi = psi * t[:, j]
+        if keep_slices:
+            psis[:, j] = psi
+            phis[:, j] = phi
+        if j < s - 1:
+            psi = fresnel_propagate(phi, h)
+    return (phi, psis, phis) if keep_slices else phi
+
+
+def forward(geom, obj_a, obj_b, probe, positions):
+    """Predicted far-field intensities I = |far_field(exit)|^2, [B][N][N]."""
+    return np.abs(far_field(exit_waves(geom, obj_a, obj_b, probe, positions))) ** 2
+
+
+def forward_pure_projection(geom, obj_a, obj_b, probe, positions):
+    """Projection-approximation exit wave (Eqs. obj_complex_modulation, obj_ri_modulation).
+
+    delta_beta: psi * exp(-k dz sum beta) * exp(i k dz sum delta);
+    real_imag:  psi * prod_j O_j.
+    """
+    corners, shifts = split_position(positions)
+    ta = take_chunks(obj_a, corners, geom.n)
+    tb = take_chunks(obj_b, corners, geom.n)
+    psi = fourier_shift(probe, shifts)
+    if geom.obj_repr == "delta_beta":
+        return psi * np.exp(-geom.kdz * tb.sum(axis=1)) * np.exp(1j * geom.kdz * ta.sum(axis=1))
+    return psi * np.prod(ta + 1j * tb, axis=1)
+
+
+# ---------------------------------------------------------------------------
+# Loss (Eqs. lsq_loss, poisson_loss)
+# ---------------------------------------------------------------------------
+
+def loss_value(kind, i_pred, i_meas, eps, n_norm=None):
+    """Data mismatch D averaged over all pixels of the batch."""
+    n_norm = i_pred.size if n_norm is None else n_norm
+    if kind == "gaussian":
+        return float(np.sum((np.sqrt(i_pred + eps) - np.sqrt(i_meas + eps)) ** 2) / n_norm)
+    if kind == "poisson":
+        return float(np.sum(i_pred - i_meas * np.log(i_pred + eps)) / n_norm)
+    raise ValueError(kind)
+
+
+def loss_dI(kind, i_pred, i_meas, eps, n_norm):
+    """dD/dI_pred elementwise."""
+    if kind == "gaussian":
+        return (1.0 - np.sqrt(i_meas + eps) / np.sqrt(i_pred + eps)) / n_norm
+    if kind == "poisson":
+        return (1.0 - i_meas / (i_pred + eps)) / n_norm
+    raise ValueError(kind)
+
+
+def loss(geom, obj_a, obj_b, probe, positions, i_meas):
+    return loss_value(geom.loss, forward(geom, obj_a, obj_b, probe, positions), i_meas, geom.eps)
+
+
+# ---------------------------------------------------------------------------
+# Gradient (reverse sweep through the multislice product)
+# ---------------------------------------------------------------------------
+
+def loss_grad(geom, obj_a, obj_b, probe, positions, i_meas):
+    """Loss and its gradient w.r.t. the object, the probe and the shifts.
+
+    Differentiates D(I(x)) through the steps of ``exit_waves`` in reverse:
+    the far-field residual g = 2 dD/dI * Psi is pulled back through the
+    Fraunhofer transform, then through each slice (modulation and Fresnel
+    propagation, whose adjoints are multiplication by conj(t) and
+    propagation with conj(H)), the Fourier shift and the chunk gather.
+
+    Returns (loss, g_a [S][Ly][Lx], g_b [S][Ly][Lx], g_probe [N][N] complex,
+    g_shift [B][2]).  ``g_shift`` is dL/ds for the residual shift s of each
+    position, which equals dL/dr for the float position r.
+    """
+    corners, shifts = split_position(positions)
+    n, s = geom.n, geom.n_slices
+    kdz = geom.kdz
+    h = geom.h
+    ta = take_chunks(obj_a, corners, n)
+    tb = take_chunks(obj_b, corners, n)
+    t = transmission(ta, tb, geom.obj_repr, kdz)
+    exit_phi, psis, phis = exit_waves(geom, obj_a, obj_b, probe, positions, keep_slices=True)
+    psi_det = far_field(exit_phi)
+    i_pred = np.abs(psi_det) ** 2
+    n_norm = i_pred.size
+    value = loss_value(geom.loss, i_pred, i_meas, geom.eps, n_norm)
+
+    g_det = 2.0 * loss_dI(geom.loss, i_pred, i_meas, geom.eps, n_norm) * psi_det
+    lam = far_field_adjoint(g_det)                       # dL/dphi_{S-1}
+    g_ta = np.empty_like(ta)
+    g_tb = np.empty_like(tb)
+    for j in range(s - 1, -1, -1):
+        if geom.obj_repr == "delta_beta":
+            # phi = psi exp(i u - v), u = kdz delta, v = kdz beta:
+            # dL/du = Im(conj(phi) lam), dL/dv = -Re(conj(phi) lam)
+            z = np.conj(phis[:, j]) * lam
+            g_ta[:, j] = kdz * np.imag(z)
+            g_tb[:, j] = -kdz * np.real(z)
+        else:
+            # phi = psi O (complex-linear in O): dL/dO = conj(psi) lam
+            z = np.conj(psis[:, j]) * lam
+            g_ta[:, j] = np.real(z)
+            g_tb[:, j] = np.imag(z)
+        mu = np.conj(t[:, j]) * lam                      # dL/dpsi_j
+        if j > 0:
+            lam = fresnel_propagate_adjoint(mu, h)       # dL/dphi_{j-1}
+    g_pb = mu                                            # dL/d(shifted probe)
+
+    # Fourier shift: p_b = F^-1[ P e_b ],  P = F[p],  e_b = exp(-2 pi i s_b.f)
+    e = shift_ramp(n, shifts)
+    big_g = fft2u(g_pb)
+    big_p = fft2u(probe)
+    g_probe = ifft2u(np.sum(big_g * np.conj(e), axis=0))
+    f = np.fft.fftfreq(n)
+    z = np.conj(big_g) * big_p[None] * e
+    g_shift = np.stack([np.sum(np.real(z * (-2j * np.pi) * f[None, :, None]), axis=(1, 2)),
+                        np.sum(np.real(z * (-2j * np.pi) * f[None, None, :]), axis=(1, 2))], axis=1)
+
+    g_a = scatter_chunks(g_ta, corners, obj_a.shape)
+    g_b = scatter_chunks(g_tb, corners, obj_b.shape)
+    return value, g_a, g_b, g_probe, g_shift
