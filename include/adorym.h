@@ -1,0 +1,141 @@
+/*
+ * adorym.h -- C ABI of the MI355X multislice ptychography library.
+ *
+ * The library evaluates the far-field multislice forward model of the
+ * paper's automatic-differentiation reconstruction framework and the
+ * gradient of its data-mismatch loss:
+ *
+ *   y = F(x, theta),   L = D(y_meas, F(x, theta))
+ *
+ * (problem statement, Sec. 1, Eqs. forward_model / problem_equation /
+ * loss_function), where x is the object (delta/beta refractive-index
+ * decrements, Eq. ri_modulation, or real/imaginary transmission,
+ * Eq. complex_modulation) and theta the probe and the per-position
+ * subpixel shifts.  For each scan position the object chunk on the beam
+ * path is gathered, the probe is placed by a Fourier shift
+ * (Eq. fourier_shift), the wave is modulated by each slice and propagated
+ * to the next with the paraxial Fresnel kernel (Eqs. fresnel_prop,
+ * paraxial_kernel; multislice product, Sec. S1.C), and the exit wave is
+ * taken to the detector with the Fraunhofer transform (Eq. fraunhofer);
+ * Alg. 1 gives the order of these steps.  The loss is the LSQ amplitude
+ * mismatch (Eq. lsq_loss) or the Poisson likelihood (Eq. poisson_loss).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array pointer is a DEVICE pointer owned by the caller; the
+ *    library never frees or retains it past the call.  Complex arrays are
+ *    interleaved (re, im) float32 pairs.
+ *  - All calls are asynchronous on the context's stream; no call
+ *    synchronises the host or allocates device memory, except
+ *    adorym_create / adorym_destroy / adorym_sync_error.
+ *  - Host-checkable errors return at once and enqueue nothing.  Errors
+ *    only the device can see (a chunk that leaves the object) set a
+ *    sticky flag read by adorym_sync_error; the offending positions
+ *    contribute nothing (zero intensity, zero gradient, zero loss).
+ *  - Object arrays are slice-major planar float32 [S][Ly][Lx]; element
+ *    (j, y, x) is at j*Ly*Lx + y*Lx + x.
+ *  - Positions: int32 corners [B][2] (y, x) of the N x N chunk in object
+ *    pixels, and float32 residual shifts [B][2] (y, x) in pixels.  The
+ *    probe is shifted so that p_b(r) = p(r - s) (periodic).  A float
+ *    position r is passed as corner floor(r + 0.5) and shift r - corner.
+ *  - The FFT convention: unitary transforms; the far field is the
+ *    positive-exponent (inverse) DFT of the exit wave, centred so that the
+ *    zero frequency lies at (N/2, N/2) of the [N][N] detector array.
+ *  - S slices give S - 1 inter-slice propagations by the slice spacing.
+ *  - Loss = mean over the B*N*N detector pixels of the call; eps is added
+ *    inside both square roots (LSQ) and inside the logarithm (Poisson).
+ *  - Complex gradients are dL/dRe + i dL/dIm.
+ */
+#ifndef ADORYM_H
+#define ADORYM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct adorym_ctx adorym_ctx;
+
+typedef enum {
+  ADORYM_OK = 0,
+  ADORYM_EINVAL = 1,        /* bad argument (null pointer, size < 1, ...)         */
+  ADORYM_EUNSUPPORTED = 2,  /* e.g. a probe size N the library has no kernel for  */
+  ADORYM_ERANGE = 3,        /* a chunk left the object (device-detected, deferred) */
+  ADORYM_ENOMEM = 4,        /* workspace smaller than adorym_workspace_size        */
+  ADORYM_EDEVICE = 5        /* a HIP runtime call failed                           */
+} adorym_status;
+
+enum { ADORYM_LOSS_GAUSSIAN = 0, ADORYM_LOSS_POISSON = 1 };
+enum { ADORYM_OBJ_DELTA_BETA = 0, ADORYM_OBJ_REAL_IMAG = 1 };
+enum {
+  ADORYM_ACCUMULATE_GRADS = 1u  /* add into the gradient arrays instead of overwriting */
+};
+
+/* Geometry and options of one scan. */
+typedef struct {
+  int32_t n;            /* probe / chunk / detector size N (N x N)                 */
+  int32_t n_slices;     /* S >= 1                                                  */
+  int32_t obj_ny;       /* Ly                                                      */
+  int32_t obj_nx;       /* Lx                                                      */
+  double wavelength_m;  /* lambda; k = 2 pi / lambda                               */
+  double pixel_m;       /* lateral pixel size dx (Fresnel kernel frequencies)      */
+  double slice_dz_m;    /* slice spacing dz (Fresnel distance and k dz)            */
+  int32_t loss;         /* ADORYM_LOSS_*                                           */
+  int32_t obj_repr;     /* ADORYM_OBJ_*                                            */
+  int32_t ckpt_every;   /* slice checkpoint interval C (>= 1; 16 is typical)       */
+  double eps;           /* loss epsilon (photons)                                  */
+  uint32_t flags;       /* ADORYM_ACCUMULATE_GRADS                                 */
+} adorym_geom;
+
+/* Create a context on HIP device `device` issuing work on `stream`
+ * (a hipStream_t; NULL = the null stream).  Allocates a few bytes of
+ * device memory for the deferred error flag. */
+adorym_status adorym_create(adorym_ctx** out, int device, void* stream);
+adorym_status adorym_destroy(adorym_ctx* ctx);
+/* Change the stream later calls are enqueued on. */
+adorym_status adorym_set_stream(adorym_ctx* ctx, void* stream);
+
+/* Probe sizes with a kernel: returns 1 if N is supported. */
+int adorym_supports_n(int32_t n);
+
+/* Bytes of device workspace adorym_forward / adorym_loss_grad need for a
+ * batch of `batch` positions (probe spectrum, per-position loss and probe
+ * partials, slice checkpoints every ckpt_every slices).  0 on bad input. */
+size_t adorym_workspace_size(const adorym_geom* g, int32_t batch);
+
+/* Forward model (Alg. 1 without refinement of anything): predicted
+ * far-field intensities |Psi|^2, float32 [B][N][N], zero frequency at
+ * (N/2, N/2).  obj_a/obj_b: delta/beta or real/imag [S][Ly][Lx];
+ * probe complex [N][N].  Workspace of adorym_workspace_size bytes. */
+adorym_status adorym_forward(adorym_ctx* ctx, const adorym_geom* g,
+                             const float* obj_a, const float* obj_b, const float* probe,
+                             const int32_t* corner, const float* shift, int32_t batch,
+                             float* intensity, void* workspace, size_t ws_bytes);
+
+/* Loss and gradient.  i_meas float32 [B][N][N] (zero frequency at N/2).
+ * Writes *loss (device double), and, for every gradient pointer that is
+ * not NULL: g_a/g_b [S][Ly][Lx] (dL/ddelta, dL/dbeta or dL/dRe O, dL/dIm O),
+ * g_probe complex [N][N], g_shift [B][2] (dL/ds, equal to dL/dr).
+ * Gradients overwrite unless ADORYM_ACCUMULATE_GRADS is set.  `intensity`
+ * may be NULL; if given, the predicted intensities are written too. */
+adorym_status adorym_loss_grad(adorym_ctx* ctx, const adorym_geom* g,
+                               const float* obj_a, const float* obj_b, const float* probe,
+                               const int32_t* corner, const float* shift, int32_t batch,
+                               const float* i_meas, void* workspace, size_t ws_bytes,
+                               double* loss, float* g_a, float* g_b, float* g_probe,
+                               float* g_shift, float* intensity);
+
+/* Synchronise the context's stream, return (and clear) any deferred
+ * device-side error, e.g. ADORYM_ERANGE. */
+adorym_status adorym_sync_error(adorym_ctx* ctx);
+
+/* Human-readable description of the last error on this context. */
+const char* adorym_last_error_message(adorym_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADORYM_H */

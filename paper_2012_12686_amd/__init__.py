@@ -1,0 +1,6 @@
+"""MI355X-native multislice ptychography forward model and gradient.
+
+The computation lives in the HIP library ``libadorym.so`` (C ABI in
+``include/adorym.h``); this package is its Python binding.
+"""
+from .api import Context, Geometry, split_positions, supports_n  # noqa: F401

@@ -1,0 +1,82 @@
+"""ctypes binding of the C ABI declared in include/adorym.h.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libadorym.so``.  The library must have been built
+(``python -m paper_2012_12686_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libadorym.so")
+
+# adorym_status
+OK, EINVAL, EUNSUPPORTED, ERANGE, ENOMEM, EDEVICE = 0, 1, 2, 3, 4, 5
+STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ERANGE: "ERANGE",
+                ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"}
+LOSS_GAUSSIAN, LOSS_POISSON = 0, 1
+OBJ_DELTA_BETA, OBJ_REAL_IMAG = 0, 1
+ACCUMULATE_GRADS = 1
+
+
+class Geom(ctypes.Structure):
+    """Mirror of ``adorym_geom``."""
+
+    _fields_ = [
+        ("n", ctypes.c_int32), ("n_slices", ctypes.c_int32),
+        ("obj_ny", ctypes.c_int32), ("obj_nx", ctypes.c_int32),
+        ("wavelength_m", ctypes.c_double), ("pixel_m", ctypes.c_double), ("slice_dz_m", ctypes.c_double),
+        ("loss", ctypes.c_int32), ("obj_repr", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
+        ("eps", ctypes.c_double), ("flags", ctypes.c_uint32),
+    ]
+
+
+# name -> (restype, argtypes); every function include/adorym.h declares
+_P = ctypes.c_void_p
+_GP = ctypes.POINTER(Geom)
+SIGNATURES = {
+    "adorym_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P]),
+    "adorym_destroy": (ctypes.c_int, [_P]),
+    "adorym_set_stream": (ctypes.c_int, [_P, _P]),
+    "adorym_supports_n": (ctypes.c_int, [ctypes.c_int32]),
+    "adorym_workspace_size": (ctypes.c_size_t, [_GP, ctypes.c_int32]),
+    "adorym_forward": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t]),
+    "adorym_loss_grad": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t,
+                                        _P, _P, _P, _P, _P, _P]),
+    "adorym_sync_error": (ctypes.c_int, [_P]),
+    "adorym_last_error_message": (ctypes.c_char_p, [_P]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libadorym.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2012_12686_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class AdorymError(RuntimeError):
+    def __init__(self, status, message=""):
+        super().__init__(f"adorym: {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def check(status, ctx=None):
+    if status != OK:
+        msg = ""
+        if ctx is not None:
+            raw = load().adorym_last_error_message(ctx)
+            msg = raw.decode() if raw else ""
+        raise AdorymError(status, msg)

@@ -1,0 +1,161 @@
+"""Python front end of libadorym over torch device tensors.
+
+PyTorch supplies device memory and the stream; the computation is the C ABI
+(include/adorym.h).  All functions here only check shapes/dtypes, allocate
+outputs and workspace, and pass raw device pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import Geom, check, load
+
+LOSSES = {"gaussian": _lib.LOSS_GAUSSIAN, "poisson": _lib.LOSS_POISSON}
+REPRS = {"delta_beta": _lib.OBJ_DELTA_BETA, "real_imag": _lib.OBJ_REAL_IMAG}
+
+
+@dataclasses.dataclass
+class Geometry:
+    """Scan geometry and options (mirrors ``adorym_geom``)."""
+
+    n: int
+    n_slices: int
+    obj_ny: int
+    obj_nx: int
+    wavelength_m: float
+    pixel_m: float
+    slice_dz_m: float
+    loss: str = "gaussian"
+    obj_repr: str = "delta_beta"
+    ckpt_every: int = 16
+    eps: float = 1e-6
+    accumulate: bool = False
+
+    def to_c(self) -> Geom:
+        return Geom(self.n, self.n_slices, self.obj_ny, self.obj_nx, self.wavelength_m, self.pixel_m,
+                    self.slice_dz_m, LOSSES[self.loss], REPRS[self.obj_repr], self.ckpt_every, self.eps,
+                    _lib.ACCUMULATE_GRADS if self.accumulate else 0)
+
+    @classmethod
+    def from_scan(cls, scan, **kw):
+        s, ly, lx = scan.obj_shape
+        return cls(scan.n, s, ly, lx, scan.wavelength_m, scan.pixel_m, scan.slice_dz_m, scan.loss,
+                   scan.obj_repr, eps=scan.eps, **kw)
+
+
+def split_positions(pos: torch.Tensor):
+    """Float (y, x) positions -> int32 corners floor(r + 0.5) and float32 shifts r - corner."""
+    corner = torch.floor(pos.double() + 0.5)
+    shift = (pos.double() - corner).float()
+    return corner.to(torch.int32).contiguous(), shift.contiguous()
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Context:
+    """One library context per device/stream."""
+
+    def __init__(self, device: Optional[torch.device] = None):
+        load()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._ctx = ctypes.c_void_p(0)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        check(load().adorym_create(ctypes.byref(self._ctx), self.device.index or 0, ctypes.c_void_p(stream)))
+
+    def _bind_stream(self):
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        check(load().adorym_set_stream(self._ctx, ctypes.c_void_p(stream)), self._ctx)
+
+    def close(self):
+        if self._ctx:
+            load().adorym_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync_error(self):
+        """Synchronise and raise on a deferred device error (e.g. a chunk out of range)."""
+        check(load().adorym_sync_error(self._ctx), self._ctx)
+
+    # --------------------------------------------------------------- calls
+    def workspace_size(self, geom: Geometry, batch: int) -> int:
+        return int(load().adorym_workspace_size(ctypes.byref(geom.to_c()), batch))
+
+    def workspace(self, geom: Geometry, batch: int) -> torch.Tensor:
+        return torch.empty(self.workspace_size(geom, batch), dtype=torch.uint8, device=self.device)
+
+    def _check_inputs(self, geom, obj_a, obj_b, probe, corner, shift):
+        n, s, ly, lx = geom.n, geom.n_slices, geom.obj_ny, geom.obj_nx
+        for t, shape, dt, name in ((obj_a, (s, ly, lx), torch.float32, "obj_a"),
+                                   (obj_b, (s, ly, lx), torch.float32, "obj_b"),
+                                   (probe, (n, n), torch.complex64, "probe")):
+            if tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous() or t.device != self.device:
+                raise ValueError(f"{name}: expected contiguous {dt} {shape} on {self.device}, got "
+                                 f"{t.dtype} {tuple(t.shape)} on {t.device}")
+        b = corner.shape[0]
+        if corner.dtype != torch.int32 or tuple(corner.shape) != (b, 2) or not corner.is_contiguous():
+            raise ValueError("corner: expected contiguous int32 [B][2]")
+        if shift.dtype != torch.float32 or tuple(shift.shape) != (b, 2) or not shift.is_contiguous():
+            raise ValueError("shift: expected contiguous float32 [B][2]")
+        return b
+
+    def forward(self, geom, obj_a, obj_b, probe, corner, shift, out=None, workspace=None):
+        """Predicted intensities [B][N][N] (zero frequency at N/2)."""
+        self._bind_stream()
+        b = self._check_inputs(geom, obj_a, obj_b, probe, corner, shift)
+        out = out if out is not None else torch.empty((b, geom.n, geom.n), dtype=torch.float32, device=self.device)
+        ws = workspace if workspace is not None else self.workspace(geom, b)
+        st = load().adorym_forward(self._ctx, ctypes.byref(geom.to_c()), _ptr(obj_a), _ptr(obj_b),
+                                   _ptr(torch.view_as_real(probe)), _ptr(corner), _ptr(shift), b, _ptr(out),
+                                   _ptr(ws), ws.numel())
+        check(st, self._ctx)
+        return out
+
+    def loss_grad(self, geom, obj_a, obj_b, probe, corner, shift, i_meas, grads=True, intensity=False,
+                  out=None, workspace=None):
+        """Loss (device float64 scalar) and gradients.
+
+        Returns dict with ``loss`` and, if ``grads``, ``g_a``, ``g_b``, ``g_probe``
+        (complex64), ``g_shift``; with ``intensity`` also the predicted ``intensity``.
+        ``out`` may carry preallocated tensors under the same names.
+        """
+        self._bind_stream()
+        b = self._check_inputs(geom, obj_a, obj_b, probe, corner, shift)
+        if tuple(i_meas.shape) != (b, geom.n, geom.n) or i_meas.dtype != torch.float32 or not i_meas.is_contiguous():
+            raise ValueError("i_meas: expected contiguous float32 [B][N][N]")
+        out = dict(out or {})
+        dev = self.device
+        if "loss" not in out:
+            out["loss"] = torch.empty((), dtype=torch.float64, device=dev)
+        if grads:
+            for name, shape, dt in (("g_a", obj_a.shape, torch.float32), ("g_b", obj_b.shape, torch.float32),
+                                    ("g_probe", probe.shape, torch.complex64), ("g_shift", (b, 2), torch.float32)):
+                if name not in out:
+                    out[name] = (torch.zeros if geom.accumulate else torch.empty)(shape, dtype=dt, device=dev)
+        if intensity and "intensity" not in out:
+            out["intensity"] = torch.empty((b, geom.n, geom.n), dtype=torch.float32, device=dev)
+        ws = workspace if workspace is not None else self.workspace(geom, b)
+        gp = out.get("g_probe")
+        st = load().adorym_loss_grad(
+            self._ctx, ctypes.byref(geom.to_c()), _ptr(obj_a), _ptr(obj_b), _ptr(torch.view_as_real(probe)),
+            _ptr(corner), _ptr(shift), b, _ptr(i_meas), _ptr(ws), ws.numel(), _ptr(out["loss"]),
+            _ptr(out.get("g_a")), _ptr(out.get("g_b")), _ptr(torch.view_as_real(gp) if gp is not None else None),
+            _ptr(out.get("g_shift")), _ptr(out.get("intensity")))
+        check(st, self._ctx)
+        return out
+
+
+def supports_n(n: int) -> bool:
+    return bool(load().adorym_supports_n(n))

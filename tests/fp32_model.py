@@ -1,0 +1,86 @@
+"""Float32 reference model: the conditioning floor of any FP32 implementation.
+
+TEST INFRASTRUCTURE ONLY.  This is the plain multislice forward model and its
+gradient written exactly like the FP64 oracle (every slice wave stored, no
+checkpoints, no inversion), but evaluated in complex64/float32 with SciPy's
+single-precision FFTs.  Its distance to the FP64 oracle measures how much a
+faithful float32 evaluation of the *same mathematics* must deviate at a
+given evaluation point.  Where that floor is above the gradient tolerance
+(ill-conditioned points: Poisson residuals of far-field pixels the model
+barely illuminates, or weak absorption gradients that are small real parts
+of large complex products) the parity tests bound the GPU error by a small
+multiple of this floor instead, and print both.
+
+It shares no code with the HIP library and is never used by it.
+"""
+import numpy as np
+import scipy.fft as sfft
+
+C64 = np.complex64
+F32 = np.float32
+
+
+def _c64(x):
+    return np.asarray(x).astype(C64)
+
+
+def loss_grad_fp32(geom, a, b, p, pos, i_meas):
+    n, s = geom.n, geom.n_slices
+    corner = np.floor(pos + 0.5).astype(np.int64)
+    shift = (pos - corner).astype(F32)
+    f = np.fft.fftfreq(n)
+    nu2 = (f[:, None] ** 2 + f[None, :] ** 2) / geom.pixel_m ** 2
+    h = _c64(np.exp(1j * np.pi * geom.wavelength_m * geom.slice_dz_m * nu2))
+    kdz = F32(2 * np.pi / geom.wavelength_m * geom.slice_dz_m)
+    nb = len(corner)
+    ta = np.stack([a[:, cy:cy + n, cx:cx + n] for cy, cx in corner]).astype(F32)
+    tb = np.stack([b[:, cy:cy + n, cx:cx + n] for cy, cx in corner]).astype(F32)
+    if geom.obj_repr == "delta_beta":
+        t = (np.exp(-kdz * tb) * (np.cos(kdz * ta) + 1j * np.sin(kdz * ta))).astype(C64)
+    else:
+        t = (ta + 1j * tb).astype(C64)
+    e = _c64(np.exp(-2j * np.pi * (shift[:, 0, None, None] * f[:, None] + shift[:, 1, None, None] * f[None, :])))
+    pf = sfft.fft2(_c64(p), norm="ortho")
+    psi = sfft.ifft2(pf[None] * e, norm="ortho")
+    psis = np.empty((nb, s, n, n), C64)
+    phis = np.empty((nb, s, n, n), C64)
+    for j in range(s):
+        psis[:, j] = psi
+        phi = psi * t[:, j]
+        phis[:, j] = phi
+        if j < s - 1:
+            psi = sfft.ifft2(sfft.fft2(phi, norm="ortho") * h, norm="ortho")
+    det = np.fft.fftshift(sfft.ifft2(phi, norm="ortho"), axes=(-2, -1))
+    ip = (det.real ** 2 + det.imag ** 2).astype(F32)
+    im = i_meas.astype(F32)
+    eps = F32(geom.eps)
+    nn = F32(ip.size)
+    if geom.loss == "gaussian":
+        sp, sm = np.sqrt(ip + eps), np.sqrt(im + eps)
+        value = float(np.sum(((sp - sm) ** 2).astype(np.float64))) / ip.size
+        dldi = (F32(1) - sm / sp) / nn
+    else:
+        value = float(np.sum((ip - im * np.log(ip + eps)).astype(np.float64))) / ip.size
+        dldi = (F32(1) - im / (ip + eps)) / nn
+    lam = sfft.fft2(np.fft.ifftshift((F32(2) * dldi * det).astype(C64), axes=(-2, -1)), norm="ortho")
+    ga = np.zeros(a.shape, F32)
+    gb = np.zeros(b.shape, F32)
+    for j in range(s - 1, -1, -1):
+        if geom.obj_repr == "delta_beta":
+            z = np.conj(phis[:, j]) * lam
+            da, db = kdz * z.imag, -kdz * z.real
+        else:
+            z = np.conj(psis[:, j]) * lam
+            da, db = z.real, z.imag
+        for k, (cy, cx) in enumerate(corner):
+            ga[j, cy:cy + n, cx:cx + n] += da[k]
+            gb[j, cy:cy + n, cx:cx + n] += db[k]
+        mu = np.conj(t[:, j]) * lam
+        if j > 0:
+            lam = sfft.ifft2(sfft.fft2(mu, norm="ortho") * np.conj(h), norm="ortho")
+    big_g = sfft.fft2(mu, norm="ortho")
+    gp = sfft.ifft2(np.sum(big_g * np.conj(e), axis=0), norm="ortho")
+    z = np.conj(big_g) * pf[None] * e
+    gs = np.stack([2 * np.pi * np.sum(f[None, :, None] * z.imag, axis=(1, 2)),
+                   2 * np.pi * np.sum(f[None, None, :] * z.imag, axis=(1, 2))], axis=1)
+    return value, ga, gb, gp, gs

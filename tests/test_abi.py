@@ -1,0 +1,82 @@
+"""C ABI contract tests that need no GPU.
+
+The library loads, exports every function include/adorym.h declares, the
+ctypes struct mirrors the C struct byte for byte, and host-side argument
+validation and workspace sizing behave as documented.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2012_12686_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "adorym.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(adorym_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    lib = _lib.load()
+    names = declared_functions()
+    assert names, "no declarations found"
+    for n in names:
+        assert hasattr(lib, n), f"{n} not exported"
+    assert sorted(_lib.SIGNATURES) == names
+
+
+def test_geom_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "probe.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "adorym.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(adorym_geom),'
+                   ' offsetof(adorym_geom, wavelength_m), offsetof(adorym_geom, loss),'
+                   ' offsetof(adorym_geom, eps), offsetof(adorym_geom, flags)); return 0;}\n')
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    G = _lib.Geom
+    assert got == [ctypes.sizeof(G), G.wavelength_m.offset, G.loss.offset, G.eps.offset, G.flags.offset]
+
+
+def _geom(**kw):
+    base = dict(n=128, n_slices=64, obj_ny=256, obj_nx=256, wavelength_m=1.24e-10, pixel_m=1e-8,
+                slice_dz_m=1e-8, loss=0, obj_repr=0, ckpt_every=16, eps=1e-6, flags=0)
+    base.update(kw)
+    return _lib.Geom(**base)
+
+
+def test_workspace_size_formula():
+    lib = _lib.load()
+    g = _geom()
+    size = lib.adorym_workspace_size(ctypes.byref(g), 50)
+    nn = 128 * 128 * 8
+    slots = 63 // 16 + 1 + 1            # slices 0, 16, 32, 48 and the last (63)
+    expect = nn + 512 + 50 * nn + 50 * slots * nn
+    assert expect <= size < expect + 4 * 256
+    assert lib.adorym_workspace_size(ctypes.byref(_geom(n_slices=0)), 50) == 0
+    assert lib.adorym_workspace_size(ctypes.byref(g), 0) == 0
+
+
+def test_supported_sizes():
+    lib = _lib.load()
+    assert lib.adorym_supports_n(64) == 1 and lib.adorym_supports_n(128) == 1
+    assert lib.adorym_supports_n(100) == 0 and lib.adorym_supports_n(0) == 0
+
+
+def test_null_context_rejected_without_touching_the_device():
+    lib = _lib.load()
+    g = _geom()
+    st = lib.adorym_forward(None, ctypes.byref(g), None, None, None, None, None, 1, None, None, 0)
+    assert st == _lib.EINVAL
+    st = lib.adorym_loss_grad(None, ctypes.byref(g), None, None, None, None, None, 1, None, None, 0,
+                              None, None, None, None, None, None)
+    assert st == _lib.EINVAL
+    assert lib.adorym_sync_error(None) == _lib.EINVAL
+    assert lib.adorym_destroy(None) == _lib.EINVAL

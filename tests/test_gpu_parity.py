@@ -1,0 +1,189 @@
+"""GPU parity: the HIP library against the FP64 oracle, through the C ABI.
+
+Tolerances (float32 GPU path vs float64 oracle, same float32-rounded inputs):
+  * intensities: relative L2 <= 1e-5;
+  * loss: |dL| <= 2e-5 ||I|| ||dL/dI|| -- the intensity tolerance pushed
+    through the loss by Cauchy-Schwarz (per-pixel terms are float32, the sum
+    float64);
+  * gradients: relative L2 <= 1e-4, or, at evaluation points where even a
+    faithful float32 evaluation of the same mathematics cannot reach 1e-4
+    (the float32 reference model of tests/fp32_model.py), <= 3x that
+    model's own error.  Both numbers are printed.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_helpers import Case, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL_I = 1e-5
+TOL_G = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_12686_amd import Context
+    c = Context()
+    yield c
+    c.close()
+
+
+def _geom(case, **kw):
+    from paper_2012_12686_amd import Geometry
+    return Geometry.from_scan(case.scan, **kw)
+
+
+def run_forward(ctx, case, **kw):
+    import torch
+    inp, _ = case.torch_inputs()
+    out = ctx.forward(_geom(case, **kw), **inp)
+    torch.cuda.synchronize()
+    ctx.sync_error()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def run_grad(ctx, case, **kw):
+    import torch
+    inp, i_meas = case.torch_inputs()
+    out = ctx.loss_grad(_geom(case, **kw), **inp, i_meas=i_meas, intensity=True)
+    torch.cuda.synchronize()
+    ctx.sync_error()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def loss_tolerance(case):
+    """TOL_I * ||I|| * ||dL/dI|| (Cauchy-Schwarz), doubled for rounding."""
+    from oracle import multislice as om
+    i_ref = case.oracle_forward()
+    dldi = om.loss_dI(case.geom.loss, i_ref, case.i_meas, case.geom.eps, i_ref.size)
+    return 2 * TOL_I * np.linalg.norm(i_ref) * np.linalg.norm(dldi)
+
+
+def check_grads(got, ref, case):
+    from tests.fp32_model import loss_grad_fp32
+    L, ga, gb, gp, gs = ref
+    tol_l = loss_tolerance(case)
+    assert abs(float(got["loss"]) - L) <= tol_l, (float(got["loss"]), L, tol_l)
+    model = loss_grad_fp32(case.geom, case.a, case.b, case.p, case.pos, case.i_meas)
+    names = ("g_a", "g_b", "g_probe", "g_shift")
+    for name, r, m in zip(names, (ga, gb, gp, gs), model[1:]):
+        e_gpu, e_f32 = rel_l2(got[name], r), rel_l2(m, r)
+        print(f"{name}: GPU rel-L2 {e_gpu:.3e}   float32-model floor {e_f32:.3e}")
+        assert e_gpu <= max(TOL_G, 3.0 * e_f32), (name, e_gpu, e_f32)
+
+
+# ------------------------------------------------------------------ forward
+
+@pytest.mark.parametrize("n,s,lat,npos,repr_", [
+    (64, 1, 96, 5, "real_imag"),
+    (64, 7, 100, 3, "delta_beta"),
+    (128, 1, 160, 2, "delta_beta"),
+    (128, 20, 150, 3, "delta_beta"),
+    (128, 5, 140, 2, "real_imag"),
+])
+def test_forward_matches_oracle(ctx, n, s, lat, npos, repr_):
+    sc = synth.small_case(seed=100 + n + s, n=n, n_slices=s, lateral=lat, n_pos=npos, obj_repr=repr_,
+                          strength=30.0)
+    case = Case(sc)
+    got = run_forward(ctx, case)
+    ref = case.oracle_forward()
+    err = rel_l2(got, ref)
+    print(sc.name, "intensity rel-L2", err)
+    assert err <= TOL_I
+
+
+# ------------------------------------------------------------------ gradients
+
+@pytest.mark.parametrize("n,s,lat,npos,repr_,loss,ckpt", [
+    (64, 1, 90, 3, "delta_beta", "gaussian", 16),
+    (64, 18, 100, 4, "delta_beta", "gaussian", 16),
+    (64, 18, 100, 4, "delta_beta", "poisson", 16),
+    (64, 9, 96, 3, "delta_beta", "poisson", 4),
+    (64, 3, 90, 3, "real_imag", "gaussian", 16),
+    (128, 33, 150, 3, "delta_beta", "gaussian", 16),
+    (128, 2, 140, 2, "delta_beta", "poisson", 1),
+])
+def test_loss_grad_matches_oracle(ctx, n, s, lat, npos, repr_, loss, ckpt):
+    sc = synth.small_case(seed=200 + n + s, n=n, n_slices=s, lateral=lat, n_pos=npos, obj_repr=repr_,
+                          loss=loss, strength=30.0)
+    case = Case(sc, poisson_seed=7 if loss == "poisson" else None)
+    got = run_grad(ctx, case, ckpt_every=ckpt)
+    ref = case.oracle_loss_grad()
+    assert rel_l2(got["intensity"], case.oracle_forward()) <= TOL_I
+    check_grads(got, ref, case)
+
+
+def test_checkpoint_interval_does_not_change_results(ctx):
+    sc = synth.small_case(seed=31, n=64, n_slices=12, lateral=90, n_pos=3, strength=30.0)
+    case = Case(sc)
+    outs = [run_grad(ctx, case, ckpt_every=c) for c in (1, 3, 16, 1000)]
+    for o in outs[1:]:
+        for k in ("g_a", "g_b", "g_probe", "g_shift"):
+            assert rel_l2(o[k], outs[0][k]) <= TOL_G / 10, k
+
+
+def test_accumulate_flag_adds(ctx):
+    import torch
+    sc = synth.small_case(seed=32, n=64, n_slices=4, lateral=90, n_pos=2, strength=30.0)
+    case = Case(sc)
+    inp, i_meas = case.torch_inputs()
+    g1 = ctx.loss_grad(_geom(case), **inp, i_meas=i_meas)
+    acc = {k: v.clone() for k, v in g1.items() if k != "loss"}
+    ctx.loss_grad(_geom(case, accumulate=True), **inp, i_meas=i_meas, out=acc)
+    torch.cuda.synchronize()
+    for k in ("g_a", "g_b", "g_probe", "g_shift"):
+        assert rel_l2(acc[k].cpu().numpy(), 2 * g1[k].cpu().numpy()) < 1e-6, k
+
+
+def test_chunk_out_of_range_is_flagged_and_skipped(ctx):
+    import torch
+    from paper_2012_12686_amd._lib import AdorymError, ERANGE
+    sc = synth.small_case(seed=33, n=64, n_slices=3, lateral=90, n_pos=3, strength=30.0)
+    case = Case(sc)
+    inp, i_meas = case.torch_inputs()
+    good = ctx.forward(_geom(case), **inp).cpu().numpy()
+    bad_corner = inp["corner"].clone()
+    bad_corner[1, 1] = 90 - 64 + 1          # one column past the edge
+    inp2 = dict(inp, corner=bad_corner)
+    out = ctx.forward(_geom(case), **inp2)
+    with pytest.raises(AdorymError) as ei:
+        ctx.sync_error()
+    assert ei.value.status == ERANGE
+    out = out.cpu().numpy()
+    assert np.all(out[1] == 0)
+    assert np.array_equal(out[[0, 2]], good[[0, 2]])
+    ctx.sync_error()   # flag was cleared
+
+
+def test_loss_is_deterministic(ctx):
+    sc = synth.small_case(seed=34, n=64, n_slices=6, lateral=96, n_pos=5, strength=30.0)
+    case = Case(sc)
+    l1 = run_grad(ctx, case)["loss"]
+    l2 = run_grad(ctx, case)["loss"]
+    assert float(l1) == float(l2)
+
+
+# ------------------------------------------------------------------ the named workloads
+
+def test_config1_ptychography_2d(ctx):
+    """64x64 probe, one slice, complex object 128x128, 64 raster positions, LSQ."""
+    case = Case(synth.config1())
+    got = run_grad(ctx, case)
+    assert rel_l2(got["intensity"], case.oracle_forward()) <= TOL_I
+    check_grads(got, case.oracle_loss_grad(), case)
+
+
+def test_config2_first_minibatch(ctx):
+    """128x128 probe, 64 slices at 10 nm, 256x256 object, minibatch of 50, Poisson."""
+    sc = synth.config2()
+    case = Case(sc, idx=slice(0, 50), poisson_seed=2)
+    got = run_grad(ctx, case)
+    err_i = rel_l2(got["intensity"], case.oracle_forward())
+    print("c2 intensity rel-L2", err_i)
+    assert err_i <= TOL_I
+    check_grads(got, case.oracle_loss_grad(), case)
