@@ -1,0 +1,188 @@
+"""Benchmark: multislice forward + adjoint throughput on one MI355X.
+
+Workload (default): 128x128 probe, 64 slices of delta/beta at 10 nm and
+10 keV, a 256x256 object of random ellipsoids, 400 positions on a jittered
+20x20 raster processed in minibatches of 50, Poisson loss on 1e4-photon
+patterns, evaluated at delta = beta = 0 with the true probe and positions.
+One step = one minibatch through the whole path: chunk gather, Fourier
+shift, slice modulation, Fresnel propagation, far field, loss and the
+reverse sweep with checkpoint re-anchoring and gradient scatter.
+
+Prints ONE JSON line.  `value` = positions per second of the timed steps
+(inputs already resident in HBM).  `roofline` prices the dominant kernel
+(the fused multislice kernel) against HBM peak using algorithmic bytes per
+position 24 N^2 S + 4 N^2 + 16 N^2 ceil(S/16); its duration comes from HIP
+events recorded around each of its launches on its own stream.
+`cpu_baseline` times the FP64 oracle on one full minibatch of the same
+workload on the host cores.
+
+Measured data: Poisson(I_true) with I_true from this library's forward
+model at the ground-truth object (synthetic data, not a parity claim).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP32_PEAK_TFLOPS = 157.3       # MI355X vector FP32, published
+
+
+def algorithmic_bytes_per_position(n, s, c=16):
+    return 24 * n * n * s + 4 * n * n + 16 * n * n * math.ceil(s / c)
+
+
+def algorithmic_flops_per_position(n, s):
+    return 6 * s * 5 * n * n * math.log2(n * n) + 60 * n * n * s
+
+
+def cpu_baseline(sc, mb_idx, i_meas_np):
+    """Time the FP64 oracle (fwd + loss + adjoint) on one minibatch."""
+    from oracle import multislice as om
+    geom = om.Geometry.from_scan(sc)
+    z = np.zeros(sc.obj_shape)
+    pos = sc.positions[mb_idx]
+    t0 = time.perf_counter()
+    om.loss_grad(geom, z, z, sc.probe, pos, i_meas_np)
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"value": len(pos) / dt, "unit": "positions/s", "cores": cores, "kind": "oracle",
+            "sample": f"one minibatch of {len(pos)} positions (N=128, S=64), FP64 fwd+loss+adjoint, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (to scale HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a "
+              f"design note, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")    # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 4}))
+        return
+
+    import synth
+    from paper_2012_12686_amd import Context, Geometry, split_positions
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    sc = synth.config2()
+    n, s = sc.n, sc.n_slices
+    mb = sc.minibatch
+    n_mb = len(sc.positions) // mb
+    ctx = Context(dev)
+    geom = Geometry.from_scan(sc)
+
+    to_t = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device=dev)
+    true_a, true_b = to_t(sc.obj_a, torch.float32), to_t(sc.obj_b, torch.float32)
+    probe = to_t(sc.probe, torch.complex64)
+    corner, shift = split_positions(to_t(sc.positions, torch.float64))
+    # synthetic measurements: Poisson counts of the forward model at the truth
+    i_true = torch.cat([ctx.forward(geom, true_a, true_b, probe, corner[k * mb:(k + 1) * mb],
+                                    shift[k * mb:(k + 1) * mb]) for k in range(n_mb)])
+    rng = np.random.default_rng(2)
+    i_meas_np = rng.poisson(i_true.cpu().numpy().astype(np.float64)).astype(np.float32)
+    i_meas = to_t(i_meas_np, torch.float32)
+
+    # evaluation point: delta = beta = 0
+    a = torch.zeros_like(true_a)
+    b = torch.zeros_like(true_b)
+    ws = ctx.workspace(geom, mb)
+    out = {"loss": torch.empty((), dtype=torch.float64, device=dev),
+           "g_a": torch.empty_like(a), "g_b": torch.empty_like(b),
+           "g_probe": torch.empty_like(probe), "g_shift": torch.empty((mb, 2), dtype=torch.float32, device=dev)}
+
+    def step(k):
+        sl = slice((k % n_mb) * mb, (k % n_mb + 1) * mb)
+        ctx.loss_grad(geom, a, b, probe, corner[sl], shift[sl], i_meas[sl], out=out, workspace=ws)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    ctx.sync_error()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ctx.profile_start(args.steps + 8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record()
+        step(k)
+        ends[k].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms, kern_n = ctx.profile_stop()
+    ctx.sync_error()
+
+    elapsed = t1 - t0
+    ms_step = 1e3 * elapsed / args.steps
+    lat = sorted(st.elapsed_time(en) for st, en in zip(starts, ends))
+    p50 = float(np.percentile(lat, 50))
+    p99 = float(np.percentile(lat, 99))
+    value = mb * args.steps / elapsed
+
+    kern_avg_s = kern_ms / max(kern_n, 1) / 1e3
+    bytes_launch = algorithmic_bytes_per_position(n, s) * mb
+    achieved_gbs = bytes_launch / kern_avg_s / 1e9
+    flops_launch = algorithmic_flops_per_position(n, s) * mb
+    achieved_tflops = flops_launch / kern_avg_s / 1e12
+
+    line = {
+        "metric": "multislice fwd+adjoint positions/s, % HBM roofline; p50/p99 iter latency",
+        "value": value,
+        "unit": "positions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "multislice ptychography N=128 S=64 object 256x256x64 (10 nm, 10 keV), "
+                               "minibatch 50 of 400 positions, Poisson 1e4 photons, fwd+loss+adjoint",
+                   "global_batch": mb, "seq_len": s, "parallelism": "none"},
+        "p50_iter_ms": p50,
+        "p99_iter_ms": p99,
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "multislice_kernel<N=128, delta/beta, Poisson, loss+adjoint>",
+                     "kernel_avg_ms": kern_avg_s * 1e3, "kernel_launches": kern_n,
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "fp32_tflops": achieved_tflops, "fp32_frac": achieved_tflops / FP32_PEAK_TFLOPS},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(sc, slice(0, mb), i_meas_np[:mb].astype(np.float64))
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -134,6 +134,15 @@ adorym_status adorym_sync_error(adorym_ctx* ctx);
 /* Human-readable description of the last error on this context. */
 const char* adorym_last_error_message(adorym_ctx* ctx);
 
+/* Kernel timing for benchmarks.  adorym_profile_start creates up to
+ * max_launches pairs of HIP events (it allocates: call it outside a timed
+ * region); while enabled, every forward / loss_grad call records one pair
+ * around its main multislice kernel on the context's stream.
+ * adorym_profile_stop synchronises the stream and returns the summed
+ * kernel time in milliseconds and the number of timed launches. */
+adorym_status adorym_profile_start(adorym_ctx* ctx, int32_t max_launches);
+adorym_status adorym_profile_stop(adorym_ctx* ctx, double* total_ms, int32_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,7 +36,8 @@ import os
 import numpy as np
 import scipy.fft as sfft
 
-_WORKERS = os.cpu_count() or 1
+# FFT worker threads: the CPU cores this process may run on
+_WORKERS = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
 
 
 # ---------------------------------------------------------------------------

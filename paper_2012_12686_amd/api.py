@@ -89,6 +89,16 @@ class Context:
         """Synchronise and raise on a deferred device error (e.g. a chunk out of range)."""
         check(load().adorym_sync_error(self._ctx), self._ctx)
 
+    def profile_start(self, max_launches: int = 4096):
+        """Time the main multislice kernel of each later call with HIP events."""
+        check(load().adorym_profile_start(self._ctx, max_launches), self._ctx)
+
+    def profile_stop(self):
+        """(summed kernel milliseconds, number of timed launches)."""
+        ms, cnt = ctypes.c_double(0), ctypes.c_int32(0)
+        check(load().adorym_profile_stop(self._ctx, ctypes.byref(ms), ctypes.byref(cnt)), self._ctx)
+        return ms.value, cnt.value
+
     # --------------------------------------------------------------- calls
     def workspace_size(self, geom: Geometry, batch: int) -> int:
         return int(load().adorym_workspace_size(ctypes.byref(geom.to_c()), batch))

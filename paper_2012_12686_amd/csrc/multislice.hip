@@ -21,6 +21,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "../../include/adorym.h"
 #include "fastmath.hpp"
@@ -37,6 +38,10 @@ struct adorym_ctx {
   hipStream_t stream;
   int* d_err;          // deferred device error flags (bit 0: chunk out of range)
   char msg[512];
+  // optional timing of the main multislice kernel (adorym_profile_*)
+  std::vector<hipEvent_t> ev;   // start/stop pairs
+  int ev_used = 0;
+  bool prof = false;
 };
 
 namespace {
@@ -591,6 +596,7 @@ adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const f
   P.inv_n = 1.0 / ((double)batch * g->n * g->n);
 
   hipStream_t st = ctx->stream;
+  const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
   hipLaunchKernelGGL((probe_spectrum_kernel<C>), dim3(1), dim3(C::THREADS), 0, st,
                      reinterpret_cast<const float2*>(probe), const_cast<float2*>(P.q));
   if (with_loss) {
@@ -599,11 +605,15 @@ adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const f
       if (g_a) fill(st, g_a, nobj, 0.f);
       if (g_b) fill(st, g_b, nobj, 0.f);
     }
+    if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
     launch_ms<C, true>(P, g->obj_repr, g->loss, batch, st);
+    if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
     hipLaunchKernelGGL((finalize_kernel<C>), dim3(1), dim3(C::THREADS), 0, st, P.loss_part, batch, loss,
                        P.gacc, reinterpret_cast<float2*>(g_probe), P.accumulate);
   } else {
+    if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
     launch_ms<C, false>(P, g->obj_repr, g->loss, batch, st);
+    if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
@@ -641,14 +651,15 @@ adorym_status adorym_create(adorym_ctx** out, int device, void* stream) {
   c->stream = static_cast<hipStream_t>(stream);
   c->msg[0] = 0;
   if (hipMalloc(&c->d_err, 256) != hipSuccess) { delete c; return ADORYM_EDEVICE; }
-  if (hipMemset(c->d_err, 0, 256) != hipSuccess) { hipFree(c->d_err); delete c; return ADORYM_EDEVICE; }
+  if (hipMemset(c->d_err, 0, 256) != hipSuccess) { (void)hipFree(c->d_err); delete c; return ADORYM_EDEVICE; }
   *out = c;
   return ADORYM_OK;
 }
 
 adorym_status adorym_destroy(adorym_ctx* ctx) {
   if (!ctx) return ADORYM_EINVAL;
-  hipFree(ctx->d_err);
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  (void)hipFree(ctx->d_err);
   delete ctx;
   return ADORYM_OK;
 }
@@ -702,5 +713,35 @@ adorym_status adorym_sync_error(adorym_ctx* ctx) {
 }
 
 const char* adorym_last_error_message(adorym_ctx* ctx) { return ctx ? ctx->msg : "no context"; }
+
+adorym_status adorym_profile_start(adorym_ctx* ctx, int32_t max_launches) {
+  if (!ctx || max_launches < 1) return ADORYM_EINVAL;
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  ctx->ev.assign(2 * (size_t)max_launches, nullptr);
+  for (auto& e : ctx->ev)
+    if (hipEventCreate(&e) != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, "hipEventCreate failed");
+  ctx->ev_used = 0;
+  ctx->prof = true;
+  return ADORYM_OK;
+}
+
+adorym_status adorym_profile_stop(adorym_ctx* ctx, double* total_ms, int32_t* launches) {
+  if (!ctx || !total_ms || !launches) return ADORYM_EINVAL;
+  ctx->prof = false;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, "stream sync failed");
+  double tot = 0.0;
+  for (int i = 0; i + 1 < ctx->ev_used; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]) != hipSuccess)
+      return set_err(ctx, ADORYM_EDEVICE, "hipEventElapsedTime failed");
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = ctx->ev_used / 2;
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  ctx->ev.clear();
+  ctx->ev_used = 0;
+  return ADORYM_OK;
+}
 
 }  // extern "C"
