@@ -46,6 +46,31 @@ def algorithmic_flops_per_position(n, s):
     return 6 * s * 5 * n * n * math.log2(n * n) + 60 * n * n * s
 
 
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2012_12686_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counters, if they were
+    taken on the kernel sources as they are now; else None."""
+    path = os.path.join(ROOT, "profiles", "multislice_n128_s64_b50_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("csrc_sha256") != kernel_source_hash():
+        return None
+    return rec["read_bytes"] + rec["write_bytes"]
+
+
 def cpu_baseline(sc, mb_idx, i_meas_np):
     """Time the FP64 oracle (fwd + loss + adjoint) on one minibatch."""
     from oracle import multislice as om
@@ -172,7 +197,7 @@ def main():
         "p50_iter_ms": p50,
         "p99_iter_ms": p99,
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "multislice_kernel<N=128, delta/beta, Poisson, loss+adjoint>",
                      "kernel_avg_ms": kern_avg_s * 1e3, "kernel_launches": kern_n,
                      "algorithmic_bytes_per_launch": bytes_launch,
