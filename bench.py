@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--split", type=int, default=0,
+                    help="workgroups per position (0 = the library's automatic choice)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters)")
     args = ap.parse_args()
@@ -122,6 +124,8 @@ def main():
     n_mb = len(sc.positions) // mb
     ctx = Context(dev)
     geom = Geometry.from_scan(sc)
+    if args.split:
+        ctx.set_split(n, args.split)
 
     to_t = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device=dev)
     true_a, true_b = to_t(sc.obj_a, torch.float32), to_t(sc.obj_b, torch.float32)

@@ -101,8 +101,9 @@ adorym_status adorym_set_stream(adorym_ctx* ctx, void* stream);
 int adorym_supports_n(int32_t n);
 
 /* Bytes of device workspace adorym_forward / adorym_loss_grad need for a
- * batch of `batch` positions (probe spectrum, per-position loss and probe
- * partials, slice checkpoints every ckpt_every slices).  0 on bad input. */
+ * batch of `batch` positions (probe spectrum, per-position loss, shift and
+ * probe partials, slice checkpoints every ckpt_every slices, and the
+ * exchange buffers of split workgroups).  0 on bad input. */
 size_t adorym_workspace_size(const adorym_geom* g, int32_t batch);
 
 /* Forward model (Alg. 1 without refinement of anything): predicted
@@ -133,6 +134,15 @@ adorym_status adorym_sync_error(adorym_ctx* ctx);
 
 /* Human-readable description of the last error on this context. */
 const char* adorym_last_error_message(adorym_ctx* ctx);
+
+/* Number of workgroups that share one position's wavefield for probe size
+ * n: k = 1 keeps the field in one workgroup (transposes through LDS);
+ * k > 1 splits its lines over k workgroups that exchange through L2.
+ * k = 0 restores the automatic choice (enough workgroups to cover the
+ * CUs).  Supported: n = 64 with k in {1, 2, 4}; n = 128 with k in
+ * {1, 2, 4, 8}; else ADORYM_EUNSUPPORTED.  Results do not depend on k
+ * beyond float rounding of the gradient atomics. */
+adorym_status adorym_set_split(adorym_ctx* ctx, int32_t n, int32_t k);
 
 /* Kernel timing for benchmarks.  adorym_profile_start creates up to
  * max_launches pairs of HIP events (it allocates: call it outside a timed

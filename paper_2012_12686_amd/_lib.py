@@ -47,6 +47,7 @@ SIGNATURES = {
                                         _P, _P, _P, _P, _P, _P]),
     "adorym_sync_error": (ctypes.c_int, [_P]),
     "adorym_last_error_message": (ctypes.c_char_p, [_P]),
+    "adorym_set_split": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "adorym_profile_start": (ctypes.c_int, [_P, ctypes.c_int32]),
     "adorym_profile_stop": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
 }

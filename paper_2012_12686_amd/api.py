@@ -89,6 +89,10 @@ class Context:
         """Synchronise and raise on a deferred device error (e.g. a chunk out of range)."""
         check(load().adorym_sync_error(self._ctx), self._ctx)
 
+    def set_split(self, n: int, k: int):
+        """Workgroups per position for probe size n (0 = automatic)."""
+        check(load().adorym_set_split(self._ctx, n, k), self._ctx)
+
     def profile_start(self, max_launches: int = 4096):
         """Time the main multislice kernel of each later call with HIP events."""
         check(load().adorym_profile_start(self._ctx, max_launches), self._ctx)

@@ -1,0 +1,6 @@
+// Kernel instantiations: N=64 K=1, N=64 K=2, N=64 K=4.
+#include "multislice_impl.hpp"
+
+template ADORYM_RUN_SIGNATURE(64, 4, 1);
+template ADORYM_RUN_SIGNATURE(64, 4, 2);
+template ADORYM_RUN_SIGNATURE(64, 4, 4);

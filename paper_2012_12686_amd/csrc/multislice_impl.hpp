@@ -1,0 +1,695 @@
+// multislice_impl.hpp -- fused multislice forward / loss / adjoint kernels.
+// Included by the instantiation units (one per probe size and split) and
+// by the C ABI unit multislice.hip.
+//
+// One workgroup per scan position does everything for that position:
+//   probe placement by Fourier shift (Eq. fourier_shift),
+//   S slice modulations (Eq. ri_modulation / complex_modulation) with S - 1
+//   paraxial Fresnel propagations (Eqs. fresnel_prop, paraxial_kernel),
+//   the Fraunhofer far field (Eq. fraunhofer) and |Psi|^2,
+//   the loss (Eq. lsq_loss or poisson_loss) and its residual,
+//   and the reverse sweep giving dL/d(object), dL/d(probe), dL/d(shift).
+// Steps follow Alg. 1 (TakeObjectChunk, FourierShift, MultislicePropagate,
+// FarFieldPropagate).  The wave stays in registers for the whole sweep; the
+// object is read straight from HBM slice by slice and its gradient is
+// scattered with float atomics.  The reverse sweep rebuilds the wave
+// entering each slice by stepping the forward recursion backwards
+// (psi_{j-1} = t_{j-1}^{-1} P^H psi_j), and re-anchors it on checkpoints of
+// the forward sweep stored every ckpt_every slices.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "adorym.h"
+#include "fastmath.hpp"
+#include "tile.hpp"
+
+using namespace adorym;
+
+#ifndef ADORYM_L128
+#define ADORYM_L128 8
+#endif
+
+struct adorym_ctx {
+  int device;
+  hipStream_t stream;
+  int* d_err;          // deferred device error flags (bit 0: chunk out of range)
+  char msg[512];
+  // optional timing of the main multislice kernel (adorym_profile_*)
+  std::vector<hipEvent_t> ev;   // start/stop pairs
+  int ev_used = 0;
+  bool prof = false;
+  // workgroups per position (0 = automatic) for N = 64 and N = 128
+  int split64 = 0, split128 = 0;
+};
+
+namespace adorym_ms {
+
+struct MsParams {
+  const float* a;          // delta or Re O, [S][Ly][Lx]
+  const float* b;          // beta or Im O
+  const float2* q;         // probe spectrum DFT(p)/N^2, natural [ky][kx]
+  const int32_t* corner;   // [B][2]
+  const float* shift;      // [B][2]
+  const float* i_meas;     // [B][N][N]
+  float* intensity;        // [B][N][N] or null
+  float* g_a;              // [S][Ly][Lx] or null
+  float* g_b;
+  float2* ckpt;            // [B][nslots][K][R*THREADS]
+  float2* gacc;            // [B][N][N] natural, or null (probe-gradient partials)
+  double* loss_part;       // [B][K]
+  double* gs_part;         // [B][K][2] shift-gradient partials
+  float2* xbuf;            // [B][2][2][N][N] exchange buffers (K > 1)
+  int* counters;           // [B] group barrier counters (K > 1)
+  int* err;
+  int B, S, Ly, Lx, ckpt_every, nslots;
+  float kdz;               // k * dz
+  double chirp;            // lambda dz / dx^2
+  double eps;
+  double inv_n;            // 1 / (B N^2)
+};
+
+constexpr int kErrChunkRange = 1;   // error bit: a chunk left the object
+
+__device__ __forceinline__ bool is_ckpt(int j, int S, int C) { return (j % C == 0) || (j == S - 1); }
+__device__ __forceinline__ int ckpt_slot(int j, int S, int C) {
+  return (j % C == 0) ? j / C : (S - 1) / C + 1;
+}
+
+// fftfreq(N) in cycles/pixel for natural index k
+template <int N>
+__device__ __forceinline__ double freq(int k) {
+  return double(k < (N + 1) / 2 ? k : k - N) / double(N);
+}
+
+// Transmission t and its inverse for one voxel (REPR = ADORYM_OBJ_*).
+template <int REPR>
+__device__ __forceinline__ void transmission(float kdz, float a, float b, float2& t, float2& tinv) {
+  if constexpr (REPR == ADORYM_OBJ_DELTA_BETA) {
+    float s, c;
+    sincos_f32(kdz * a, s, c);
+    const float v = kdz * b;
+    const float att = exp_f32(-v), gain = exp_f32(v);
+    t = make_float2(c * att, s * att);
+    tinv = make_float2(c * gain, -s * gain);
+  } else {
+    t = make_float2(a, b);
+    const float inv = 1.0f / (a * a + b * b);
+    tinv = make_float2(a * inv, -b * inv);
+  }
+}
+
+// Shared memory of the multislice kernel.
+template <class C>
+struct MsShared {
+  float2 buf[C::LDS_FIELD];   // transpose buffer (K == 1)
+  Tables<C> tb;
+  float2 ey[C::N];            // exp(-2 pi i s_y f(k)), natural k
+  float2 ex[C::N];
+  double red[2 * C::WAVES];
+};
+
+// Per-workgroup state: which field (position) and which part of it.
+template <class C>
+struct Work {
+  Lane<C> ln;
+  int b, part, cy, cx;
+  Exchange x;
+  __device__ __forceinline__ Work(int t, int b_, int part_) : ln(t, part_), b(b_), part(part_) {}
+};
+
+// Transpose one field / two fields (ROW <-> COL).
+template <class C>
+__device__ __forceinline__ void xfer(float2 (&v)[C::R], MsShared<C>& sh, Work<C>& wk, bool src_spec, bool dst_spec) {
+  if constexpr (C::K == 1) transpose<C>(v, sh.buf, wk.ln, src_spec, dst_spec);
+  else transpose_global<C, 1>(v, v, wk.x, wk.ln, src_spec, dst_spec);
+}
+template <class C>
+__device__ __forceinline__ void xfer2(float2 (&v0)[C::R], float2 (&v1)[C::R], MsShared<C>& sh, Work<C>& wk,
+                                      bool src_spec, bool dst_spec) {
+  if constexpr (C::K == 1) {
+    transpose<C>(v0, sh.buf, wk.ln, src_spec, dst_spec);
+    transpose<C>(v1, sh.buf, wk.ln, src_spec, dst_spec);
+  } else {
+    transpose_global<C, 2>(v0, v1, wk.x, wk.ln, src_spec, dst_spec);
+  }
+}
+
+template <class C>
+__device__ __forceinline__ void setup_tables(MsShared<C>& sh, const Lane<C>& ln, double chirp, float sy, float sx) {
+  build_twiddles<C>(sh.tb, ln.tid);
+  build_fresnel<C>(sh.tb, ln.tid, chirp);
+  for (int k = ln.tid; k < C::N; k += C::THREADS) {
+    double f = freq<C::N>(k), s, c;
+    sincospi(-2.0 * double(sy) * f, &s, &c);
+    sh.ey[k] = make_float2(float(c), float(s));
+    sincospi(-2.0 * double(sx) * f, &s, &c);
+    sh.ex[k] = make_float2(float(c), float(s));
+  }
+  __syncthreads();
+}
+
+// Per-thread byte offsets of the chunk elements inside one object slice.
+//   ROW layout: element m at row_off + 4 L m         (immediate offsets)
+//   COL layout: element m at col_off + m * col_step  (uniform step in an SGPR)
+struct ChunkOffsets {
+  uint32_t row_off, col_off, col_step, slice_bytes;
+};
+
+template <class C>
+__device__ __forceinline__ ChunkOffsets chunk_offsets(const Lane<C>& ln, int cy, int cx, int Ly, int Lx) {
+  ChunkOffsets o;
+  o.row_off = (uint32_t)(((cy + ln.line) * Lx + cx + ln.q) * 4);
+  o.col_off = (uint32_t)(((cy + ln.q) * Lx + cx + ln.line) * 4);
+  o.col_step = (uint32_t)(4 * C::L * Lx);
+  o.slice_bytes = (uint32_t)((size_t)Ly * Lx * 4);
+  return o;
+}
+
+template <class C, bool ROW>
+__device__ __forceinline__ float chunk_load(rsrc_t r, const ChunkOffsets& o, int m) {
+  return ROW ? bload(r, o.row_off + 4 * C::L * m, 0) : bload(r, o.col_off, (uint32_t)m * o.col_step);
+}
+template <class C, bool ROW>
+__device__ __forceinline__ void chunk_atomic_add(rsrc_t r, const ChunkOffsets& o, int m, float v) {
+  if (ROW) batomic_add(r, v, o.row_off + 4 * C::L * m, 0);
+  else batomic_add(r, v, o.col_off, (uint32_t)m * o.col_step);
+}
+
+__device__ __forceinline__ rsrc_t slice_rsrc(const float* base, int j, const ChunkOffsets& o) {
+  return make_rsrc(base + (size_t)j * (o.slice_bytes / 4), o.slice_bytes);
+}
+
+// Modulate the wave by slice j (Eq. ri_modulation or complex_modulation).
+template <class C, int REPR, bool ROW>
+__device__ __forceinline__ void modulate(float2 (&v)[C::R], const MsParams& P, const ChunkOffsets& o, int j) {
+  const rsrc_t ra = slice_rsrc(P.a, j, o), rb = slice_rsrc(P.b, j, o);
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    float2 t, tinv;
+    transmission<REPR>(P.kdz, chunk_load<C, ROW>(ra, o, m), chunk_load<C, ROW>(rb, o, m), t, tinv);
+    v[m] = cmul(v[m], t);
+  }
+}
+
+// Thread-native storage of this workgroup's part of a field.
+template <class C>
+__device__ __forceinline__ void field_store(const float2 (&v)[C::R], float2* base, const Lane<C>& ln) {
+  const rsrc_t r = make_rsrc(base, C::R * C::THREADS * 8);
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) bstore2(r, v[m], ln.tid * 8, m * C::THREADS * 8);
+}
+template <class C>
+__device__ __forceinline__ void field_load(float2 (&v)[C::R], const float2* base, const Lane<C>& ln) {
+  const rsrc_t r = make_rsrc(base, C::R * C::THREADS * 8);
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) v[m] = bload2(r, ln.tid * 8, m * C::THREADS * 8);
+}
+
+template <class C>
+__device__ __forceinline__ float2* ckpt_ptr(const MsParams& P, const Work<C>& wk, int slot) {
+  return P.ckpt + (((size_t)wk.b * P.nslots + slot) * C::K + wk.part) * (C::R * C::THREADS);
+}
+
+// psi_0 = IDFT(Q e_b): Q loaded in COL layout (line kx, pos ky spectral).
+template <class C>
+__device__ __forceinline__ void place_probe(float2 (&v)[C::R], const MsParams& P, MsShared<C>& sh, Work<C>& wk) {
+  const Lane<C>& ln = wk.ln;
+  const float2 exv = sh.ex[ln.line];
+  const rsrc_t rq = make_rsrc(P.q, C::N * C::N * 8);
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    const int ky = ln.pos_spec(m);
+    v[m] = cmul(bload2(rq, (uint32_t)(ky * C::N + ln.line) * 8, 0), cmul(sh.ey[ky], exv));
+  }
+  ifft_line<C, +1>(v, sh.tb, ln);                 // along y -> natural
+  xfer<C>(v, sh, wk, false, true);                // -> ROW, x spectral
+  ifft_line<C, +1>(v, sh.tb, ln);                 // along x -> natural
+}
+
+// One forward slice step: (store) modulate, and propagate to slice j + 1.
+template <class C, int REPR, bool ROW, bool CKPT>
+__device__ __forceinline__ void forward_slice(float2 (&v)[C::R], const MsParams& P, MsShared<C>& sh, Work<C>& wk,
+                                              const ChunkOffsets& o, int j) {
+  if (CKPT && is_ckpt(j, P.S, P.ckpt_every)) field_store<C>(v, ckpt_ptr<C>(P, wk, ckpt_slot(j, P.S, P.ckpt_every)), wk.ln);
+  modulate<C, REPR, ROW>(v, P, o, j);
+  if (j < P.S - 1) {
+    propagate_line<C, false>(v, sh.tb, wk.ln);
+    xfer<C>(v, sh, wk, false, false);
+    propagate_line<C, false>(v, sh.tb, wk.ln);
+  }
+}
+
+// Reverse slice step j (layout ROW/COL): gradient of slice j, then the two
+// fields are taken back to slice j-1 by the adjoint propagator.
+//   in : psi = phi_j (the wave leaving slice j, rebuilt by the backward
+//        recursion) unless slice j is anchored on a checkpoint;
+//        lam = dL/dphi_j
+//   out: psi = phi_{j-1} = P^H psi_j, lam = dL/dphi_{j-1} = P^H conj(t_j) lam
+template <class C, int REPR, bool ROW>
+__device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam)[C::R], const MsParams& P,
+                                               MsShared<C>& sh, Work<C>& wk, const ChunkOffsets& o, int j) {
+  const Lane<C>& ln = wk.ln;
+  const bool anchored = is_ckpt(j, P.S, P.ckpt_every);
+  if (anchored) field_load<C>(psi, ckpt_ptr<C>(P, wk, ckpt_slot(j, P.S, P.ckpt_every)), ln);  // psi_j exactly
+  const rsrc_t ra = slice_rsrc(P.a, j, o), rb = slice_rsrc(P.b, j, o);
+  const bool grads = P.g_a != nullptr;
+  const rsrc_t rga = grads ? slice_rsrc(P.g_a, j, o) : ra;
+  const rsrc_t rgb = grads ? slice_rsrc(P.g_b, j, o) : rb;
+  const float kdz = P.kdz;
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    float2 t, tinv;
+    transmission<REPR>(kdz, chunk_load<C, ROW>(ra, o, m), chunk_load<C, ROW>(rb, o, m), t, tinv);
+    const float2 in_wave = anchored ? psi[m] : cmul(psi[m], tinv);   // psi_j
+    const float2 out_wave = anchored ? cmul(psi[m], t) : psi[m];     // phi_j
+    const float2 l = lam[m];
+    if (grads) {
+      if constexpr (REPR == ADORYM_OBJ_DELTA_BETA) {
+        const float2 z = cmulc(l, out_wave);          // lam conj(phi)
+        chunk_atomic_add<C, ROW>(rga, o, m, kdz * z.y);
+        chunk_atomic_add<C, ROW>(rgb, o, m, -kdz * z.x);
+      } else {
+        const float2 z = cmulc(l, in_wave);           // lam conj(psi)
+        chunk_atomic_add<C, ROW>(rga, o, m, z.x);
+        chunk_atomic_add<C, ROW>(rgb, o, m, z.y);
+      }
+    }
+    lam[m] = cmulc(l, t);                              // conj(t) lam = dL/dpsi_j
+    psi[m] = in_wave;
+  }
+  if (j > 0) {
+    const bool need_psi = !is_ckpt(j - 1, P.S, P.ckpt_every);
+    if (need_psi) {
+      propagate_line<C, true>(psi, sh.tb, ln);
+      propagate_line<C, true>(lam, sh.tb, ln);
+      xfer2<C>(psi, lam, sh, wk, false, false);
+      propagate_line<C, true>(psi, sh.tb, ln);
+      propagate_line<C, true>(lam, sh.tb, ln);
+    } else {
+      propagate_line<C, true>(lam, sh.tb, ln);
+      xfer<C>(lam, sh, wk, false, false);
+      propagate_line<C, true>(lam, sh.tb, ln);
+    }
+  }
+}
+
+// Map the workgroup index to (position, part).  The K parts of a position
+// sit in consecutive slots of one XCD (workgroups are dealt to the 8 XCDs
+// round-robin), so their exchange traffic stays in that XCD's L2.
+template <class C>
+__device__ __forceinline__ void group_of_block(int& b, int& part) {
+  const int i = blockIdx.x;
+  const int xcd = i & 7, slot = i >> 3;
+  b = (slot / C::K) * 8 + xcd;
+  part = slot % C::K;
+}
+
+template <class C, int REPR, int LOSSK, bool LOSS>
+__global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
+  __shared__ MsShared<C> sh;
+  int b, part;
+  group_of_block<C>(b, part);
+  if (b >= P.B) return;                       // padding of the XCD-aware grid
+  Work<C> wk(threadIdx.x, b, part);
+  const Lane<C>& ln = wk.ln;
+  constexpr int N = C::N;
+  constexpr int NN = N * N;
+  wk.cy = P.corner[2 * b];
+  wk.cx = P.corner[2 * b + 1];
+  const float sy = P.shift[2 * b], sx = P.shift[2 * b + 1];
+  wk.x.buf = P.xbuf + (size_t)b * 4 * NN;
+  wk.x.counter = P.counters + b;
+  wk.x.err = P.err;
+  wk.x.phase = 0;
+
+  // TakeObjectChunk: the chunk must lie inside the object.
+  if (wk.cy < 0 || wk.cx < 0 || wk.cy + N > P.Ly || wk.cx + N > P.Lx) {
+    if (threadIdx.x == 0 && part == 0) atomicOr(P.err, kErrChunkRange);
+    if (LOSS) {
+      if (threadIdx.x == 0) {
+        P.loss_part[b * C::K + part] = 0.0;
+        P.gs_part[2 * (b * C::K + part)] = 0.0;
+        P.gs_part[2 * (b * C::K + part) + 1] = 0.0;
+      }
+      if (P.gacc)
+        for (int i = part * C::THREADS + threadIdx.x; i < NN; i += C::K * C::THREADS)
+          P.gacc[(size_t)b * NN + i] = make_float2(0.f, 0.f);
+    }
+    if (P.intensity)
+      for (int i = part * C::THREADS + threadIdx.x; i < NN; i += C::K * C::THREADS)
+        P.intensity[(size_t)b * NN + i] = 0.f;
+    return;
+  }
+
+  setup_tables<C>(sh, ln, P.chirp, sy, sx);
+  const ChunkOffsets o = chunk_offsets<C>(ln, wk.cy, wk.cx, P.Ly, P.Lx);
+
+  float2 v[C::R];
+  place_probe<C>(v, P, sh, wk);
+
+  // MultislicePropagate: even slices in ROW layout, odd slices in COL layout.
+  for (int j = 0; j < P.S; j += 2) {
+    forward_slice<C, REPR, true, LOSS>(v, P, sh, wk, o, j);
+    if (j + 1 < P.S) forward_slice<C, REPR, false, LOSS>(v, P, sh, wk, o, j + 1);
+  }
+  const bool last_row = ((P.S - 1) & 1) == 0;
+
+  // FarFieldPropagate: inverse DFT along the current lines, transpose, along
+  // the other axis.  Result: spectral along the lines of the final layout.
+  fft_line<C, +1>(v, sh.tb, ln);
+  xfer<C>(v, sh, wk, true, false);
+  fft_line<C, +1>(v, sh.tb, ln);
+  const float inv_nf = 1.0f / float(N);
+
+  // Per-pixel loss terms in FP32; the sum over pixels is accumulated in FP64.
+  double lsum = 0.0;
+  const float eps = (float)P.eps;
+  const float inv_n = (float)P.inv_n;
+  const rsrc_t rim = make_rsrc(LOSS ? (const void*)(P.i_meas + (size_t)b * NN) : (const void*)P.q, NN * 4);
+  const rsrc_t rint = make_rsrc(P.intensity ? (const void*)(P.intensity + (size_t)b * NN) : (const void*)P.q, NN * 4);
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    int ky, kx;
+    if (last_row) { ky = ln.pos_spec(m); kx = ln.line; }    // final layout COL
+    else          { ky = ln.line; kx = ln.pos_spec(m); }    // final layout ROW
+    const uint32_t det = (uint32_t)(((ky + N / 2) % N) * N + (kx + N / 2) % N) * 4;
+    const float2 psi_det = cscale(v[m], inv_nf);
+    const float ip = psi_det.x * psi_det.x + psi_det.y * psi_det.y;
+    if (P.intensity) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, ip), rint, det, 0, 0);
+    if (LOSS) {
+      const float imv = bload(rim, det, 0);
+      float term, dldi;
+      if constexpr (LOSSK == ADORYM_LOSS_GAUSSIAN) {
+        const float sp = sqrtf(ip + eps), sm = sqrtf(imv + eps);
+        term = (sp - sm) * (sp - sm);
+        dldi = (1.0f - sm / sp) * inv_n;
+      } else {
+        term = ip - imv * logf(ip + eps);
+        dldi = (1.0f - imv / (ip + eps)) * inv_n;
+      }
+      lsum += (double)term;
+      // far-field residual 2 dL/dI Psi, scaled by 1/N for the adjoint DFT
+      v[m] = cscale(psi_det, 2.0f * dldi * inv_nf);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (!LOSS) return;
+
+  {
+    double tot = block_sum<C::THREADS>(lsum, sh.red);
+    if (threadIdx.x == 0) P.loss_part[b * C::K + part] = tot * P.inv_n;   // mean over the B N^2 pixels
+  }
+
+  // Adjoint of the far field: DFT back along the two axes.
+  ifft_line<C, -1>(v, sh.tb, ln);
+  xfer<C>(v, sh, wk, false, true);
+  ifft_line<C, -1>(v, sh.tb, ln);
+  // v = lambda_{S-1} in the layout of slice S-1
+
+  float2 psi[C::R];
+  int j = P.S - 1;
+  if (!last_row) {
+    backward_slice<C, REPR, false>(psi, v, P, sh, wk, o, j);
+    --j;
+  }
+  // now slice j is even (ROW); pairs (j ROW, j-1 COL) down to slice 0
+  for (; j >= 1; j -= 2) {
+    backward_slice<C, REPR, true>(psi, v, P, sh, wk, o, j);
+    backward_slice<C, REPR, false>(psi, v, P, sh, wk, o, j - 1);
+  }
+  if (j == 0) backward_slice<C, REPR, true>(psi, v, P, sh, wk, o, 0);
+  // v = dL/d(shifted probe) in ROW layout, natural order.
+
+  // FourierShift adjoint: G = DFT(g_pb) in COL layout (kx line, ky spectral).
+  fft_line<C, -1>(v, sh.tb, ln);
+  xfer<C>(v, sh, wk, true, false);
+  fft_line<C, -1>(v, sh.tb, ln);
+  const float2 exv = sh.ex[ln.line];
+  const double fx = freq<N>(ln.line);
+  double gsy = 0.0, gsx = 0.0;
+  const rsrc_t rq = make_rsrc(P.q, NN * 8);
+  const rsrc_t rg = make_rsrc(P.gacc ? P.gacc + (size_t)b * NN : P.q, NN * 8);
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    const int ky = ln.pos_spec(m);
+    const uint32_t off = (uint32_t)(ky * N + ln.line) * 8;
+    const float2 e = cmul(sh.ey[ky], exv);
+    const float2 g = v[m];
+    if (P.gacc) bstore2(rg, cmulc(g, e), off, 0);
+    const float2 qv = bload2(rq, off, 0);
+    const float2 z = cmul(cmulc(qv, g), e);     // conj(G) Q e
+    gsy += freq<N>(ky) * double(z.y);
+    gsx += fx * double(z.y);
+  }
+  double ty = block_sum<C::THREADS>(gsy, sh.red);
+  double tx = block_sum<C::THREADS>(gsx, sh.red + C::WAVES);
+  if (threadIdx.x == 0) {
+    const double two_pi = 6.283185307179586476925286766559;
+    P.gs_part[2 * (b * C::K + part)] = two_pi * ty;
+    P.gs_part[2 * (b * C::K + part) + 1] = two_pi * tx;
+  }
+}
+
+// Probe spectrum Q = DFT(p) / N^2 (natural [ky][kx]); also clears the
+// group barrier counters of the main kernel that follows on the stream.
+template <class C>
+__global__ void __launch_bounds__(C::THREADS) probe_spectrum_kernel(const float2* __restrict__ probe,
+                                                                    float2* __restrict__ q, int* counters,
+                                                                    int n_counters) {
+  __shared__ float2 buf[C::LDS_FIELD];
+  __shared__ Tables<C> tb;
+  for (int i = threadIdx.x; i < n_counters; i += C::THREADS) counters[i] = 0;
+  const Lane<C> ln(threadIdx.x);
+  build_twiddles<C>(tb, ln.tid);
+  __syncthreads();
+  constexpr int N = C::N;
+  float2 v[C::R];
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) v[m] = probe[ln.line * N + ln.pos_nat(m)];
+  fft_line<C, -1>(v, tb, ln);
+  transpose<C>(v, buf, ln, true, false);
+  fft_line<C, -1>(v, tb, ln);
+  const float s = 1.0f / float(N * N);
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) q[ln.pos_spec(m) * N + ln.line] = cscale(v[m], s);
+}
+
+// Sums of the per-position partials: probe-gradient spectrum (natural
+// order, fixed order over positions), loss (block 0), shift gradients.
+static __global__ void reduce_partials_kernel(const float2* __restrict__ gacc, int nb, int nn, float2* __restrict__ gsum,
+                                       const double* __restrict__ loss_part, const double* __restrict__ gs_part,
+                                       int k, double* __restrict__ loss, float* __restrict__ g_shift,
+                                       int accumulate) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gacc && i < nn) {
+    float sx = 0.f, sy = 0.f;
+    for (int bb = 0; bb < nb; ++bb) {
+      const float2 t = gacc[(size_t)bb * nn + i];
+      sx += t.x;
+      sy += t.y;
+    }
+    gsum[i] = make_float2(sx, sy);
+  }
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0 && loss) {
+      double s = 0.0;
+      for (int t = 0; t < nb * k; ++t) s += loss_part[t];
+      *loss = s;
+    }
+    if (g_shift) {
+      for (int bb = threadIdx.x; bb < nb; bb += blockDim.x) {
+        double sy = 0.0, sx = 0.0;
+        for (int p = 0; p < k; ++p) {
+          sy += gs_part[2 * (bb * k + p)];
+          sx += gs_part[2 * (bb * k + p) + 1];
+        }
+        if (accumulate) { g_shift[2 * bb] += (float)sy; g_shift[2 * bb + 1] += (float)sx; }
+        else { g_shift[2 * bb] = (float)sy; g_shift[2 * bb + 1] = (float)sx; }
+      }
+    }
+  }
+}
+
+// Probe gradient g_p = IDFT(sum_b G_b conj(e_b)) / N^2 from the natural-order sum.
+template <class C>
+__global__ void __launch_bounds__(C::THREADS) probe_grad_kernel(const float2* __restrict__ gsum,
+                                                                float2* __restrict__ g_probe, int accumulate) {
+  __shared__ float2 buf[C::LDS_FIELD];
+  __shared__ Tables<C> tb;
+  const Lane<C> ln(threadIdx.x);
+  constexpr int N = C::N, NN = N * N;
+  build_twiddles<C>(tb, ln.tid);
+  __syncthreads();
+  float2 v[C::R];
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) v[m] = gsum[ln.pos_spec(m) * N + ln.line];
+  ifft_line<C, +1>(v, tb, ln);
+  transpose<C>(v, buf, ln, false, true);
+  ifft_line<C, +1>(v, tb, ln);
+  const float s = 1.0f / float(NN);
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    const int idx = ln.line * N + ln.pos_nat(m);
+    float2 g = cscale(v[m], s);
+    if (accumulate) g = cadd(g, g_probe[idx]);
+    g_probe[idx] = g;
+  }
+}
+
+static __global__ void fill_kernel(float* __restrict__ p, size_t n, float val) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = val;
+}
+
+// ----------------------------------------------------------------------------
+// Host side
+// ----------------------------------------------------------------------------
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+constexpr int kMaxSplit = 8;   // largest K any kernel uses
+
+struct WsLayout {
+  size_t q, gsum, loss_part, gs_part, counters, gacc, ckpt, xbuf, total;
+  int nslots;
+};
+
+inline WsLayout ws_layout(const adorym_geom* g, int batch) {
+  WsLayout w{};
+  const size_t nn = (size_t)g->n * g->n;
+  const int S = g->n_slices, C = g->ckpt_every;
+  w.nslots = (S - 1) / C + 1 + (((S - 1) % C) != 0 ? 1 : 0);
+  size_t off = 0;
+  w.q = off; off += align256(nn * sizeof(float2));
+  w.gsum = off; off += align256(nn * sizeof(float2));
+  w.loss_part = off; off += align256((size_t)batch * kMaxSplit * sizeof(double));
+  w.gs_part = off; off += align256((size_t)batch * kMaxSplit * 2 * sizeof(double));
+  w.counters = off; off += align256((size_t)batch * sizeof(int));
+  w.gacc = off; off += align256((size_t)batch * nn * sizeof(float2));
+  w.ckpt = off; off += align256((size_t)batch * w.nslots * nn * sizeof(float2));
+  w.xbuf = off; off += align256((size_t)batch * 4 * nn * sizeof(float2));
+  w.total = off;
+  return w;
+}
+
+inline adorym_status set_err(adorym_ctx* ctx, adorym_status st, const char* what) {
+  if (ctx) snprintf(ctx->msg, sizeof(ctx->msg), "%s", what);
+  return st;
+}
+
+inline adorym_status check_geom(adorym_ctx* ctx, const adorym_geom* g, int batch) {
+  if (!ctx) return ADORYM_EINVAL;
+  if (!g) return set_err(ctx, ADORYM_EINVAL, "geometry is NULL");
+  if (!adorym_supports_n(g->n)) return set_err(ctx, ADORYM_EUNSUPPORTED, "probe size N has no kernel");
+  if (g->n_slices < 1) return set_err(ctx, ADORYM_EINVAL, "n_slices must be >= 1");
+  if (g->obj_ny < g->n || g->obj_nx < g->n) return set_err(ctx, ADORYM_EINVAL, "object smaller than the probe");
+  if ((size_t)g->obj_ny * g->obj_nx * 4 > 0xFFFFFFF0ull)
+    return set_err(ctx, ADORYM_EUNSUPPORTED, "one object slice exceeds 4 GiB");
+  if (g->ckpt_every < 1) return set_err(ctx, ADORYM_EINVAL, "ckpt_every must be >= 1");
+  if (!(g->wavelength_m > 0) || !(g->pixel_m > 0) || !(g->slice_dz_m >= 0))
+    return set_err(ctx, ADORYM_EINVAL, "wavelength, pixel and slice spacing must be positive");
+  if (g->loss != ADORYM_LOSS_GAUSSIAN && g->loss != ADORYM_LOSS_POISSON)
+    return set_err(ctx, ADORYM_EINVAL, "unknown loss");
+  if (g->obj_repr != ADORYM_OBJ_DELTA_BETA && g->obj_repr != ADORYM_OBJ_REAL_IMAG)
+    return set_err(ctx, ADORYM_EINVAL, "unknown object representation");
+  if (!(g->eps >= 0)) return set_err(ctx, ADORYM_EINVAL, "eps must be >= 0");
+  if (batch < 1) return set_err(ctx, ADORYM_EINVAL, "batch must be >= 1");
+  return ADORYM_OK;
+}
+
+inline void fill(hipStream_t st, float* p, size_t n, float v) {
+  if (!p || n == 0) return;
+  int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, st, p, n, v);
+}
+
+template <class C, bool LOSS>
+void launch_ms(const MsParams& P, int repr, int lossk, hipStream_t st) {
+  // XCD-aware grid: ceil(B/8) groups per XCD, K slots per group
+  const dim3 grid(((P.B + 7) / 8) * 8 * C::K), block(C::THREADS);
+  if (repr == ADORYM_OBJ_DELTA_BETA) {
+    if (lossk == ADORYM_LOSS_GAUSSIAN)
+      hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, ADORYM_LOSS_GAUSSIAN, LOSS>), grid, block, 0, st, P);
+    else
+      hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, ADORYM_LOSS_POISSON, LOSS>), grid, block, 0, st, P);
+  } else {
+    if (lossk == ADORYM_LOSS_GAUSSIAN)
+      hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, ADORYM_LOSS_GAUSSIAN, LOSS>), grid, block, 0, st, P);
+    else
+      hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, ADORYM_LOSS_POISSON, LOSS>), grid, block, 0, st, P);
+  }
+}
+
+// One probe size N with lanes-per-line L; C1 is the single-workgroup tile.
+template <int N, int L, int K>
+adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b, const float* probe,
+                  const int32_t* corner, const float* shift, int batch, const float* i_meas, void* ws,
+                  double* loss, float* g_a, float* g_b, float* g_probe, float* g_shift, float* intensity,
+                  bool with_loss) {
+  using C = TileCfg<N, L, K>;
+  using C1 = TileCfg<N, L, 1>;
+  const WsLayout w = ws_layout(g, batch);
+  char* base = static_cast<char*>(ws);
+  MsParams P{};
+  P.a = a; P.b = b;
+  P.q = reinterpret_cast<const float2*>(base + w.q);
+  P.corner = corner; P.shift = shift; P.i_meas = i_meas; P.intensity = intensity;
+  P.g_a = g_a; P.g_b = g_b;
+  P.ckpt = reinterpret_cast<float2*>(base + w.ckpt);
+  P.gacc = g_probe ? reinterpret_cast<float2*>(base + w.gacc) : nullptr;
+  P.loss_part = reinterpret_cast<double*>(base + w.loss_part);
+  P.gs_part = reinterpret_cast<double*>(base + w.gs_part);
+  P.xbuf = reinterpret_cast<float2*>(base + w.xbuf);
+  P.counters = reinterpret_cast<int*>(base + w.counters);
+  P.err = ctx->d_err;
+  P.B = batch; P.S = g->n_slices; P.Ly = g->obj_ny; P.Lx = g->obj_nx;
+  P.ckpt_every = g->ckpt_every; P.nslots = w.nslots;
+  P.kdz = (float)(2.0 * M_PI / g->wavelength_m * g->slice_dz_m);
+  P.chirp = g->wavelength_m * g->slice_dz_m / (g->pixel_m * g->pixel_m);
+  P.eps = g->eps;
+  P.inv_n = 1.0 / ((double)batch * g->n * g->n);
+  const int accumulate = (g->flags & ADORYM_ACCUMULATE_GRADS) ? 1 : 0;
+
+  hipStream_t st = ctx->stream;
+  const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
+  hipLaunchKernelGGL((probe_spectrum_kernel<C1>), dim3(1), dim3(C1::THREADS), 0, st,
+                     reinterpret_cast<const float2*>(probe), const_cast<float2*>(P.q), P.counters, batch);
+  if (with_loss) {
+    const size_t nobj = (size_t)g->n_slices * g->obj_ny * g->obj_nx;
+    if (!accumulate) {
+      if (g_a) fill(st, g_a, nobj, 0.f);
+      if (g_b) fill(st, g_b, nobj, 0.f);
+    }
+    if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
+    launch_ms<C, true>(P, g->obj_repr, g->loss, st);
+    if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
+    const int nn = N * N;
+    float2* gsum = reinterpret_cast<float2*>(base + w.gsum);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((nn + 255) / 256), dim3(256), 0, st, P.gacc, batch, nn, gsum,
+                       P.loss_part, P.gs_part, C::K, loss, g_shift, accumulate);
+    if (g_probe)
+      hipLaunchKernelGGL((probe_grad_kernel<C1>), dim3(1), dim3(C1::THREADS), 0, st, gsum,
+                         reinterpret_cast<float2*>(g_probe), accumulate);
+  } else {
+    if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
+    launch_ms<C, false>(P, g->obj_repr, g->loss, st);
+    if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
+  return ADORYM_OK;
+}
+
+}  // namespace adorym_ms
+
+// Explicit instantiation helpers
+#define ADORYM_RUN_SIGNATURE(N_, L_, K_) \
+  adorym_status adorym_ms::run<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, const float*, const float*, \
+                                           const int32_t*, const float*, int, const float*, void*, double*, float*, \
+                                           float*, float*, float*, float*, bool)

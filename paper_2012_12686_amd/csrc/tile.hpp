@@ -235,25 +235,31 @@ __host__ __device__ constexpr int bitrev_n(int x, int bits) {
 // ----------------------------------------------------------------------------
 // Tile configuration
 // ----------------------------------------------------------------------------
-template <int N_, int L_>
+// N: field size; L: lanes per line; K: workgroups sharing one field.
+// With K == 1 the whole field is in one workgroup and transposes go
+// through LDS; with K > 1 workgroup `part` owns lines [part*N/K, ...) in
+// both layouts and transposes go through an L2-resident exchange buffer.
+template <int N_, int L_, int K_ = 1>
 struct TileCfg {
   static constexpr int N = N_;
   static constexpr int L = L_;
+  static constexpr int K = K_;
   static constexpr int R = N / L;
   static constexpr int RPW = 64 / L;            // lines per wave
-  static constexpr int WAVES = N / RPW;
+  static constexpr int LINES = N / K;           // lines per workgroup
+  static constexpr int WAVES = LINES / RPW;
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int LOGL = ilog2(L);
   static constexpr int PITCH = N + 8;           // LDS row pitch in float2 (bank spread)
-  static constexpr int LDS_FIELD = N * PITCH;   // float2 elements of the transpose buffer
-  static_assert(N % L == 0 && N % RPW == 0, "bad tile");
+  static constexpr int LDS_FIELD = K == 1 ? N * PITCH : 1;   // LDS transpose buffer (K == 1 only)
+  static_assert(N % L == 0 && LINES % RPW == 0 && WAVES >= 1, "bad tile");
 };
 
 // Per-thread coordinates.
 template <class C>
 struct Lane {
   int tid, w, g, l, q, k1, line;
-  __device__ __forceinline__ explicit Lane(int t) {
+  __device__ __forceinline__ explicit Lane(int t, int part = 0) {
     tid = t;
     w = t >> 6;
     int lane = t & 63;
@@ -261,7 +267,7 @@ struct Lane {
     l = lane % C::L;
     q = (C::L == 8 && l >= 4) ? 11 - l : l;
     k1 = bitrev_n(q, C::LOGL);
-    line = w * C::RPW + g;
+    line = part * C::LINES + w * C::RPW + g;
   }
   __device__ __forceinline__ int pos_nat(int m) const { return q + C::L * m; }
   __device__ __forceinline__ int pos_spec(int m) const { return C::R * k1 + m; }
@@ -435,18 +441,92 @@ __device__ f32x2 adorym_raw_load_v2f32(rsrc_t rsrc, int voffset, int soffset, in
 __device__ void adorym_raw_store_v2f32(f32x2 v, rsrc_t rsrc, int voffset, int soffset, int aux)
     __asm("llvm.amdgcn.raw.ptr.buffer.store.v2f32");
 
+// Cache-policy operand: 0 = default; kCoherent = sc0|sc1 (system scope:
+// stores write through every cache level, loads miss in every cache), used
+// for data that other workgroups read within the same kernel.
+constexpr int kCoherent = 1 | 16;
+
+template <int AUX = 0>
 __device__ __forceinline__ float2 bload2(rsrc_t r, uint32_t voff, uint32_t soff) {
-  const f32x2 t = adorym_raw_load_v2f32(r, (int)voff, (int)soff, 0);
+  const f32x2 t = adorym_raw_load_v2f32(r, (int)voff, (int)soff, AUX);
   return make_float2(t.x, t.y);
 }
+template <int AUX = 0>
 __device__ __forceinline__ void bstore2(rsrc_t r, float2 v, uint32_t voff, uint32_t soff) {
   f32x2 t;
   t.x = v.x;
   t.y = v.y;
-  adorym_raw_store_v2f32(t, r, (int)voff, (int)soff, 0);
+  adorym_raw_store_v2f32(t, r, (int)voff, (int)soff, AUX);
 }
 __device__ __forceinline__ void batomic_add(rsrc_t r, float v, uint32_t voff, uint32_t soff) {
   (void)__builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(v, r, voff, soff, 0);
+}
+
+// ----------------------------------------------------------------------------
+// Cross-workgroup exchange (K > 1)
+// ----------------------------------------------------------------------------
+// The K workgroups of a field meet at a barrier on a per-field counter.  The
+// counter only grows: the t-th barrier waits for K*t arrivals.  No
+// device-scope fences are used (on this chip they write back and invalidate
+// the per-XCD L2 caches): the exchanged data bypasses the caches
+// (kCoherent), each wave waits for its own stores to complete before the
+// workgroup barrier, and the counter is read and updated with relaxed
+// device-scope atomics.  The wait is bounded so that a group that cannot be
+// co-resident sets an error bit and finishes instead of hanging.
+constexpr int kSpinLimit = 1 << 22;
+constexpr int kErrBarrierTimeout = 2;
+
+__device__ __forceinline__ void wait_stores() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's memory operations have completed
+}
+
+__device__ __forceinline__ void group_barrier(int* counter, int target, int* err) {
+  wait_stores();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int spins = 0;
+    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) {
+        __hip_atomic_fetch_or(err, kErrBarrierTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Exchange state of one field group: two alternating N x N halves per field
+// slot, the barrier counter and the number of barriers passed so far.
+struct Exchange {
+  float2* buf;      // [2 phases][2 fields][N][N]
+  int* counter;
+  int* err;
+  int phase;
+};
+
+// Transpose of one or two fields through the exchange buffer (K > 1).
+template <class C, int NF>
+__device__ __forceinline__ void transpose_global(float2 (&v0)[C::R], float2 (&v1)[C::R], Exchange& x,
+                                                 const Lane<C>& ln, bool src_spec, bool dst_spec) {
+  constexpr int NN = C::N * C::N;
+  float2* base = x.buf + (size_t)(x.phase & 1) * 2 * NN;
+  const rsrc_t r = make_rsrc(base, 2 * NN * 8);
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    const uint32_t off = (uint32_t)(ln.line * C::N + ln.pos(m, src_spec)) * 8;
+    bstore2<kCoherent>(r, v0[m], off, 0);
+    if (NF == 2) bstore2<kCoherent>(r, v1[m], off, NN * 8);
+  }
+  ++x.phase;
+  group_barrier(x.counter, C::K * x.phase, x.err);
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    const uint32_t off = (uint32_t)(ln.pos(m, dst_spec) * C::N + ln.line) * 8;
+    v0[m] = bload2<kCoherent>(r, off, 0);
+    if (NF == 2) v1[m] = bload2<kCoherent>(r, off, NN * 8);
+  }
 }
 
 // ----------------------------------------------------------------------------

@@ -56,10 +56,13 @@ def test_workspace_size_formula():
     lib = _lib.load()
     g = _geom()
     size = lib.adorym_workspace_size(ctypes.byref(g), 50)
-    nn = 128 * 128 * 8
+    nn = 128 * 128 * 8                  # one complex64 field
     slots = 63 // 16 + 1 + 1            # slices 0, 16, 32, 48 and the last (63)
-    expect = nn + 512 + 50 * nn + 50 * slots * nn
-    assert expect <= size < expect + 4 * 256
+    # probe spectrum + its gradient sum, loss and shift partials for up to 8
+    # workgroups per position, barrier counters, probe-gradient partials,
+    # checkpoints, and two double-buffered exchange fields per position
+    expect = 2 * nn + 50 * 8 * 8 + 50 * 8 * 2 * 8 + 50 * 4 + 50 * nn + 50 * slots * nn + 50 * 4 * nn
+    assert expect <= size < expect + 8 * 256
     assert lib.adorym_workspace_size(ctypes.byref(_geom(n_slices=0)), 50) == 0
     assert lib.adorym_workspace_size(ctypes.byref(g), 0) == 0
 
@@ -68,6 +71,11 @@ def test_supported_sizes():
     lib = _lib.load()
     assert lib.adorym_supports_n(64) == 1 and lib.adorym_supports_n(128) == 1
     assert lib.adorym_supports_n(100) == 0 and lib.adorym_supports_n(0) == 0
+
+
+def test_set_split_validation_without_device():
+    lib = _lib.load()
+    assert lib.adorym_set_split(None, 128, 4) == _lib.EINVAL
 
 
 def test_null_context_rejected_without_touching_the_device():

@@ -118,6 +118,20 @@ def test_loss_grad_matches_oracle(ctx, n, s, lat, npos, repr_, loss, ckpt):
     check_grads(got, ref, case)
 
 
+@pytest.mark.parametrize("n,k", [(64, 1), (64, 2), (64, 4), (128, 1), (128, 2), (128, 4), (128, 8)])
+def test_every_split_matches_oracle(ctx, n, k):
+    """Fields split over k cooperating workgroups give the same results."""
+    sc = synth.small_case(seed=300 + n + k, n=n, n_slices=7, lateral=n + 30, n_pos=3, strength=30.0)
+    case = Case(sc)
+    ctx.set_split(n, k)
+    try:
+        got = run_grad(ctx, case)
+    finally:
+        ctx.set_split(n, 0)
+    assert rel_l2(got["intensity"], case.oracle_forward()) <= TOL_I
+    check_grads(got, case.oracle_loss_grad(), case)
+
+
 def test_checkpoint_interval_does_not_change_results(ctx):
     sc = synth.small_case(seed=31, n=64, n_slices=12, lateral=90, n_pos=3, strength=30.0)
     case = Case(sc)
