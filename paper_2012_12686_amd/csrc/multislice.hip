@@ -20,9 +20,10 @@ namespace {
 int pick_split(const adorym_ctx* ctx, int n, int batch) {
   const int forced = n == 64 ? ctx->split64 : (n == 128 ? ctx->split128 : 0);
   if (forced > 0) return forced;
+  // largest power-of-two split that keeps the grid within one workgroup per CU
   const int kmax = n == 64 ? 4 : 8;
   int k = 1;
-  while (k < kmax && batch * k < 256) k *= 2;
+  while (k < kmax && batch * (2 * k) <= 256) k *= 2;
   return k;
 }
 

@@ -66,6 +66,7 @@ struct MsParams {
   double* gs_part;         // [B][K][2] shift-gradient partials
   float2* xbuf;            // [B][2][2][N][N] exchange buffers (K > 1)
   int* counters;           // [B] group barrier counters (K > 1)
+  int* xcc;                // [B][K] XCD ids of each group's members (K > 1)
   int* err;
   int B, S, Ly, Lx, ckpt_every, nslots;
   float kdz;               // k * dz
@@ -185,14 +186,26 @@ __device__ __forceinline__ rsrc_t slice_rsrc(const float* base, int j, const Chu
   return make_rsrc(base + (size_t)j * (o.slice_bytes / 4), o.slice_bytes);
 }
 
-// Modulate the wave by slice j (Eq. ri_modulation or complex_modulation).
-template <class C, int REPR, bool ROW>
-__device__ __forceinline__ void modulate(float2 (&v)[C::R], const MsParams& P, const ChunkOffsets& o, int j) {
+// Object values of slice j on this thread's elements (layout ROW/COL).
+template <class C, bool ROW>
+__device__ __forceinline__ void load_chunk(float (&ca)[C::R], float (&cb)[C::R], const MsParams& P,
+                                           const ChunkOffsets& o, int j) {
   const rsrc_t ra = slice_rsrc(P.a, j, o), rb = slice_rsrc(P.b, j, o);
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
+    ca[m] = chunk_load<C, ROW>(ra, o, m);
+    cb[m] = chunk_load<C, ROW>(rb, o, m);
+  }
+}
+
+// Modulate the wave by one slice (Eq. ri_modulation or complex_modulation).
+template <class C, int REPR>
+__device__ __forceinline__ void modulate(float2 (&v)[C::R], const float (&ca)[C::R], const float (&cb)[C::R],
+                                         float kdz) {
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
     float2 t, tinv;
-    transmission<REPR>(P.kdz, chunk_load<C, ROW>(ra, o, m), chunk_load<C, ROW>(rb, o, m), t, tinv);
+    transmission<REPR>(kdz, ca[m], cb[m], t, tinv);
     v[m] = cmul(v[m], t);
   }
 }
@@ -233,12 +246,17 @@ __device__ __forceinline__ void place_probe(float2 (&v)[C::R], const MsParams& P
 }
 
 // One forward slice step: (store) modulate, and propagate to slice j + 1.
+// ca/cb hold slice j's object values on entry (loaded ahead of time when
+// the tile prefetches) and slice j+1's on exit when prefetching.
 template <class C, int REPR, bool ROW, bool CKPT>
-__device__ __forceinline__ void forward_slice(float2 (&v)[C::R], const MsParams& P, MsShared<C>& sh, Work<C>& wk,
+__device__ __forceinline__ void forward_slice(float2 (&v)[C::R], float (&ca)[C::R], float (&cb)[C::R],
+                                              const MsParams& P, MsShared<C>& sh, Work<C>& wk,
                                               const ChunkOffsets& o, int j) {
   if (CKPT && is_ckpt(j, P.S, P.ckpt_every)) field_store<C>(v, ckpt_ptr<C>(P, wk, ckpt_slot(j, P.S, P.ckpt_every)), wk.ln);
-  modulate<C, REPR, ROW>(v, P, o, j);
+  if (!C::PREFETCH) load_chunk<C, ROW>(ca, cb, P, o, j);
+  modulate<C, REPR>(v, ca, cb, P.kdz);
   if (j < P.S - 1) {
+    if (C::PREFETCH) load_chunk<C, !ROW>(ca, cb, P, o, j + 1);   // in flight during the propagation
     propagate_line<C, false>(v, sh.tb, wk.ln);
     xfer<C>(v, sh, wk, false, false);
     propagate_line<C, false>(v, sh.tb, wk.ln);
@@ -249,23 +267,25 @@ __device__ __forceinline__ void forward_slice(float2 (&v)[C::R], const MsParams&
 // fields are taken back to slice j-1 by the adjoint propagator.
 //   in : psi = phi_j (the wave leaving slice j, rebuilt by the backward
 //        recursion) unless slice j is anchored on a checkpoint;
-//        lam = dL/dphi_j
-//   out: psi = phi_{j-1} = P^H psi_j, lam = dL/dphi_{j-1} = P^H conj(t_j) lam
+//        lam = dL/dphi_j; ca/cb = slice j's object values when prefetching
+//   out: psi = phi_{j-1} = P^H psi_j, lam = dL/dphi_{j-1} = P^H conj(t_j) lam;
+//        ca/cb = slice j-1's object values when prefetching
 template <class C, int REPR, bool ROW>
-__device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam)[C::R], const MsParams& P,
-                                               MsShared<C>& sh, Work<C>& wk, const ChunkOffsets& o, int j) {
+__device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam)[C::R], float (&ca)[C::R],
+                                               float (&cb)[C::R], const MsParams& P, MsShared<C>& sh, Work<C>& wk,
+                                               const ChunkOffsets& o, int j) {
   const Lane<C>& ln = wk.ln;
   const bool anchored = is_ckpt(j, P.S, P.ckpt_every);
   if (anchored) field_load<C>(psi, ckpt_ptr<C>(P, wk, ckpt_slot(j, P.S, P.ckpt_every)), ln);  // psi_j exactly
-  const rsrc_t ra = slice_rsrc(P.a, j, o), rb = slice_rsrc(P.b, j, o);
+  if (!C::PREFETCH) load_chunk<C, ROW>(ca, cb, P, o, j);
   const bool grads = P.g_a != nullptr;
-  const rsrc_t rga = grads ? slice_rsrc(P.g_a, j, o) : ra;
-  const rsrc_t rgb = grads ? slice_rsrc(P.g_b, j, o) : rb;
+  const rsrc_t rga = grads ? slice_rsrc(P.g_a, j, o) : make_rsrc(P.a, 0);
+  const rsrc_t rgb = grads ? slice_rsrc(P.g_b, j, o) : make_rsrc(P.b, 0);
   const float kdz = P.kdz;
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
     float2 t, tinv;
-    transmission<REPR>(kdz, chunk_load<C, ROW>(ra, o, m), chunk_load<C, ROW>(rb, o, m), t, tinv);
+    transmission<REPR>(kdz, ca[m], cb[m], t, tinv);
     const float2 in_wave = anchored ? psi[m] : cmul(psi[m], tinv);   // psi_j
     const float2 out_wave = anchored ? cmul(psi[m], t) : psi[m];     // phi_j
     const float2 l = lam[m];
@@ -284,6 +304,7 @@ __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam
     psi[m] = in_wave;
   }
   if (j > 0) {
+    if (C::PREFETCH) load_chunk<C, !ROW>(ca, cb, P, o, j - 1);   // in flight during the propagation
     const bool need_psi = !is_ckpt(j - 1, P.S, P.ckpt_every);
     if (need_psi) {
       propagate_line<C, true>(psi, sh.tb, ln);
@@ -327,6 +348,7 @@ __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
   wk.x.counter = P.counters + b;
   wk.x.err = P.err;
   wk.x.phase = 0;
+  wk.x.local = false;
 
   // TakeObjectChunk: the chunk must lie inside the object.
   if (wk.cy < 0 || wk.cx < 0 || wk.cy + N > P.Ly || wk.cx + N > P.Lx) {
@@ -349,14 +371,17 @@ __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
 
   setup_tables<C>(sh, ln, P.chirp, sy, sx);
   const ChunkOffsets o = chunk_offsets<C>(ln, wk.cy, wk.cx, P.Ly, P.Lx);
+  if constexpr (C::K > 1) exchange_init<C::K>(wk.x, P.xcc + b * C::K, part);
 
   float2 v[C::R];
+  float ca[C::R], cb[C::R];
+  if (C::PREFETCH) load_chunk<C, true>(ca, cb, P, o, 0);
   place_probe<C>(v, P, sh, wk);
 
   // MultislicePropagate: even slices in ROW layout, odd slices in COL layout.
   for (int j = 0; j < P.S; j += 2) {
-    forward_slice<C, REPR, true, LOSS>(v, P, sh, wk, o, j);
-    if (j + 1 < P.S) forward_slice<C, REPR, false, LOSS>(v, P, sh, wk, o, j + 1);
+    forward_slice<C, REPR, true, LOSS>(v, ca, cb, P, sh, wk, o, j);
+    if (j + 1 < P.S) forward_slice<C, REPR, false, LOSS>(v, ca, cb, P, sh, wk, o, j + 1);
   }
   const bool last_row = ((P.S - 1) & 1) == 0;
 
@@ -414,16 +439,17 @@ __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
 
   float2 psi[C::R];
   int j = P.S - 1;
+  // the forward sweep left slice S-1's object values in ca/cb
   if (!last_row) {
-    backward_slice<C, REPR, false>(psi, v, P, sh, wk, o, j);
+    backward_slice<C, REPR, false>(psi, v, ca, cb, P, sh, wk, o, j);
     --j;
   }
   // now slice j is even (ROW); pairs (j ROW, j-1 COL) down to slice 0
   for (; j >= 1; j -= 2) {
-    backward_slice<C, REPR, true>(psi, v, P, sh, wk, o, j);
-    backward_slice<C, REPR, false>(psi, v, P, sh, wk, o, j - 1);
+    backward_slice<C, REPR, true>(psi, v, ca, cb, P, sh, wk, o, j);
+    backward_slice<C, REPR, false>(psi, v, ca, cb, P, sh, wk, o, j - 1);
   }
-  if (j == 0) backward_slice<C, REPR, true>(psi, v, P, sh, wk, o, 0);
+  if (j == 0) backward_slice<C, REPR, true>(psi, v, ca, cb, P, sh, wk, o, 0);
   // v = dL/d(shifted probe) in ROW layout, natural order.
 
   // FourierShift adjoint: G = DFT(g_pb) in COL layout (kx line, ky spectral).
@@ -556,7 +582,7 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 constexpr int kMaxSplit = 8;   // largest K any kernel uses
 
 struct WsLayout {
-  size_t q, gsum, loss_part, gs_part, counters, gacc, ckpt, xbuf, total;
+  size_t q, gsum, loss_part, gs_part, counters, xcc, gacc, ckpt, xbuf, total;
   int nslots;
 };
 
@@ -571,6 +597,7 @@ inline WsLayout ws_layout(const adorym_geom* g, int batch) {
   w.loss_part = off; off += align256((size_t)batch * kMaxSplit * sizeof(double));
   w.gs_part = off; off += align256((size_t)batch * kMaxSplit * 2 * sizeof(double));
   w.counters = off; off += align256((size_t)batch * sizeof(int));
+  w.xcc = off; off += align256((size_t)batch * kMaxSplit * sizeof(int));
   w.gacc = off; off += align256((size_t)batch * nn * sizeof(float2));
   w.ckpt = off; off += align256((size_t)batch * w.nslots * nn * sizeof(float2));
   w.xbuf = off; off += align256((size_t)batch * 4 * nn * sizeof(float2));
@@ -647,6 +674,7 @@ adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const f
   P.gs_part = reinterpret_cast<double*>(base + w.gs_part);
   P.xbuf = reinterpret_cast<float2*>(base + w.xbuf);
   P.counters = reinterpret_cast<int*>(base + w.counters);
+  P.xcc = reinterpret_cast<int*>(base + w.xcc);
   P.err = ctx->d_err;
   P.B = batch; P.S = g->n_slices; P.Ly = g->obj_ny; P.Lx = g->obj_nx;
   P.ckpt_every = g->ckpt_every; P.nslots = w.nslots;

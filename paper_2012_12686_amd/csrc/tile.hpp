@@ -252,6 +252,11 @@ struct TileCfg {
   static constexpr int LOGL = ilog2(L);
   static constexpr int PITCH = N + 8;           // LDS row pitch in float2 (bank spread)
   static constexpr int LDS_FIELD = K == 1 ? N * PITCH : 1;   // LDS transpose buffer (K == 1 only)
+  // K == 1 workgroups have 1024 threads and 128 registers per lane: fence the
+  // scheduler so table loads are not hoisted early; split tiles have room.
+  static constexpr bool FENCE = (K == 1);
+  // Split tiles also have the registers to prefetch the next slice's chunk.
+  static constexpr bool PREFETCH = (K > 1);
   static_assert(N % L == 0 && LINES % RPW == 0 && WAVES >= 1, "bad tile");
 };
 
@@ -279,7 +284,7 @@ template <class C>
 struct Tables {
   float2 wn[C::N];          // W_N^e = exp(-2 pi i e / N), e in [0, N)
   float2 tw[C::R * C::L];   // entry k2*L + q: W_N^{q k2} (inter-stage twiddles)
-  float2 h[C::N];           // 1D Fresnel kernel / N, natural frequency order
+  float2 h[C::N];           // 1D Fresnel kernel / N at spectral slot m*L + k1 (frequency R*k1 + m)
 };
 
 template <class C>
@@ -297,15 +302,18 @@ __device__ void build_twiddles(Tables<C>& tb, int tid) {
   }
 }
 
-// 1D Fresnel kernel exp(i pi (lambda dz / dx^2) f^2) / N, f = fftfreq(N).
+// 1D Fresnel kernel exp(i pi (lambda dz / dx^2) f^2) / N, f = fftfreq(N),
+// stored so that the L lanes of a line read L consecutive entries.
 template <class C>
 __device__ void build_fresnel(Tables<C>& tb, int tid, double chirp /* lambda dz / dx^2 */) {
-  for (int k = tid; k < C::N; k += C::THREADS) {
+  for (int idx = tid; idx < C::N; idx += C::THREADS) {
+    const int m = idx / C::L, k1 = idx % C::L;
+    const int k = C::R * k1 + m;
     int kk = (k < (C::N + 1) / 2) ? k : k - C::N;
     double f = double(kk) / double(C::N);
     double s, c;
     sincospi(chirp * f * f, &s, &c);
-    tb.h[k] = make_float2(float(c / C::N), float(s / C::N));
+    tb.h[idx] = make_float2(float(c / C::N), float(s / C::N));
   }
 }
 
@@ -331,9 +339,9 @@ __device__ __forceinline__ void apply_twiddles(float2 (&v)[C::R], const Tables<C
 #pragma unroll
   for (int k2 = 1; k2 < C::R; ++k2) {
     v[k2] = cmul(v[k2], tw_at<C, SIGN>(tb, ln.q, k2));
-    if ((k2 & 3) == 3) sched_fence();
+    if (C::FENCE && (k2 & 3) == 3) sched_fence();
   }
-  sched_fence();
+  if (C::FENCE) sched_fence();
 }
 
 // ----------------------------------------------------------------------------
@@ -387,12 +395,12 @@ __device__ __forceinline__ void ifft_line(float2 (&v)[C::R], const Tables<C>& tb
 template <class C, bool CONJ>
 __device__ __forceinline__ void propagate_line(float2 (&v)[C::R], const Tables<C>& tb, const Lane<C>& ln) {
   fft_line<C, -1>(v, tb, ln);
-  sched_fence();
+  if (C::FENCE) sched_fence();
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
-    float2 h = tb.h[ln.pos_spec(m)];
+    float2 h = tb.h[m * C::L + ln.k1];     // kernel at frequency R*k1 + m
     v[m] = CONJ ? cmulc(v[m], h) : cmul(v[m], h);
-    if ((m & 3) == 3) sched_fence();
+    if (C::FENCE && (m & 3) == 3) sched_fence();
   }
   ifft_line<C, +1>(v, tb, ln);
 }
@@ -499,34 +507,66 @@ __device__ __forceinline__ void group_barrier(int* counter, int target, int* err
 
 // Exchange state of one field group: two alternating N x N halves per field
 // slot, the barrier counter and the number of barriers passed so far.
+// `local` is set when every member of the group runs on the same XCD: the
+// exchange then stays in that XCD's L2 (stores write through the L1, loads
+// skip it); otherwise it goes through memory (kCoherent).
 struct Exchange {
   float2* buf;      // [2 phases][2 fields][N][N]
   int* counter;
   int* err;
   int phase;
+  bool local;
 };
 
-// Transpose of one or two fields through the exchange buffer (K > 1).
-template <class C, int NF>
-__device__ __forceinline__ void transpose_global(float2 (&v0)[C::R], float2 (&v1)[C::R], Exchange& x,
-                                                 const Lane<C>& ln, bool src_spec, bool dst_spec) {
+constexpr int kL1Bypass = 1;      // sc0: load misses in the L1, hits in L2
+
+__device__ __forceinline__ int xcc_id() {
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);   // HW_REG_XCC_ID bits [3:0]
+}
+
+// First barrier of a group: publish this workgroup's XCD, learn whether all
+// members share one.  ids: [K] ints of this field's group.
+template <int K>
+__device__ __forceinline__ void exchange_init(Exchange& x, int* ids, int part) {
+  x.phase = 0;
+  x.local = false;
+  if (threadIdx.x == 0) __hip_atomic_store(ids + part, xcc_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  ++x.phase;
+  group_barrier(x.counter, K * x.phase, x.err);
+  bool same = true;
+  const int first = __hip_atomic_load(ids, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int i = 1; i < K; ++i) same &= __hip_atomic_load(ids + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == first;
+  x.local = same;
+}
+
+template <class C, int NF, int LD, int ST>
+__device__ __forceinline__ void transpose_global_impl(float2 (&v0)[C::R], float2 (&v1)[C::R], Exchange& x,
+                                                      const Lane<C>& ln, bool src_spec, bool dst_spec) {
   constexpr int NN = C::N * C::N;
   float2* base = x.buf + (size_t)(x.phase & 1) * 2 * NN;
   const rsrc_t r = make_rsrc(base, 2 * NN * 8);
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
     const uint32_t off = (uint32_t)(ln.line * C::N + ln.pos(m, src_spec)) * 8;
-    bstore2<kCoherent>(r, v0[m], off, 0);
-    if (NF == 2) bstore2<kCoherent>(r, v1[m], off, NN * 8);
+    bstore2<ST>(r, v0[m], off, 0);
+    if (NF == 2) bstore2<ST>(r, v1[m], off, NN * 8);
   }
   ++x.phase;
   group_barrier(x.counter, C::K * x.phase, x.err);
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
     const uint32_t off = (uint32_t)(ln.pos(m, dst_spec) * C::N + ln.line) * 8;
-    v0[m] = bload2<kCoherent>(r, off, 0);
-    if (NF == 2) v1[m] = bload2<kCoherent>(r, off, NN * 8);
+    v0[m] = bload2<LD>(r, off, 0);
+    if (NF == 2) v1[m] = bload2<LD>(r, off, NN * 8);
   }
+}
+
+// Transpose of one or two fields through the exchange buffer (K > 1).
+template <class C, int NF>
+__device__ __forceinline__ void transpose_global(float2 (&v0)[C::R], float2 (&v1)[C::R], Exchange& x,
+                                                 const Lane<C>& ln, bool src_spec, bool dst_spec) {
+  if (x.local) transpose_global_impl<C, NF, kL1Bypass, 0>(v0, v1, x, ln, src_spec, dst_spec);
+  else transpose_global_impl<C, NF, kCoherent, kCoherent>(v0, v1, x, ln, src_spec, dst_spec);
 }
 
 // ----------------------------------------------------------------------------
