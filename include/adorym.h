@@ -128,6 +128,22 @@ adorym_status adorym_loss_grad(adorym_ctx* ctx, const adorym_geom* g,
                                double* loss, float* g_a, float* g_b, float* g_probe,
                                float* g_shift, float* intensity);
 
+/* Tilt rotation of a slice-major float32 object [lz][ly][lx] about the y
+ * axis (Sec. S1.D.2, Eq. rotation_transform): every xz-plane is resampled
+ * by bilinear interpolation at (x0, z0) = R(theta)(x_t - cx, z_t - cz) + c,
+ * c = ((lx-1)/2, (lz-1)/2), zero outside.  transpose = 0: out = R in;
+ * transpose = 1: out = R^T in, the exact adjoint (for gradients).  `out` is
+ * overwritten and must not alias `in`.  Coordinates are computed in FP64. */
+adorym_status adorym_rotate(adorym_ctx* ctx, const float* in, float* out, int32_t lz, int32_t ly, int32_t lx,
+                            double theta, int transpose);
+
+/* One Adam step (Sec. S1.F) on n float32 values, in place on x, m, v:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * x -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), t >= 1.
+ * Complex arrays are updated as independent real and imaginary parts. */
+adorym_status adorym_adam(adorym_ctx* ctx, float* x, const float* g, float* m, float* v, size_t n, double lr,
+                          double beta1, double beta2, double eps, int32_t t);
+
 /* Synchronise the context's stream, return (and clear) any deferred
  * device-side error, e.g. ADORYM_ERANGE. */
 adorym_status adorym_sync_error(adorym_ctx* ctx);

@@ -171,5 +171,28 @@ class Context:
         return out
 
 
+    def rotate(self, obj: torch.Tensor, theta: float, transpose: bool = False, out=None) -> torch.Tensor:
+        """Rotate a float32 [Z][Y][X] object about y by theta (radians); transpose=True is R^T."""
+        self._bind_stream()
+        if obj.dtype != torch.float32 or obj.dim() != 3 or not obj.is_contiguous():
+            raise ValueError("obj: expected contiguous float32 [Z][Y][X]")
+        out = out if out is not None else torch.empty_like(obj)
+        lz, ly, lx = obj.shape
+        check(load().adorym_rotate(self._ctx, _ptr(obj), _ptr(out), lz, ly, lx, float(theta), int(transpose)),
+              self._ctx)
+        return out
+
+    def adam(self, x: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, t: int, lr: float,
+             beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        """In-place Adam step on float32 (or complex64, as pairs of reals) tensors."""
+        self._bind_stream()
+        arrs = [torch.view_as_real(a) if a.is_complex() else a for a in (x, g, m, v)]
+        n = arrs[0].numel()
+        for a in arrs:
+            if a.dtype != torch.float32 or a.numel() != n or not a.is_contiguous():
+                raise ValueError("adam: expected contiguous float32/complex64 tensors of one size")
+        check(load().adorym_adam(self._ctx, *[_ptr(a) for a in arrs], n, lr, beta1, beta2, eps, t), self._ctx)
+
+
 def supports_n(n: int) -> bool:
     return bool(load().adorym_supports_n(n))

@@ -1,0 +1,18 @@
+// context.hpp -- the library context behind the opaque adorym_ctx handle.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+struct adorym_ctx {
+  int device;
+  hipStream_t stream;
+  int* d_err;          // deferred device error flags (bit 0: chunk out of range)
+  char msg[512];
+  // optional timing of the main multislice kernel (adorym_profile_*)
+  std::vector<hipEvent_t> ev;   // start/stop pairs
+  int ev_used = 0;
+  bool prof = false;
+  // workgroups per position (0 = automatic) for N = 64 and N = 128
+  int split64 = 0, split128 = 0;
+};

@@ -35,18 +35,7 @@ using namespace adorym;
 #define ADORYM_L128 8
 #endif
 
-struct adorym_ctx {
-  int device;
-  hipStream_t stream;
-  int* d_err;          // deferred device error flags (bit 0: chunk out of range)
-  char msg[512];
-  // optional timing of the main multislice kernel (adorym_profile_*)
-  std::vector<hipEvent_t> ev;   // start/stop pairs
-  int ev_used = 0;
-  bool prof = false;
-  // workgroups per position (0 = automatic) for N = 64 and N = 128
-  int split64 = 0, split128 = 0;
-};
+#include "context.hpp"
 
 namespace adorym_ms {
 
