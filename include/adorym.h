@@ -144,6 +144,30 @@ adorym_status adorym_rotate(adorym_ctx* ctx, const float* in, float* out, int32_
 adorym_status adorym_adam(adorym_ctx* ctx, float* x, const float* g, float* m, float* v, size_t n, double lr,
                           double beta1, double beta2, double eps, int32_t t);
 
+/* ---- Batched evaluation of many independent scans --------------------
+ * One job = the arguments of one adorym_loss_grad call (its own geometry,
+ * object, probe, positions, measurements, outputs and workspace of
+ * adorym_workspace_size(&g, batch) bytes).  adorym_plan_create validates the
+ * jobs and uploads a job table (it allocates and synchronises: call it
+ * outside timed or captured regions).  adorym_plan_run then evaluates every
+ * job's loss and gradients: per probe size, one persistent launch whose
+ * workgroup groups draw (job, position) items from a device queue, longest
+ * first; it only launches kernels, so a whole iteration can be captured in
+ * a HIP graph.  The arrays named in the jobs must stay valid while the plan
+ * is used.  Supported probe sizes as adorym_supports_n. */
+typedef struct {
+  adorym_geom g;
+  const float* obj_a; const float* obj_b; const float* probe;
+  const int32_t* corner; const float* shift; int32_t batch;
+  const float* i_meas;
+  double* loss; float* g_a; float* g_b; float* g_probe; float* g_shift;
+  void* workspace; size_t ws_bytes;
+} adorym_job;
+typedef struct adorym_plan adorym_plan;
+adorym_status adorym_plan_create(adorym_ctx* ctx, const adorym_job* jobs, int32_t n_jobs, adorym_plan** out);
+adorym_status adorym_plan_run(adorym_ctx* ctx, adorym_plan* plan);
+adorym_status adorym_plan_destroy(adorym_plan* plan);
+
 /* Synchronise the context's stream, return (and clear) any deferred
  * device-side error, e.g. ADORYM_ERANGE. */
 adorym_status adorym_sync_error(adorym_ctx* ctx);
@@ -155,8 +179,8 @@ const char* adorym_last_error_message(adorym_ctx* ctx);
  * n: k = 1 keeps the field in one workgroup (transposes through LDS);
  * k > 1 splits its lines over k workgroups that exchange through L2.
  * k = 0 restores the automatic choice (enough workgroups to cover the
- * CUs).  Supported: n = 64 with k in {1, 2, 4}; n = 128 with k in
- * {1, 2, 4, 8}; else ADORYM_EUNSUPPORTED.  Results do not depend on k
+ * CUs).  Supported: n = 64 and n = 96 with k in {1, 2, 4}; n = 128 with
+ * k in {1, 2, 4, 8}; else ADORYM_EUNSUPPORTED.  Results do not depend on k
  * beyond float rounding of the gradient atomics. */
 adorym_status adorym_set_split(adorym_ctx* ctx, int32_t n, int32_t k);
 

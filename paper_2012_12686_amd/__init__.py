@@ -3,5 +3,5 @@
 The computation lives in the HIP library ``libadorym.so`` (C ABI in
 ``include/adorym.h``); this package is its Python binding.
 """
-from .api import Context, Geometry, split_positions, supports_n  # noqa: F401
+from .api import Context, Geometry, Job, Plan, split_positions, supports_n  # noqa: F401
 from .autograd import MultisliceLoss, multislice_loss  # noqa: F401

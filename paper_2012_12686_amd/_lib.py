@@ -33,6 +33,20 @@ class Geom(ctypes.Structure):
     ]
 
 
+class Job(ctypes.Structure):
+    """Mirror of ``adorym_job``."""
+
+    _fields_ = [
+        ("g", Geom),
+        ("obj_a", ctypes.c_void_p), ("obj_b", ctypes.c_void_p), ("probe", ctypes.c_void_p),
+        ("corner", ctypes.c_void_p), ("shift", ctypes.c_void_p), ("batch", ctypes.c_int32),
+        ("i_meas", ctypes.c_void_p),
+        ("loss", ctypes.c_void_p), ("g_a", ctypes.c_void_p), ("g_b", ctypes.c_void_p),
+        ("g_probe", ctypes.c_void_p), ("g_shift", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t),
+    ]
+
+
 # name -> (restype, argtypes); every function include/adorym.h declares
 _P = ctypes.c_void_p
 _GP = ctypes.POINTER(Geom)
@@ -52,6 +66,9 @@ SIGNATURES = {
     "adorym_sync_error": (ctypes.c_int, [_P]),
     "adorym_last_error_message": (ctypes.c_char_p, [_P]),
     "adorym_set_split": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "adorym_plan_create": (ctypes.c_int, [_P, ctypes.POINTER(Job), ctypes.c_int32, ctypes.POINTER(_P)]),
+    "adorym_plan_run": (ctypes.c_int, [_P, _P]),
+    "adorym_plan_destroy": (ctypes.c_int, [_P]),
     "adorym_profile_start": (ctypes.c_int, [_P, ctypes.c_int32]),
     "adorym_profile_stop": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
 }

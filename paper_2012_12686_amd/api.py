@@ -194,5 +194,78 @@ class Context:
         check(load().adorym_adam(self._ctx, *[_ptr(a) for a in arrs], n, lr, beta1, beta2, eps, t), self._ctx)
 
 
+    def plan(self, jobs) -> "Plan":
+        """A batched plan over many jobs; see ``Plan``."""
+        return Plan(self, jobs)
+
+
+@dataclasses.dataclass
+class Job:
+    """One scan for a batched plan: inputs, outputs and workspace (all device tensors)."""
+
+    geom: Geometry
+    obj_a: torch.Tensor
+    obj_b: torch.Tensor
+    probe: torch.Tensor
+    corner: torch.Tensor
+    shift: torch.Tensor
+    i_meas: torch.Tensor
+    out: dict = dataclasses.field(default_factory=dict)
+    workspace: Optional[torch.Tensor] = None
+
+
+class Plan:
+    """Loss and gradients of many jobs in one persistent launch per probe size.
+
+    The plan keeps references to every tensor it names; ``run()`` only enqueues
+    kernels (capturable in a graph).  Outputs are in each job's ``out`` dict
+    (``loss``, ``g_a``, ``g_b``, ``g_probe``, ``g_shift``).
+    """
+
+    def __init__(self, ctx: "Context", jobs):
+        self.ctx = ctx
+        self.jobs = list(jobs)
+        dev = ctx.device
+        cjobs = (_lib.Job * len(self.jobs))()
+        for i, j in enumerate(self.jobs):
+            b = ctx._check_inputs(j.geom, j.obj_a, j.obj_b, j.probe, j.corner, j.shift)
+            o = j.out
+            o.setdefault("loss", torch.empty((), dtype=torch.float64, device=dev))
+            o.setdefault("g_a", torch.empty_like(j.obj_a))
+            o.setdefault("g_b", torch.empty_like(j.obj_b))
+            o.setdefault("g_probe", torch.empty_like(j.probe))
+            o.setdefault("g_shift", torch.empty((b, 2), dtype=torch.float32, device=dev))
+            if j.workspace is None:
+                j.workspace = ctx.workspace(j.geom, b)
+            cj = cjobs[i]
+            cj.g = j.geom.to_c()
+            cj.obj_a, cj.obj_b = j.obj_a.data_ptr(), j.obj_b.data_ptr()
+            cj.probe = torch.view_as_real(j.probe).data_ptr()
+            cj.corner, cj.shift, cj.batch = j.corner.data_ptr(), j.shift.data_ptr(), b
+            cj.i_meas = j.i_meas.data_ptr()
+            cj.loss, cj.g_a, cj.g_b = o["loss"].data_ptr(), o["g_a"].data_ptr(), o["g_b"].data_ptr()
+            cj.g_probe = torch.view_as_real(o["g_probe"]).data_ptr()
+            cj.g_shift = o["g_shift"].data_ptr()
+            cj.workspace, cj.ws_bytes = j.workspace.data_ptr(), j.workspace.numel()
+        self._cjobs = cjobs
+        self._plan = ctypes.c_void_p(0)
+        check(load().adorym_plan_create(ctx._ctx, cjobs, len(self.jobs), ctypes.byref(self._plan)), ctx._ctx)
+
+    def run(self):
+        self.ctx._bind_stream()
+        check(load().adorym_plan_run(self.ctx._ctx, self._plan), self.ctx._ctx)
+
+    def close(self):
+        if self._plan:
+            load().adorym_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def supports_n(n: int) -> bool:
     return bool(load().adorym_supports_n(n))

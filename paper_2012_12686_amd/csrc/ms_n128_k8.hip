@@ -2,3 +2,5 @@
 #include "multislice_impl.hpp"
 
 template ADORYM_RUN_SIGNATURE(128, 8, 8);
+template ADORYM_BATCHED_SIGNATURE(128, 8, 8);
+template ADORYM_PARAMS_SIGNATURE(128, 8, 8);

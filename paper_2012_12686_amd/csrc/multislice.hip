@@ -6,22 +6,51 @@
 using namespace adorym_ms;
 
 extern template ADORYM_RUN_SIGNATURE(64, 4, 1);
+extern template ADORYM_BATCHED_SIGNATURE(64, 4, 1);
+extern template ADORYM_PARAMS_SIGNATURE(64, 4, 1);
 extern template ADORYM_RUN_SIGNATURE(64, 4, 2);
+extern template ADORYM_BATCHED_SIGNATURE(64, 4, 2);
+extern template ADORYM_PARAMS_SIGNATURE(64, 4, 2);
 extern template ADORYM_RUN_SIGNATURE(64, 4, 4);
+extern template ADORYM_BATCHED_SIGNATURE(64, 4, 4);
+extern template ADORYM_PARAMS_SIGNATURE(64, 4, 4);
+extern template ADORYM_RUN_SIGNATURE(96, 8, 1);
+extern template ADORYM_BATCHED_SIGNATURE(96, 8, 1);
+extern template ADORYM_PARAMS_SIGNATURE(96, 8, 1);
+extern template ADORYM_RUN_SIGNATURE(96, 8, 2);
+extern template ADORYM_BATCHED_SIGNATURE(96, 8, 2);
+extern template ADORYM_PARAMS_SIGNATURE(96, 8, 2);
+extern template ADORYM_RUN_SIGNATURE(96, 8, 4);
+extern template ADORYM_BATCHED_SIGNATURE(96, 8, 4);
+extern template ADORYM_PARAMS_SIGNATURE(96, 8, 4);
 extern template ADORYM_RUN_SIGNATURE(128, 8, 1);
+extern template ADORYM_BATCHED_SIGNATURE(128, 8, 1);
+extern template ADORYM_PARAMS_SIGNATURE(128, 8, 1);
 extern template ADORYM_RUN_SIGNATURE(128, 8, 2);
+extern template ADORYM_BATCHED_SIGNATURE(128, 8, 2);
+extern template ADORYM_PARAMS_SIGNATURE(128, 8, 2);
 extern template ADORYM_RUN_SIGNATURE(128, 8, 4);
+extern template ADORYM_BATCHED_SIGNATURE(128, 8, 4);
+extern template ADORYM_PARAMS_SIGNATURE(128, 8, 4);
 extern template ADORYM_RUN_SIGNATURE(128, 8, 8);
+extern template ADORYM_BATCHED_SIGNATURE(128, 8, 8);
+extern template ADORYM_PARAMS_SIGNATURE(128, 8, 8);
+extern template ADORYM_PROLOGUE_SIGNATURE(64, 4);
+extern template ADORYM_EPILOGUE_SIGNATURE(64, 4);
+extern template ADORYM_PROLOGUE_SIGNATURE(96, 8);
+extern template ADORYM_EPILOGUE_SIGNATURE(96, 8);
+extern template ADORYM_PROLOGUE_SIGNATURE(128, 8);
+extern template ADORYM_EPILOGUE_SIGNATURE(128, 8);
 
 namespace {
 
 // Workgroups per position: the context's choice for this N if one was set
 // (adorym_set_split, e.g. by an autotuner), else enough to cover the CUs.
 int pick_split(const adorym_ctx* ctx, int n, int batch) {
-  const int forced = n == 64 ? ctx->split64 : (n == 128 ? ctx->split128 : 0);
+  const int forced = n == 64 ? ctx->split64 : (n == 96 ? ctx->split96 : (n == 128 ? ctx->split128 : 0));
   if (forced > 0) return forced;
   // largest power-of-two split that keeps the grid within one workgroup per CU
-  const int kmax = n == 64 ? 4 : 8;
+  const int kmax = n == 128 ? 8 : 4;
   int k = 1;
   while (k < kmax && batch * (2 * k) <= 256) k *= 2;
   return k;
@@ -41,6 +70,12 @@ adorym_status dispatch(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
       case 2: ADORYM_RUN(64, 4, 2);
       case 4: ADORYM_RUN(64, 4, 4);
     }
+  } else if (g->n == 96) {
+    switch (k) {
+      case 1: ADORYM_RUN(96, 8, 1);
+      case 2: ADORYM_RUN(96, 8, 2);
+      case 4: ADORYM_RUN(96, 8, 4);
+    }
   } else if (g->n == 128) {
     switch (k) {
       case 1: ADORYM_RUN(128, 8, 1);
@@ -53,11 +88,93 @@ adorym_status dispatch(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
   return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size / split");
 }
 
+
+// ----------------------------------------------------------------------------
+// Batched plans: many jobs of several probe sizes in persistent launches
+// ----------------------------------------------------------------------------
+struct PlanClass {
+  int n, l, k, groups, repr;
+  int n_items;
+  int2* items;          // device [(job, position)] sorted by decreasing cost
+  int* state;           // device: ticket, then mailbox[groups], counters[groups], xcc[groups*K]
+  float2* xbuf;         // device [groups][4][N][N]
+};
+
+}  // namespace
+
+struct adorym_plan {
+  std::vector<adorym_job> jobs;
+  std::vector<MsParams> params;     // host copy
+  MsParams* d_params = nullptr;     // device job table
+  std::vector<PlanClass> classes;
+  int device = 0;
+};
+
+namespace {
+
+template <int N, int L>
+MsParams params_for(adorym_ctx* ctx, const adorym_job& j, int k) {
+  MsParams P;
+  switch (k) {
+    case 1: P = make_params<N, L, 1>(ctx, &j.g, j.obj_a, j.obj_b, j.batch, j.corner, j.shift, j.i_meas,
+                                     j.workspace, j.g_probe != nullptr, j.g_a, j.g_b, nullptr); break;
+    case 2: P = make_params<N, L, 2>(ctx, &j.g, j.obj_a, j.obj_b, j.batch, j.corner, j.shift, j.i_meas,
+                                     j.workspace, j.g_probe != nullptr, j.g_a, j.g_b, nullptr); break;
+    default: P = make_params<N, L, 4>(ctx, &j.g, j.obj_a, j.obj_b, j.batch, j.corner, j.shift, j.i_meas,
+                                      j.workspace, j.g_probe != nullptr, j.g_a, j.g_b, nullptr); break;
+  }
+  P.ksplit = k;
+  return P;
+}
+
+void job_prologue(const MsParams& P, const adorym_job& j, hipStream_t st) {
+  switch (j.g.n) {
+    case 64: launch_prologue<64, 4>(P, j.probe, &j.g, st); break;
+    case 96: launch_prologue<96, 8>(P, j.probe, &j.g, st); break;
+    default: launch_prologue<128, 8>(P, j.probe, &j.g, st); break;
+  }
+}
+
+void job_epilogue(const MsParams& P, const adorym_job& j, hipStream_t st) {
+  switch (j.g.n) {
+    case 64: launch_epilogue<64, 4>(P, j.workspace, &j.g, j.loss, j.g_probe, j.g_shift, st); break;
+    case 96: launch_epilogue<96, 8>(P, j.workspace, &j.g, j.loss, j.g_probe, j.g_shift, st); break;
+    default: launch_epilogue<128, 8>(P, j.workspace, &j.g, j.loss, j.g_probe, j.g_shift, st); break;
+  }
+}
+
+static __global__ void reset_ints_kernel(int* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+void class_launch(const PlanClass& c, const MsParams* d_params, int* err, hipStream_t st) {
+  const int n_state = 1 + 2 * c.groups + c.groups * c.k;
+  hipLaunchKernelGGL(reset_ints_kernel, dim3((n_state + 255) / 256), dim3(256), 0, st, c.state, n_state);
+  int* ticket = c.state;
+  int* mailbox = c.state + 1;
+  int* counters = mailbox + c.groups;
+  int* xcc = counters + c.groups;
+#define ADORYM_BATCH(N_, L_, K_) \
+  launch_batched<N_, L_, K_>(d_params, c.items, c.n_items, ticket, mailbox, counters, xcc, c.xbuf, err, c.groups, \
+                             c.repr, st)
+  if (c.n == 64) {
+    if (c.k == 1) ADORYM_BATCH(64, 4, 1); else if (c.k == 2) ADORYM_BATCH(64, 4, 2); else ADORYM_BATCH(64, 4, 4);
+  } else if (c.n == 96) {
+    if (c.k == 1) ADORYM_BATCH(96, 8, 1); else if (c.k == 2) ADORYM_BATCH(96, 8, 2); else ADORYM_BATCH(96, 8, 4);
+  } else {
+    if (c.k == 1) ADORYM_BATCH(128, 8, 1);
+    else if (c.k == 2) ADORYM_BATCH(128, 8, 2);
+    else if (c.k == 4) ADORYM_BATCH(128, 8, 4);
+    else ADORYM_BATCH(128, 8, 8);
+  }
+#undef ADORYM_BATCH
+}
+
 }  // namespace
 
 extern "C" {
 
-int adorym_supports_n(int32_t n) { return n == 64 || n == 128; }
+int adorym_supports_n(int32_t n) { return n == 64 || n == 96 || n == 128; }
 
 adorym_status adorym_create(adorym_ctx** out, int device, void* stream) {
   if (!out) return ADORYM_EINVAL;
@@ -132,12 +249,107 @@ adorym_status adorym_sync_error(adorym_ctx* ctx) {
 
 const char* adorym_last_error_message(adorym_ctx* ctx) { return ctx ? ctx->msg : "no context"; }
 
+adorym_status adorym_plan_create(adorym_ctx* ctx, const adorym_job* jobs, int32_t n_jobs, adorym_plan** out) {
+  if (!ctx || !jobs || !out || n_jobs < 1) return ADORYM_EINVAL;
+  *out = nullptr;
+  adorym_plan* plan = new adorym_plan();
+  plan->device = ctx->device;
+  plan->jobs.assign(jobs, jobs + n_jobs);
+  // validate every job; the plan's kernels are the loss+gradient path
+  for (int i = 0; i < n_jobs; ++i) {
+    const adorym_job& j = jobs[i];
+    adorym_status st = check_geom(ctx, &j.g, j.batch);
+    if (st == ADORYM_OK && (!j.obj_a || !j.obj_b || !j.probe || !j.corner || !j.shift || !j.i_meas || !j.workspace ||
+                            !j.loss))
+      st = set_err(ctx, ADORYM_EINVAL, "NULL array argument in a job");
+    if (st == ADORYM_OK && ((j.g_a == nullptr) != (j.g_b == nullptr)))
+      st = set_err(ctx, ADORYM_EINVAL, "g_a and g_b must both be given");
+    if (st == ADORYM_OK && j.ws_bytes < adorym_workspace_size(&j.g, j.batch))
+      st = set_err(ctx, ADORYM_ENOMEM, "job workspace too small");
+    if (st != ADORYM_OK) { delete plan; return st; }
+  }
+  // classes: one per (probe size, object representation)
+  struct Key { int n, repr; };
+  std::vector<Key> keys;
+  for (const adorym_job& j : plan->jobs) {
+    bool seen = false;
+    for (const Key& k : keys) seen |= (k.n == j.g.n && k.repr == j.g.obj_repr);
+    if (!seen) keys.push_back({j.g.n, j.g.obj_repr});
+  }
+  plan->params.resize(n_jobs);
+  for (const Key& key : keys) {
+    PlanClass c{};
+    c.n = key.n; c.repr = key.repr;
+    c.l = key.n == 64 ? 4 : 8;
+    const int forced = key.n == 64 ? ctx->split64 : (key.n == 96 ? ctx->split96 : ctx->split128);
+    c.k = forced > 0 ? forced : (key.n == 128 ? 4 : 2);
+    if (key.n != 128 && c.k > 4) c.k = 4;
+    // one workgroup per CU: 256 / K groups, a multiple of 8 (one per XCD slot)
+    c.groups = std::max(8, (256 / c.k) / 8 * 8);
+    std::vector<std::pair<double, int2>> work;
+    for (int i = 0; i < n_jobs; ++i) {
+      const adorym_job& j = plan->jobs[i];
+      if (j.g.n != key.n || j.g.obj_repr != key.repr) continue;
+      switch (key.n) {
+        case 64: plan->params[i] = params_for<64, 4>(ctx, j, c.k); break;
+        case 96: plan->params[i] = params_for<96, 8>(ctx, j, c.k); break;
+        default: plan->params[i] = params_for<128, 8>(ctx, j, c.k); break;
+      }
+      for (int b = 0; b < j.batch; ++b) work.push_back({(double)j.g.n_slices * j.g.n * j.g.n, make_int2(i, b)});
+    }
+    std::stable_sort(work.begin(), work.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    std::vector<int2> items;
+    for (const auto& w : work) items.push_back(w.second);
+    c.n_items = (int)items.size();
+    const int n_state = 1 + 2 * c.groups + c.groups * c.k;
+    bool ok = hipMalloc(&c.items, items.size() * sizeof(int2)) == hipSuccess &&
+              hipMalloc(&c.state, n_state * sizeof(int)) == hipSuccess &&
+              hipMalloc(&c.xbuf, (size_t)c.groups * 4 * key.n * key.n * sizeof(float2)) == hipSuccess &&
+              hipMemcpy(c.items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess;
+    plan->classes.push_back(c);
+    if (!ok) { adorym_plan_destroy(plan); return set_err(ctx, ADORYM_EDEVICE, "plan allocation failed"); }
+  }
+  if (hipMalloc(&plan->d_params, n_jobs * sizeof(MsParams)) != hipSuccess ||
+      hipMemcpy(plan->d_params, plan->params.data(), n_jobs * sizeof(MsParams), hipMemcpyHostToDevice) != hipSuccess) {
+    adorym_plan_destroy(plan);
+    return set_err(ctx, ADORYM_EDEVICE, "plan allocation failed");
+  }
+  *out = plan;
+  return ADORYM_OK;
+}
+
+adorym_status adorym_plan_run(adorym_ctx* ctx, adorym_plan* plan) {
+  if (!ctx || !plan) return ADORYM_EINVAL;
+  hipStream_t st = ctx->stream;
+  for (size_t i = 0; i < plan->jobs.size(); ++i) job_prologue(plan->params[i], plan->jobs[i], st);
+  const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
+  if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
+  for (const PlanClass& c : plan->classes) class_launch(c, plan->d_params, ctx->d_err, st);
+  if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
+  for (size_t i = 0; i < plan->jobs.size(); ++i) job_epilogue(plan->params[i], plan->jobs[i], st);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ADORYM_OK : set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
+}
+
+adorym_status adorym_plan_destroy(adorym_plan* plan) {
+  if (!plan) return ADORYM_EINVAL;
+  for (PlanClass& c : plan->classes) {
+    if (c.items) (void)hipFree(c.items);
+    if (c.state) (void)hipFree(c.state);
+    if (c.xbuf) (void)hipFree(c.xbuf);
+  }
+  if (plan->d_params) (void)hipFree(plan->d_params);
+  delete plan;
+  return ADORYM_OK;
+}
+
 adorym_status adorym_set_split(adorym_ctx* ctx, int32_t n, int32_t k) {
   if (!ctx) return ADORYM_EINVAL;
-  const bool ok = k == 0 || (n == 64 && (k == 1 || k == 2 || k == 4)) ||
+  const bool ok = k == 0 || ((n == 64 || n == 96) && (k == 1 || k == 2 || k == 4)) ||
                   (n == 128 && (k == 1 || k == 2 || k == 4 || k == 8));
   if (!ok) return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size / split");
   if (n == 64) ctx->split64 = k;
+  else if (n == 96) ctx->split96 = k;
   else ctx->split128 = k;
   return ADORYM_OK;
 }

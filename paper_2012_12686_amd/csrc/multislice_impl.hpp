@@ -58,6 +58,8 @@ struct MsParams {
   int* xcc;                // [B][K] XCD ids of each group's members (K > 1)
   int* err;
   int B, S, Ly, Lx, ckpt_every, nslots;
+  int loss;                // ADORYM_LOSS_*
+  int ksplit;              // workgroups per position of the launch that fills the partials
   float kdz;               // k * dz
   double chirp;            // lambda dz / dx^2
   double eps;
@@ -320,24 +322,17 @@ __device__ __forceinline__ void group_of_block(int& b, int& part) {
   part = slot % C::K;
 }
 
-template <class C, int REPR, int LOSSK, bool LOSS>
-__global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
-  __shared__ MsShared<C> sh;
-  int b, part;
-  group_of_block<C>(b, part);
-  if (b >= P.B) return;                       // padding of the XCD-aware grid
-  Work<C> wk(threadIdx.x, b, part);
+// Everything one workgroup does for its part of one position.  wk.b, wk.part
+// and the exchange state wk.x are set by the caller.
+template <class C, int REPR, bool LOSS>
+__device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>& sh, Work<C>& wk) {
+  const int b = wk.b, part = wk.part;
   const Lane<C>& ln = wk.ln;
   constexpr int N = C::N;
   constexpr int NN = N * N;
   wk.cy = P.corner[2 * b];
   wk.cx = P.corner[2 * b + 1];
   const float sy = P.shift[2 * b], sx = P.shift[2 * b + 1];
-  wk.x.buf = P.xbuf + (size_t)b * 4 * NN;
-  wk.x.counter = P.counters + b;
-  wk.x.err = P.err;
-  wk.x.phase = 0;
-  wk.x.local = false;
 
   // TakeObjectChunk: the chunk must lie inside the object.
   if (wk.cy < 0 || wk.cx < 0 || wk.cy + N > P.Ly || wk.cx + N > P.Lx) {
@@ -360,7 +355,6 @@ __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
 
   setup_tables<C>(sh, ln, P.chirp, sy, sx);
   const ChunkOffsets o = chunk_offsets<C>(ln, wk.cy, wk.cx, P.Ly, P.Lx);
-  if constexpr (C::K > 1) exchange_init<C::K>(wk.x, P.xcc + b * C::K, part);
 
   float2 v[C::R];
   float ca[C::R], cb[C::R];
@@ -399,7 +393,7 @@ __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
     if (LOSS) {
       const float imv = bload(rim, det, 0);
       float term, dldi;
-      if constexpr (LOSSK == ADORYM_LOSS_GAUSSIAN) {
+      if (P.loss == ADORYM_LOSS_GAUSSIAN) {
         const float sp = sqrtf(ip + eps), sm = sqrtf(imv + eps);
         term = (sp - sm) * (sp - sm);
         dldi = (1.0f - sm / sp) * inv_n;
@@ -468,6 +462,67 @@ __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
     const double two_pi = 6.283185307179586476925286766559;
     P.gs_part[2 * (b * C::K + part)] = two_pi * ty;
     P.gs_part[2 * (b * C::K + part) + 1] = two_pi * tx;
+  }
+}
+
+// One group of K workgroups per position of a single job.
+template <class C, int REPR, bool LOSS>
+__global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
+  __shared__ MsShared<C> sh;
+  int b, part;
+  group_of_block<C>(b, part);
+  if (b >= P.B) return;                       // padding of the XCD-aware grid
+  Work<C> wk(threadIdx.x, b, part);
+  wk.x.buf = P.xbuf + (size_t)b * 4 * C::N * C::N;
+  wk.x.counter = P.counters + b;
+  wk.x.err = P.err;
+  wk.x.phase = 0;
+  wk.x.local = false;
+  const int cy = P.corner[2 * b], cx = P.corner[2 * b + 1];
+  const bool inside = cy >= 0 && cx >= 0 && cy + C::N <= P.Ly && cx + C::N <= P.Lx;
+  if (C::K > 1 && inside) exchange_init<C::K>(wk.x, P.xcc + b * C::K, part);
+  process_position<C, REPR, LOSS>(P, sh, wk);
+}
+
+// Persistent multi-job kernel: groups of K workgroups take (job, position)
+// items from a device queue until it is empty.  Every member of a group sees
+// the same ticket (member 0 draws it and publishes it behind the group
+// barrier), so all of them leave the loop together.
+template <class C, int REPR>
+__global__ void __launch_bounds__(C::THREADS) multislice_batched_kernel(const MsParams* __restrict__ jobs,
+                                                                        const int2* __restrict__ items,
+                                                                        int n_items, int* ticket, int* mailbox,
+                                                                        int* counters, int* xcc, float2* xbuf,
+                                                                        int* err) {
+  __shared__ MsShared<C> sh;
+  __shared__ int sh_ticket;
+  int g, part;
+  group_of_block<C>(g, part);
+  Work<C> wk(threadIdx.x, 0, part);
+  wk.x.buf = xbuf + (size_t)g * 4 * C::N * C::N;
+  wk.x.counter = counters + g;
+  wk.x.err = err;
+  wk.x.phase = 0;
+  wk.x.local = false;
+  if (C::K > 1) exchange_init<C::K>(wk.x, xcc + g * C::K, part);
+  for (;;) {
+    int t;
+    if constexpr (C::K == 1) {
+      __syncthreads();
+      if (threadIdx.x == 0) sh_ticket = atomicAdd(ticket, 1);
+      __syncthreads();
+      t = sh_ticket;
+    } else {
+      if (threadIdx.x == 0 && part == 0)
+        __hip_atomic_store(mailbox + g, atomicAdd(ticket, 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ++wk.x.phase;
+      group_barrier(wk.x.counter, C::K * wk.x.phase, wk.x.err);
+      t = __hip_atomic_load(mailbox + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (t >= n_items) break;
+    const int2 it = items[t];
+    wk.b = it.y;
+    process_position<C, REPR, true>(jobs[it.x], sh, wk);
   }
 }
 
@@ -626,20 +681,73 @@ inline void fill(hipStream_t st, float* p, size_t n, float v) {
 }
 
 template <class C, bool LOSS>
-void launch_ms(const MsParams& P, int repr, int lossk, hipStream_t st) {
+void launch_ms(const MsParams& P, int repr, hipStream_t st) {
   // XCD-aware grid: ceil(B/8) groups per XCD, K slots per group
   const dim3 grid(((P.B + 7) / 8) * 8 * C::K), block(C::THREADS);
-  if (repr == ADORYM_OBJ_DELTA_BETA) {
-    if (lossk == ADORYM_LOSS_GAUSSIAN)
-      hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, ADORYM_LOSS_GAUSSIAN, LOSS>), grid, block, 0, st, P);
-    else
-      hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, ADORYM_LOSS_POISSON, LOSS>), grid, block, 0, st, P);
-  } else {
-    if (lossk == ADORYM_LOSS_GAUSSIAN)
-      hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, ADORYM_LOSS_GAUSSIAN, LOSS>), grid, block, 0, st, P);
-    else
-      hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, ADORYM_LOSS_POISSON, LOSS>), grid, block, 0, st, P);
+  if (repr == ADORYM_OBJ_DELTA_BETA)
+    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, LOSS>), grid, block, 0, st, P);
+  else
+    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, LOSS>), grid, block, 0, st, P);
+}
+
+// Kernel parameters of one job; `ws` is its workspace (adorym_workspace_size).
+template <int N, int L, int K>
+MsParams make_params(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b, int batch,
+                     const int32_t* corner, const float* shift, const float* i_meas, void* ws, bool with_probe_grad,
+                     float* g_a, float* g_b, float* intensity) {
+  const WsLayout w = ws_layout(g, batch);
+  char* base = static_cast<char*>(ws);
+  MsParams P{};
+  P.a = a; P.b = b;
+  P.q = reinterpret_cast<const float2*>(base + w.q);
+  P.corner = corner; P.shift = shift; P.i_meas = i_meas; P.intensity = intensity;
+  P.g_a = g_a; P.g_b = g_b;
+  P.ckpt = reinterpret_cast<float2*>(base + w.ckpt);
+  P.gacc = with_probe_grad ? reinterpret_cast<float2*>(base + w.gacc) : nullptr;
+  P.loss_part = reinterpret_cast<double*>(base + w.loss_part);
+  P.gs_part = reinterpret_cast<double*>(base + w.gs_part);
+  P.xbuf = reinterpret_cast<float2*>(base + w.xbuf);
+  P.counters = reinterpret_cast<int*>(base + w.counters);
+  P.xcc = reinterpret_cast<int*>(base + w.xcc);
+  P.err = ctx->d_err;
+  P.B = batch; P.S = g->n_slices; P.Ly = g->obj_ny; P.Lx = g->obj_nx;
+  P.ckpt_every = g->ckpt_every; P.nslots = w.nslots;
+  P.loss = g->loss;
+  P.kdz = (float)(2.0 * M_PI / g->wavelength_m * g->slice_dz_m);
+  P.chirp = g->wavelength_m * g->slice_dz_m / (g->pixel_m * g->pixel_m);
+  P.eps = g->eps;
+  P.inv_n = 1.0 / ((double)batch * g->n * g->n);
+  return P;
+}
+
+// Per-job work before the multislice kernel: probe spectrum (also clears the
+// job's barrier counters) and, unless accumulating, zeroed object gradients.
+template <int N, int L>
+void launch_prologue(const MsParams& P, const float* probe, const adorym_geom* g, hipStream_t st) {
+  using C1 = TileCfg<N, L, 1>;
+  hipLaunchKernelGGL((probe_spectrum_kernel<C1>), dim3(1), dim3(C1::THREADS), 0, st,
+                     reinterpret_cast<const float2*>(probe), const_cast<float2*>(P.q), P.counters, P.B);
+  const size_t nobj = (size_t)g->n_slices * g->obj_ny * g->obj_nx;
+  if (!(g->flags & ADORYM_ACCUMULATE_GRADS)) {
+    if (P.g_a) fill(st, P.g_a, nobj, 0.f);
+    if (P.g_b) fill(st, P.g_b, nobj, 0.f);
   }
+}
+
+// Per-job work after it: loss, shift gradients, probe gradient.
+template <int N, int L>
+void launch_epilogue(const MsParams& P, void* ws, const adorym_geom* g, double* loss, float* g_probe,
+                     float* g_shift, hipStream_t st) {
+  using C1 = TileCfg<N, L, 1>;
+  const WsLayout w = ws_layout(g, P.B);
+  float2* gsum = reinterpret_cast<float2*>(static_cast<char*>(ws) + w.gsum);
+  const int accumulate = (g->flags & ADORYM_ACCUMULATE_GRADS) ? 1 : 0;
+  const int nn = N * N;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((nn + 255) / 256), dim3(256), 0, st, P.gacc, P.B, nn, gsum,
+                     P.loss_part, P.gs_part, P.ksplit, loss, g_shift, accumulate);
+  if (g_probe)
+    hipLaunchKernelGGL((probe_grad_kernel<C1>), dim3(1), dim3(C1::THREADS), 0, st, gsum,
+                       reinterpret_cast<float2*>(g_probe), accumulate);
 }
 
 // One probe size N with lanes-per-line L; C1 is the single-workgroup tile.
@@ -649,63 +757,52 @@ adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const f
                   double* loss, float* g_a, float* g_b, float* g_probe, float* g_shift, float* intensity,
                   bool with_loss) {
   using C = TileCfg<N, L, K>;
-  using C1 = TileCfg<N, L, 1>;
-  const WsLayout w = ws_layout(g, batch);
-  char* base = static_cast<char*>(ws);
-  MsParams P{};
-  P.a = a; P.b = b;
-  P.q = reinterpret_cast<const float2*>(base + w.q);
-  P.corner = corner; P.shift = shift; P.i_meas = i_meas; P.intensity = intensity;
-  P.g_a = g_a; P.g_b = g_b;
-  P.ckpt = reinterpret_cast<float2*>(base + w.ckpt);
-  P.gacc = g_probe ? reinterpret_cast<float2*>(base + w.gacc) : nullptr;
-  P.loss_part = reinterpret_cast<double*>(base + w.loss_part);
-  P.gs_part = reinterpret_cast<double*>(base + w.gs_part);
-  P.xbuf = reinterpret_cast<float2*>(base + w.xbuf);
-  P.counters = reinterpret_cast<int*>(base + w.counters);
-  P.xcc = reinterpret_cast<int*>(base + w.xcc);
-  P.err = ctx->d_err;
-  P.B = batch; P.S = g->n_slices; P.Ly = g->obj_ny; P.Lx = g->obj_nx;
-  P.ckpt_every = g->ckpt_every; P.nslots = w.nslots;
-  P.kdz = (float)(2.0 * M_PI / g->wavelength_m * g->slice_dz_m);
-  P.chirp = g->wavelength_m * g->slice_dz_m / (g->pixel_m * g->pixel_m);
-  P.eps = g->eps;
-  P.inv_n = 1.0 / ((double)batch * g->n * g->n);
-  const int accumulate = (g->flags & ADORYM_ACCUMULATE_GRADS) ? 1 : 0;
-
+  MsParams P = make_params<N, L, K>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
+                                    with_loss ? g_a : nullptr, with_loss ? g_b : nullptr, intensity);
+  P.ksplit = K;
   hipStream_t st = ctx->stream;
   const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
-  hipLaunchKernelGGL((probe_spectrum_kernel<C1>), dim3(1), dim3(C1::THREADS), 0, st,
-                     reinterpret_cast<const float2*>(probe), const_cast<float2*>(P.q), P.counters, batch);
-  if (with_loss) {
-    const size_t nobj = (size_t)g->n_slices * g->obj_ny * g->obj_nx;
-    if (!accumulate) {
-      if (g_a) fill(st, g_a, nobj, 0.f);
-      if (g_b) fill(st, g_b, nobj, 0.f);
-    }
-    if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
-    launch_ms<C, true>(P, g->obj_repr, g->loss, st);
-    if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
-    const int nn = N * N;
-    float2* gsum = reinterpret_cast<float2*>(base + w.gsum);
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((nn + 255) / 256), dim3(256), 0, st, P.gacc, batch, nn, gsum,
-                       P.loss_part, P.gs_part, C::K, loss, g_shift, accumulate);
-    if (g_probe)
-      hipLaunchKernelGGL((probe_grad_kernel<C1>), dim3(1), dim3(C1::THREADS), 0, st, gsum,
-                         reinterpret_cast<float2*>(g_probe), accumulate);
-  } else {
-    if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
-    launch_ms<C, false>(P, g->obj_repr, g->loss, st);
-    if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
-  }
+  launch_prologue<N, L>(P, probe, g, st);
+  if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
+  if (with_loss) launch_ms<C, true>(P, g->obj_repr, st);
+  else launch_ms<C, false>(P, g->obj_repr, st);
+  if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
+  if (with_loss) launch_epilogue<N, L>(P, ws, g, loss, g_probe, g_shift, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
   return ADORYM_OK;
 }
 
+// The persistent multi-job kernel of one probe-size class (device tables
+// prepared by the plan).
+template <int N, int L, int K>
+void launch_batched(const MsParams* jobs, const int2* items, int n_items, int* ticket, int* mailbox, int* counters,
+                    int* xcc, float2* xbuf, int* err, int groups, int repr, hipStream_t st) {
+  using C = TileCfg<N, L, K>;
+  const dim3 grid(groups * K), block(C::THREADS);
+  if (repr == ADORYM_OBJ_DELTA_BETA)
+    hipLaunchKernelGGL((multislice_batched_kernel<C, ADORYM_OBJ_DELTA_BETA>), grid, block, 0, st, jobs, items,
+                       n_items, ticket, mailbox, counters, xcc, xbuf, err);
+  else
+    hipLaunchKernelGGL((multislice_batched_kernel<C, ADORYM_OBJ_REAL_IMAG>), grid, block, 0, st, jobs, items,
+                       n_items, ticket, mailbox, counters, xcc, xbuf, err);
+}
+
 }  // namespace adorym_ms
 
 // Explicit instantiation helpers
+#define ADORYM_BATCHED_SIGNATURE(N_, L_, K_) \
+  void adorym_ms::launch_batched<N_, L_, K_>(const adorym_ms::MsParams*, const int2*, int, int*, int*, int*, int*, \
+                                              float2*, int*, int, int, hipStream_t)
+#define ADORYM_PROLOGUE_SIGNATURE(N_, L_) \
+  void adorym_ms::launch_prologue<N_, L_>(const adorym_ms::MsParams&, const float*, const adorym_geom*, hipStream_t)
+#define ADORYM_EPILOGUE_SIGNATURE(N_, L_) \
+  void adorym_ms::launch_epilogue<N_, L_>(const adorym_ms::MsParams&, void*, const adorym_geom*, double*, float*, \
+                                          float*, hipStream_t)
+#define ADORYM_PARAMS_SIGNATURE(N_, L_, K_) \
+  adorym_ms::MsParams adorym_ms::make_params<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, \
+                                                        const float*, int, const int32_t*, const float*, \
+                                                        const float*, void*, bool, float*, float*, float*)
 #define ADORYM_RUN_SIGNATURE(N_, L_, K_) \
   adorym_status adorym_ms::run<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, const float*, const float*, \
                                            const int32_t*, const float*, int, const float*, void*, double*, float*, \

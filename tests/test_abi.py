@@ -45,6 +45,19 @@ def test_geom_struct_layout_matches_c(tmp_path):
     assert got == [ctypes.sizeof(G), G.wavelength_m.offset, G.loss.offset, G.eps.offset, G.flags.offset]
 
 
+def test_job_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "probe.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "adorym.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(adorym_job),'
+                   ' offsetof(adorym_job, obj_a), offsetof(adorym_job, batch),'
+                   ' offsetof(adorym_job, i_meas), offsetof(adorym_job, ws_bytes)); return 0;}\n')
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    J = _lib.Job
+    assert got == [ctypes.sizeof(J), J.obj_a.offset, J.batch.offset, J.i_meas.offset, J.ws_bytes.offset]
+
+
 def _geom(**kw):
     base = dict(n=128, n_slices=64, obj_ny=256, obj_nx=256, wavelength_m=1.24e-10, pixel_m=1e-8,
                 slice_dz_m=1e-8, loss=0, obj_repr=0, ckpt_every=16, eps=1e-6, flags=0)
@@ -69,7 +82,7 @@ def test_workspace_size_formula():
 
 def test_supported_sizes():
     lib = _lib.load()
-    assert lib.adorym_supports_n(64) == 1 and lib.adorym_supports_n(128) == 1
+    assert lib.adorym_supports_n(64) == 1 and lib.adorym_supports_n(96) == 1 and lib.adorym_supports_n(128) == 1
     assert lib.adorym_supports_n(100) == 0 and lib.adorym_supports_n(0) == 0
 
 

@@ -85,6 +85,7 @@ def check_grads(got, ref, case):
     (128, 1, 160, 2, "delta_beta"),
     (128, 20, 150, 3, "delta_beta"),
     (128, 5, 140, 2, "real_imag"),
+    (96, 9, 120, 3, "delta_beta"),
 ])
 def test_forward_matches_oracle(ctx, n, s, lat, npos, repr_):
     sc = synth.small_case(seed=100 + n + s, n=n, n_slices=s, lateral=lat, n_pos=npos, obj_repr=repr_,
@@ -107,6 +108,7 @@ def test_forward_matches_oracle(ctx, n, s, lat, npos, repr_):
     (64, 3, 90, 3, "real_imag", "gaussian", 16),
     (128, 33, 150, 3, "delta_beta", "gaussian", 16),
     (128, 2, 140, 2, "delta_beta", "poisson", 1),
+    (96, 17, 130, 3, "delta_beta", "gaussian", 16),
 ])
 def test_loss_grad_matches_oracle(ctx, n, s, lat, npos, repr_, loss, ckpt):
     sc = synth.small_case(seed=200 + n + s, n=n, n_slices=s, lateral=lat, n_pos=npos, obj_repr=repr_,
@@ -118,7 +120,8 @@ def test_loss_grad_matches_oracle(ctx, n, s, lat, npos, repr_, loss, ckpt):
     check_grads(got, ref, case)
 
 
-@pytest.mark.parametrize("n,k", [(64, 1), (64, 2), (64, 4), (128, 1), (128, 2), (128, 4), (128, 8)])
+@pytest.mark.parametrize("n,k", [(64, 1), (64, 2), (64, 4), (96, 1), (96, 2), (96, 4),
+                                 (128, 1), (128, 2), (128, 4), (128, 8)])
 def test_every_split_matches_oracle(ctx, n, k):
     """Fields split over k cooperating workgroups give the same results."""
     sc = synth.small_case(seed=300 + n + k, n=n, n_slices=7, lateral=n + 30, n_pos=3, strength=30.0)
@@ -201,3 +204,30 @@ def test_config2_first_minibatch(ctx):
     print("c2 intensity rel-L2", err_i)
     assert err_i <= TOL_I
     check_grads(got, case.oracle_loss_grad(), case)
+
+
+def test_batched_plan_equals_individual_calls(ctx):
+    """Jobs of three probe sizes, two losses and uneven depths in one plan give
+    each job's own loss_grad results (up to the order of float atomics)."""
+    import torch
+    from paper_2012_12686_amd import Job
+    specs = [(64, 3, 90, 5, "gaussian"), (96, 11, 120, 4, "poisson"), (128, 7, 150, 3, "gaussian"),
+             (64, 20, 100, 6, "poisson"), (128, 1, 140, 2, "poisson")]
+    jobs, singles = [], []
+    for i, (n, s, lat, npos, loss) in enumerate(specs):
+        sc = synth.small_case(seed=500 + i, n=n, n_slices=s, lateral=lat, n_pos=npos, loss=loss, strength=30.0)
+        case = Case(sc, poisson_seed=9 if loss == "poisson" else None)
+        inp, im = case.torch_inputs()
+        singles.append({k: v.cpu().numpy() for k, v in ctx.loss_grad(_geom(case), **inp, i_meas=im).items()})
+        jobs.append(Job(geom=_geom(case), i_meas=im, **inp))
+    plan = ctx.plan(jobs)
+    for _ in range(2):                       # twice: state must reset between runs
+        plan.run()
+    torch.cuda.synchronize()
+    ctx.sync_error()
+    for j, ref in zip(jobs, singles):
+        got = {k: v.cpu().numpy() for k, v in j.out.items()}
+        assert abs(float(got["loss"]) - float(ref["loss"])) <= 1e-12 * abs(float(ref["loss"])) + 1e-300
+        for k in ("g_a", "g_b", "g_probe", "g_shift"):
+            assert rel_l2(got[k], ref[k]) < 1e-5, k
+    plan.close()
