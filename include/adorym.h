@@ -180,7 +180,8 @@ const char* adorym_last_error_message(adorym_ctx* ctx);
  * k > 1 splits its lines over k workgroups that exchange through L2.
  * k = 0 restores the automatic choice (enough workgroups to cover the
  * CUs).  Supported: n = 64 and n = 96 with k in {1, 2, 4}; n = 128 with
- * k in {1, 2, 4, 8}; else ADORYM_EUNSUPPORTED.  Results do not depend on k
+ * k in {1, 2, 4, 8}; n = 192 with k in {2, 4, 8} (its field does not fit one
+ * workgroup); else ADORYM_EUNSUPPORTED.  Results do not depend on k
  * beyond float rounding of the gradient atomics. */
 adorym_status adorym_set_split(adorym_ctx* ctx, int32_t n, int32_t k);
 

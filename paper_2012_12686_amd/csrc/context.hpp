@@ -13,6 +13,6 @@ struct adorym_ctx {
   std::vector<hipEvent_t> ev;   // start/stop pairs
   int ev_used = 0;
   bool prof = false;
-  // workgroups per position (0 = automatic) for N = 64, 96 and 128
-  int split64 = 0, split96 = 0, split128 = 0;
+  // workgroups per position (0 = automatic) for N = 64, 96, 128 and 192
+  int split64 = 0, split96 = 0, split128 = 0, split192 = 0;
 };

@@ -3,4 +3,3 @@
 
 template ADORYM_RUN_SIGNATURE(128, 8, 4);
 template ADORYM_BATCHED_SIGNATURE(128, 8, 4);
-template ADORYM_PARAMS_SIGNATURE(128, 8, 4);

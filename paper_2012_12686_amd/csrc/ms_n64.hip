@@ -3,12 +3,10 @@
 
 template ADORYM_RUN_SIGNATURE(64, 4, 1);
 template ADORYM_BATCHED_SIGNATURE(64, 4, 1);
-template ADORYM_PARAMS_SIGNATURE(64, 4, 1);
 template ADORYM_RUN_SIGNATURE(64, 4, 2);
 template ADORYM_BATCHED_SIGNATURE(64, 4, 2);
-template ADORYM_PARAMS_SIGNATURE(64, 4, 2);
 template ADORYM_RUN_SIGNATURE(64, 4, 4);
 template ADORYM_BATCHED_SIGNATURE(64, 4, 4);
-template ADORYM_PARAMS_SIGNATURE(64, 4, 4);
+template ADORYM_PARAMS_SIGNATURE(64, 4);
 template ADORYM_PROLOGUE_SIGNATURE(64, 4);
 template ADORYM_EPILOGUE_SIGNATURE(64, 4);

@@ -7,48 +7,62 @@ using namespace adorym_ms;
 
 extern template ADORYM_RUN_SIGNATURE(64, 4, 1);
 extern template ADORYM_BATCHED_SIGNATURE(64, 4, 1);
-extern template ADORYM_PARAMS_SIGNATURE(64, 4, 1);
 extern template ADORYM_RUN_SIGNATURE(64, 4, 2);
 extern template ADORYM_BATCHED_SIGNATURE(64, 4, 2);
-extern template ADORYM_PARAMS_SIGNATURE(64, 4, 2);
 extern template ADORYM_RUN_SIGNATURE(64, 4, 4);
 extern template ADORYM_BATCHED_SIGNATURE(64, 4, 4);
-extern template ADORYM_PARAMS_SIGNATURE(64, 4, 4);
 extern template ADORYM_RUN_SIGNATURE(96, 8, 1);
 extern template ADORYM_BATCHED_SIGNATURE(96, 8, 1);
-extern template ADORYM_PARAMS_SIGNATURE(96, 8, 1);
 extern template ADORYM_RUN_SIGNATURE(96, 8, 2);
 extern template ADORYM_BATCHED_SIGNATURE(96, 8, 2);
-extern template ADORYM_PARAMS_SIGNATURE(96, 8, 2);
 extern template ADORYM_RUN_SIGNATURE(96, 8, 4);
 extern template ADORYM_BATCHED_SIGNATURE(96, 8, 4);
-extern template ADORYM_PARAMS_SIGNATURE(96, 8, 4);
 extern template ADORYM_RUN_SIGNATURE(128, 8, 1);
 extern template ADORYM_BATCHED_SIGNATURE(128, 8, 1);
-extern template ADORYM_PARAMS_SIGNATURE(128, 8, 1);
 extern template ADORYM_RUN_SIGNATURE(128, 8, 2);
 extern template ADORYM_BATCHED_SIGNATURE(128, 8, 2);
-extern template ADORYM_PARAMS_SIGNATURE(128, 8, 2);
 extern template ADORYM_RUN_SIGNATURE(128, 8, 4);
 extern template ADORYM_BATCHED_SIGNATURE(128, 8, 4);
-extern template ADORYM_PARAMS_SIGNATURE(128, 8, 4);
 extern template ADORYM_RUN_SIGNATURE(128, 8, 8);
 extern template ADORYM_BATCHED_SIGNATURE(128, 8, 8);
-extern template ADORYM_PARAMS_SIGNATURE(128, 8, 8);
+extern template ADORYM_RUN_SIGNATURE(192, 8, 2);
+extern template ADORYM_BATCHED_SIGNATURE(192, 8, 2);
+extern template ADORYM_RUN_SIGNATURE(192, 8, 4);
+extern template ADORYM_BATCHED_SIGNATURE(192, 8, 4);
+extern template ADORYM_RUN_SIGNATURE(192, 8, 8);
+extern template ADORYM_BATCHED_SIGNATURE(192, 8, 8);
+extern template ADORYM_PARAMS_SIGNATURE(64, 4);
 extern template ADORYM_PROLOGUE_SIGNATURE(64, 4);
 extern template ADORYM_EPILOGUE_SIGNATURE(64, 4);
+extern template ADORYM_PARAMS_SIGNATURE(96, 8);
 extern template ADORYM_PROLOGUE_SIGNATURE(96, 8);
 extern template ADORYM_EPILOGUE_SIGNATURE(96, 8);
+extern template ADORYM_PARAMS_SIGNATURE(128, 8);
 extern template ADORYM_PROLOGUE_SIGNATURE(128, 8);
 extern template ADORYM_EPILOGUE_SIGNATURE(128, 8);
+extern template ADORYM_PARAMS_SIGNATURE(192, 8);
+extern template ADORYM_PROLOGUE_SIGNATURE(192, 8);
+extern template ADORYM_EPILOGUE_SIGNATURE(192, 8);
 
 namespace {
+
+int split_of(const adorym_ctx* ctx, int n) {
+  switch (n) {
+    case 64: return ctx->split64;
+    case 96: return ctx->split96;
+    case 128: return ctx->split128;
+    case 192: return ctx->split192;
+    default: return 0;
+  }
+}
 
 // Workgroups per position: the context's choice for this N if one was set
 // (adorym_set_split, e.g. by an autotuner), else enough to cover the CUs.
 int pick_split(const adorym_ctx* ctx, int n, int batch) {
-  const int forced = n == 64 ? ctx->split64 : (n == 96 ? ctx->split96 : (n == 128 ? ctx->split128 : 0));
+  const int forced = split_of(ctx, n);
   if (forced > 0) return forced;
+  // N = 192: eight workgroups of 3 waves (the only split without spills)
+  if (n == 192) return 8;
   // largest power-of-two split that keeps the grid within one workgroup per CU
   const int kmax = n == 128 ? 8 : 4;
   int k = 1;
@@ -83,6 +97,12 @@ adorym_status dispatch(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
       case 4: ADORYM_RUN(128, 8, 4);
       case 8: ADORYM_RUN(128, 8, 8);
     }
+  } else if (g->n == 192) {
+    switch (k) {
+      case 2: ADORYM_RUN(192, 8, 2);
+      case 4: ADORYM_RUN(192, 8, 4);
+      case 8: ADORYM_RUN(192, 8, 8);
+    }
   }
 #undef ADORYM_RUN
   return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size / split");
@@ -114,15 +134,8 @@ namespace {
 
 template <int N, int L>
 MsParams params_for(adorym_ctx* ctx, const adorym_job& j, int k) {
-  MsParams P;
-  switch (k) {
-    case 1: P = make_params<N, L, 1>(ctx, &j.g, j.obj_a, j.obj_b, j.batch, j.corner, j.shift, j.i_meas,
-                                     j.workspace, j.g_probe != nullptr, j.g_a, j.g_b, nullptr); break;
-    case 2: P = make_params<N, L, 2>(ctx, &j.g, j.obj_a, j.obj_b, j.batch, j.corner, j.shift, j.i_meas,
-                                     j.workspace, j.g_probe != nullptr, j.g_a, j.g_b, nullptr); break;
-    default: P = make_params<N, L, 4>(ctx, &j.g, j.obj_a, j.obj_b, j.batch, j.corner, j.shift, j.i_meas,
-                                      j.workspace, j.g_probe != nullptr, j.g_a, j.g_b, nullptr); break;
-  }
+  MsParams P = make_params<N, L>(ctx, &j.g, j.obj_a, j.obj_b, j.batch, j.corner, j.shift, j.i_meas, j.workspace,
+                                 j.g_probe != nullptr, j.g_a, j.g_b, nullptr);
   P.ksplit = k;
   return P;
 }
@@ -131,7 +144,8 @@ void job_prologue(const MsParams& P, const adorym_job& j, hipStream_t st) {
   switch (j.g.n) {
     case 64: launch_prologue<64, 4>(P, j.probe, &j.g, st); break;
     case 96: launch_prologue<96, 8>(P, j.probe, &j.g, st); break;
-    default: launch_prologue<128, 8>(P, j.probe, &j.g, st); break;
+    case 128: launch_prologue<128, 8>(P, j.probe, &j.g, st); break;
+    default: launch_prologue<192, 8>(P, j.probe, &j.g, st); break;
   }
 }
 
@@ -139,12 +153,9 @@ void job_epilogue(const MsParams& P, const adorym_job& j, hipStream_t st) {
   switch (j.g.n) {
     case 64: launch_epilogue<64, 4>(P, j.workspace, &j.g, j.loss, j.g_probe, j.g_shift, st); break;
     case 96: launch_epilogue<96, 8>(P, j.workspace, &j.g, j.loss, j.g_probe, j.g_shift, st); break;
-    default: launch_epilogue<128, 8>(P, j.workspace, &j.g, j.loss, j.g_probe, j.g_shift, st); break;
+    case 128: launch_epilogue<128, 8>(P, j.workspace, &j.g, j.loss, j.g_probe, j.g_shift, st); break;
+    default: launch_epilogue<192, 8>(P, j.workspace, &j.g, j.loss, j.g_probe, j.g_shift, st); break;
   }
-}
-
-static __global__ void reset_ints_kernel(int* p, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
 void class_launch(const PlanClass& c, const MsParams* d_params, int* err, hipStream_t st) {
@@ -161,11 +172,13 @@ void class_launch(const PlanClass& c, const MsParams* d_params, int* err, hipStr
     if (c.k == 1) ADORYM_BATCH(64, 4, 1); else if (c.k == 2) ADORYM_BATCH(64, 4, 2); else ADORYM_BATCH(64, 4, 4);
   } else if (c.n == 96) {
     if (c.k == 1) ADORYM_BATCH(96, 8, 1); else if (c.k == 2) ADORYM_BATCH(96, 8, 2); else ADORYM_BATCH(96, 8, 4);
-  } else {
+  } else if (c.n == 128) {
     if (c.k == 1) ADORYM_BATCH(128, 8, 1);
     else if (c.k == 2) ADORYM_BATCH(128, 8, 2);
     else if (c.k == 4) ADORYM_BATCH(128, 8, 4);
     else ADORYM_BATCH(128, 8, 8);
+  } else {
+    if (c.k == 2) ADORYM_BATCH(192, 8, 2); else if (c.k == 4) ADORYM_BATCH(192, 8, 4); else ADORYM_BATCH(192, 8, 8);
   }
 #undef ADORYM_BATCH
 }
@@ -174,7 +187,7 @@ void class_launch(const PlanClass& c, const MsParams* d_params, int* err, hipStr
 
 extern "C" {
 
-int adorym_supports_n(int32_t n) { return n == 64 || n == 96 || n == 128; }
+int adorym_supports_n(int32_t n) { return n == 64 || n == 96 || n == 128 || n == 192; }
 
 adorym_status adorym_create(adorym_ctx** out, int device, void* stream) {
   if (!out) return ADORYM_EINVAL;
@@ -281,9 +294,8 @@ adorym_status adorym_plan_create(adorym_ctx* ctx, const adorym_job* jobs, int32_
     PlanClass c{};
     c.n = key.n; c.repr = key.repr;
     c.l = key.n == 64 ? 4 : 8;
-    const int forced = key.n == 64 ? ctx->split64 : (key.n == 96 ? ctx->split96 : ctx->split128);
-    c.k = forced > 0 ? forced : (key.n == 128 ? 4 : 2);
-    if (key.n != 128 && c.k > 4) c.k = 4;
+    const int forced = split_of(ctx, key.n);
+    c.k = forced > 0 ? forced : (key.n == 192 ? 8 : (key.n == 128 ? 4 : 2));
     // one workgroup per CU: 256 / K groups, a multiple of 8 (one per XCD slot)
     c.groups = std::max(8, (256 / c.k) / 8 * 8);
     std::vector<std::pair<double, int2>> work;
@@ -293,7 +305,8 @@ adorym_status adorym_plan_create(adorym_ctx* ctx, const adorym_job* jobs, int32_
       switch (key.n) {
         case 64: plan->params[i] = params_for<64, 4>(ctx, j, c.k); break;
         case 96: plan->params[i] = params_for<96, 8>(ctx, j, c.k); break;
-        default: plan->params[i] = params_for<128, 8>(ctx, j, c.k); break;
+        case 128: plan->params[i] = params_for<128, 8>(ctx, j, c.k); break;
+        default: plan->params[i] = params_for<192, 8>(ctx, j, c.k); break;
       }
       for (int b = 0; b < j.batch; ++b) work.push_back({(double)j.g.n_slices * j.g.n * j.g.n, make_int2(i, b)});
     }
@@ -346,11 +359,13 @@ adorym_status adorym_plan_destroy(adorym_plan* plan) {
 adorym_status adorym_set_split(adorym_ctx* ctx, int32_t n, int32_t k) {
   if (!ctx) return ADORYM_EINVAL;
   const bool ok = k == 0 || ((n == 64 || n == 96) && (k == 1 || k == 2 || k == 4)) ||
-                  (n == 128 && (k == 1 || k == 2 || k == 4 || k == 8));
+                  (n == 128 && (k == 1 || k == 2 || k == 4 || k == 8)) ||
+                  (n == 192 && (k == 2 || k == 4 || k == 8));
   if (!ok) return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size / split");
   if (n == 64) ctx->split64 = k;
   else if (n == 96) ctx->split96 = k;
-  else ctx->split128 = k;
+  else if (n == 128) ctx->split128 = k;
+  else ctx->split192 = k;
   return ADORYM_OK;
 }
 

@@ -526,28 +526,34 @@ __global__ void __launch_bounds__(C::THREADS) multislice_batched_kernel(const Ms
   }
 }
 
-// Probe spectrum Q = DFT(p) / N^2 (natural [ky][kx]); also clears the
-// group barrier counters of the main kernel that follows on the stream.
+// Probe spectrum Q = DFT(p) / N^2 (natural [ky][kx]).  One group of K
+// workgroups (block index = part); K > 1 exchanges through xbuf.
 template <class C>
 __global__ void __launch_bounds__(C::THREADS) probe_spectrum_kernel(const float2* __restrict__ probe,
-                                                                    float2* __restrict__ q, int* counters,
-                                                                    int n_counters) {
-  __shared__ float2 buf[C::LDS_FIELD];
-  __shared__ Tables<C> tb;
-  for (int i = threadIdx.x; i < n_counters; i += C::THREADS) counters[i] = 0;
-  const Lane<C> ln(threadIdx.x);
-  build_twiddles<C>(tb, ln.tid);
+                                                                    float2* __restrict__ q, float2* xbuf,
+                                                                    int* counter, int* xcc, int* err) {
+  __shared__ MsShared<C> sh;
+  const int part = blockIdx.x;
+  Work<C> wk(threadIdx.x, 0, part);
+  wk.x.buf = xbuf; wk.x.counter = counter; wk.x.err = err; wk.x.phase = 0; wk.x.local = false;
+  const Lane<C>& ln = wk.ln;
+  build_twiddles<C>(sh.tb, ln.tid);
   __syncthreads();
+  if constexpr (C::K > 1) exchange_init<C::K>(wk.x, xcc, part);
   constexpr int N = C::N;
   float2 v[C::R];
 #pragma unroll
   for (int m = 0; m < C::R; ++m) v[m] = probe[ln.line * N + ln.pos_nat(m)];
-  fft_line<C, -1>(v, tb, ln);
-  transpose<C>(v, buf, ln, true, false);
-  fft_line<C, -1>(v, tb, ln);
+  fft_line<C, -1>(v, sh.tb, ln);
+  xfer<C>(v, sh, wk, true, false);
+  fft_line<C, -1>(v, sh.tb, ln);
   const float s = 1.0f / float(N * N);
 #pragma unroll
   for (int m = 0; m < C::R; ++m) q[ln.pos_spec(m) * N + ln.line] = cscale(v[m], s);
+}
+
+static __global__ void reset_ints_kernel(int* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
 // Sums of the per-position partials: probe-gradient spectrum (natural
@@ -586,22 +592,27 @@ static __global__ void reduce_partials_kernel(const float2* __restrict__ gacc, i
   }
 }
 
-// Probe gradient g_p = IDFT(sum_b G_b conj(e_b)) / N^2 from the natural-order sum.
+// Probe gradient g_p = IDFT(sum_b G_b conj(e_b)) / N^2 from the natural-order
+// sum.  One group of K workgroups, as probe_spectrum_kernel.
 template <class C>
 __global__ void __launch_bounds__(C::THREADS) probe_grad_kernel(const float2* __restrict__ gsum,
-                                                                float2* __restrict__ g_probe, int accumulate) {
-  __shared__ float2 buf[C::LDS_FIELD];
-  __shared__ Tables<C> tb;
-  const Lane<C> ln(threadIdx.x);
+                                                                float2* __restrict__ g_probe, int accumulate,
+                                                                float2* xbuf, int* counter, int* xcc, int* err) {
+  __shared__ MsShared<C> sh;
+  const int part = blockIdx.x;
+  Work<C> wk(threadIdx.x, 0, part);
+  wk.x.buf = xbuf; wk.x.counter = counter; wk.x.err = err; wk.x.phase = 0; wk.x.local = false;
+  const Lane<C>& ln = wk.ln;
   constexpr int N = C::N, NN = N * N;
-  build_twiddles<C>(tb, ln.tid);
+  build_twiddles<C>(sh.tb, ln.tid);
   __syncthreads();
+  if constexpr (C::K > 1) exchange_init<C::K>(wk.x, xcc, part);
   float2 v[C::R];
 #pragma unroll
   for (int m = 0; m < C::R; ++m) v[m] = gsum[ln.pos_spec(m) * N + ln.line];
-  ifft_line<C, +1>(v, tb, ln);
-  transpose<C>(v, buf, ln, false, true);
-  ifft_line<C, +1>(v, tb, ln);
+  ifft_line<C, +1>(v, sh.tb, ln);
+  xfer<C>(v, sh, wk, false, true);
+  ifft_line<C, +1>(v, sh.tb, ln);
   const float s = 1.0f / float(NN);
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
@@ -626,7 +637,7 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 constexpr int kMaxSplit = 8;   // largest K any kernel uses
 
 struct WsLayout {
-  size_t q, gsum, loss_part, gs_part, counters, xcc, gacc, ckpt, xbuf, total;
+  size_t q, gsum, loss_part, gs_part, counters, xcc, aux, gacc, ckpt, xbuf, total;
   int nslots;
 };
 
@@ -642,6 +653,7 @@ inline WsLayout ws_layout(const adorym_geom* g, int batch) {
   w.gs_part = off; off += align256((size_t)batch * kMaxSplit * 2 * sizeof(double));
   w.counters = off; off += align256((size_t)batch * sizeof(int));
   w.xcc = off; off += align256((size_t)batch * kMaxSplit * sizeof(int));
+  w.aux = off; off += align256(64 * sizeof(int));   // probe kernels: 2 counters + XCD ids
   w.gacc = off; off += align256((size_t)batch * nn * sizeof(float2));
   w.ckpt = off; off += align256((size_t)batch * w.nslots * nn * sizeof(float2));
   w.xbuf = off; off += align256((size_t)batch * 4 * nn * sizeof(float2));
@@ -691,7 +703,7 @@ void launch_ms(const MsParams& P, int repr, hipStream_t st) {
 }
 
 // Kernel parameters of one job; `ws` is its workspace (adorym_workspace_size).
-template <int N, int L, int K>
+template <int N, int L>
 MsParams make_params(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b, int batch,
                      const int32_t* corner, const float* shift, const float* i_meas, void* ws, bool with_probe_grad,
                      float* g_a, float* g_b, float* intensity) {
@@ -720,13 +732,23 @@ MsParams make_params(adorym_ctx* ctx, const adorym_geom* g, const float* a, cons
   return P;
 }
 
-// Per-job work before the multislice kernel: probe spectrum (also clears the
-// job's barrier counters) and, unless accumulating, zeroed object gradients.
+// Tile of the one-group probe kernels: the whole field in one workgroup when
+// it fits, else split in four.
+template <int N, int L>
+using ProbeCfg = TileCfg<N, L, (N > 128 ? 4 : 1)>;
+
+// Per-job work before the multislice kernel: clear the barrier counters,
+// probe spectrum, and, unless accumulating, zeroed object gradients.
 template <int N, int L>
 void launch_prologue(const MsParams& P, const float* probe, const adorym_geom* g, hipStream_t st) {
-  using C1 = TileCfg<N, L, 1>;
-  hipLaunchKernelGGL((probe_spectrum_kernel<C1>), dim3(1), dim3(C1::THREADS), 0, st,
-                     reinterpret_cast<const float2*>(probe), const_cast<float2*>(P.q), P.counters, P.B);
+  using PC = ProbeCfg<N, L>;
+  const WsLayout w = ws_layout(g, P.B);
+  int* aux = reinterpret_cast<int*>(reinterpret_cast<char*>(P.counters) - w.counters + w.aux);
+  hipLaunchKernelGGL(reset_ints_kernel, dim3(1), dim3(256), 0, st, P.counters, P.B);
+  hipLaunchKernelGGL(reset_ints_kernel, dim3(1), dim3(64), 0, st, aux, 64);
+  hipLaunchKernelGGL((probe_spectrum_kernel<PC>), dim3(PC::K), dim3(PC::THREADS), 0, st,
+                     reinterpret_cast<const float2*>(probe), const_cast<float2*>(P.q), P.xbuf, aux, aux + 8,
+                     P.err);
   const size_t nobj = (size_t)g->n_slices * g->obj_ny * g->obj_nx;
   if (!(g->flags & ADORYM_ACCUMULATE_GRADS)) {
     if (P.g_a) fill(st, P.g_a, nobj, 0.f);
@@ -738,16 +760,17 @@ void launch_prologue(const MsParams& P, const float* probe, const adorym_geom* g
 template <int N, int L>
 void launch_epilogue(const MsParams& P, void* ws, const adorym_geom* g, double* loss, float* g_probe,
                      float* g_shift, hipStream_t st) {
-  using C1 = TileCfg<N, L, 1>;
+  using PC = ProbeCfg<N, L>;
   const WsLayout w = ws_layout(g, P.B);
+  int* aux = reinterpret_cast<int*>(static_cast<char*>(ws) + w.aux);
   float2* gsum = reinterpret_cast<float2*>(static_cast<char*>(ws) + w.gsum);
   const int accumulate = (g->flags & ADORYM_ACCUMULATE_GRADS) ? 1 : 0;
   const int nn = N * N;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((nn + 255) / 256), dim3(256), 0, st, P.gacc, P.B, nn, gsum,
                      P.loss_part, P.gs_part, P.ksplit, loss, g_shift, accumulate);
   if (g_probe)
-    hipLaunchKernelGGL((probe_grad_kernel<C1>), dim3(1), dim3(C1::THREADS), 0, st, gsum,
-                       reinterpret_cast<float2*>(g_probe), accumulate);
+    hipLaunchKernelGGL((probe_grad_kernel<PC>), dim3(PC::K), dim3(PC::THREADS), 0, st, gsum,
+                       reinterpret_cast<float2*>(g_probe), accumulate, P.xbuf, aux + 1, aux + 16, P.err);
 }
 
 // One probe size N with lanes-per-line L; C1 is the single-workgroup tile.
@@ -757,7 +780,7 @@ adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const f
                   double* loss, float* g_a, float* g_b, float* g_probe, float* g_shift, float* intensity,
                   bool with_loss) {
   using C = TileCfg<N, L, K>;
-  MsParams P = make_params<N, L, K>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
+  MsParams P = make_params<N, L>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
                                     with_loss ? g_a : nullptr, with_loss ? g_b : nullptr, intensity);
   P.ksplit = K;
   hipStream_t st = ctx->stream;
@@ -799,8 +822,8 @@ void launch_batched(const MsParams* jobs, const int2* items, int n_items, int* t
 #define ADORYM_EPILOGUE_SIGNATURE(N_, L_) \
   void adorym_ms::launch_epilogue<N_, L_>(const adorym_ms::MsParams&, void*, const adorym_geom*, double*, float*, \
                                           float*, hipStream_t)
-#define ADORYM_PARAMS_SIGNATURE(N_, L_, K_) \
-  adorym_ms::MsParams adorym_ms::make_params<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, \
+#define ADORYM_PARAMS_SIGNATURE(N_, L_) \
+  adorym_ms::MsParams adorym_ms::make_params<N_, L_>(adorym_ctx*, const adorym_geom*, const float*, \
                                                         const float*, int, const int32_t*, const float*, \
                                                         const float*, void*, bool, float*, float*, float*)
 #define ADORYM_RUN_SIGNATURE(N_, L_, K_) \

@@ -255,8 +255,9 @@ struct TileCfg {
   // K == 1 workgroups have 1024 threads and 128 registers per lane: fence the
   // scheduler so table loads are not hoisted early; split tiles have room.
   static constexpr bool FENCE = (K == 1);
-  // Split tiles also have the registers to prefetch the next slice's chunk.
-  static constexpr bool PREFETCH = (K > 1);
+  // Split tiles with 16 values per lane also have the registers to prefetch
+  // the next slice's chunk.
+  static constexpr bool PREFETCH = (K > 1 && R <= 16);
   static_assert(N % L == 0 && LINES % RPW == 0 && WAVES >= 1, "bad tile");
 };
 

@@ -72,17 +72,19 @@ def test_workspace_size_formula():
     nn = 128 * 128 * 8                  # one complex64 field
     slots = 63 // 16 + 1 + 1            # slices 0, 16, 32, 48 and the last (63)
     # probe spectrum + its gradient sum, loss and shift partials for up to 8
-    # workgroups per position, barrier counters and XCD ids, probe-gradient partials,
+    # workgroups per position, barrier counters and XCD ids, probe-kernel counters,
+    # probe-gradient partials,
     # checkpoints, and two double-buffered exchange fields per position
-    expect = 2 * nn + 50 * 8 * 8 + 50 * 8 * 2 * 8 + 50 * 4 + 50 * 8 * 4 + 50 * nn + 50 * slots * nn + 50 * 4 * nn
-    assert expect <= size < expect + 9 * 256
+    expect = (2 * nn + 50 * 8 * 8 + 50 * 8 * 2 * 8 + 50 * 4 + 50 * 8 * 4 + 64 * 4 + 50 * nn + 50 * slots * nn
+              + 50 * 4 * nn)
+    assert expect <= size < expect + 10 * 256
     assert lib.adorym_workspace_size(ctypes.byref(_geom(n_slices=0)), 50) == 0
     assert lib.adorym_workspace_size(ctypes.byref(g), 0) == 0
 
 
 def test_supported_sizes():
     lib = _lib.load()
-    assert lib.adorym_supports_n(64) == 1 and lib.adorym_supports_n(96) == 1 and lib.adorym_supports_n(128) == 1
+    assert all(lib.adorym_supports_n(n) == 1 for n in (64, 96, 128, 192))
     assert lib.adorym_supports_n(100) == 0 and lib.adorym_supports_n(0) == 0
 
 

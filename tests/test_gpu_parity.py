@@ -109,6 +109,7 @@ def test_forward_matches_oracle(ctx, n, s, lat, npos, repr_):
     (128, 33, 150, 3, "delta_beta", "gaussian", 16),
     (128, 2, 140, 2, "delta_beta", "poisson", 1),
     (96, 17, 130, 3, "delta_beta", "gaussian", 16),
+    (192, 18, 230, 2, "delta_beta", "poisson", 16),
 ])
 def test_loss_grad_matches_oracle(ctx, n, s, lat, npos, repr_, loss, ckpt):
     sc = synth.small_case(seed=200 + n + s, n=n, n_slices=s, lateral=lat, n_pos=npos, obj_repr=repr_,
@@ -121,7 +122,7 @@ def test_loss_grad_matches_oracle(ctx, n, s, lat, npos, repr_, loss, ckpt):
 
 
 @pytest.mark.parametrize("n,k", [(64, 1), (64, 2), (64, 4), (96, 1), (96, 2), (96, 4),
-                                 (128, 1), (128, 2), (128, 4), (128, 8)])
+                                 (128, 1), (128, 2), (128, 4), (128, 8), (192, 2), (192, 4), (192, 8)])
 def test_every_split_matches_oracle(ctx, n, k):
     """Fields split over k cooperating workgroups give the same results."""
     sc = synth.small_case(seed=300 + n + k, n=n, n_slices=7, lateral=n + 30, n_pos=3, strength=30.0)
@@ -212,7 +213,7 @@ def test_batched_plan_equals_individual_calls(ctx):
     import torch
     from paper_2012_12686_amd import Job
     specs = [(64, 3, 90, 5, "gaussian"), (96, 11, 120, 4, "poisson"), (128, 7, 150, 3, "gaussian"),
-             (64, 20, 100, 6, "poisson"), (128, 1, 140, 2, "poisson")]
+             (64, 20, 100, 6, "poisson"), (128, 1, 140, 2, "poisson"), (192, 5, 220, 3, "gaussian")]
     jobs, singles = [], []
     for i, (n, s, lat, npos, loss) in enumerate(specs):
         sc = synth.small_case(seed=500 + i, n=n, n_slices=s, lateral=lat, n_pos=npos, loss=loss, strength=30.0)
