@@ -96,6 +96,9 @@ def main():
                     help="workgroups per position (0 = the library's automatic choice)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters)")
+    ap.add_argument("--workload", default="multislice", choices=["multislice", "batching", "serving"],
+                    help="multislice: the 64-slice minibatch (default line); batching: 32 mixed scans, "
+                         "batched vs per-job; serving: the request loop")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a "
@@ -112,6 +115,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 4}))
         return
+
+    if args.workload == "batching":
+        return bench_batching(args)
+    if args.workload == "serving":
+        from paper_2012_12686_amd.serve import bench_serving
+        return bench_serving(args)
 
     import synth
     from paper_2012_12686_amd import Context, Geometry, split_positions
@@ -210,6 +219,65 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, slice(0, mb), i_meas_np[:mb].astype(np.float64))
     print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def bench_batching(args):
+    """32 independent scans (N in {64, 96, 128, 192}, S in 1..64, 50..500
+    positions): one iteration = loss and gradients of every job.  Times the
+    plain per-job form, the batched plan (eager) and its captured graph."""
+    import torch
+
+    import synth
+    from paper_2012_12686_amd import Context
+    from paper_2012_12686_amd.autotune import autotune
+    from paper_2012_12686_amd.batch import BatchRunner, to_device_scan
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ctx = Context(dev)
+    t0 = time.perf_counter()
+    scans = [to_device_scan(ctx, sc, seed=i) for i, sc in enumerate(synth.config4_jobs())]
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t0
+    runner = BatchRunner(ctx, scans)
+    npos = runner.positions()
+    tune = autotune(ctx, runner.jobs, reps=1)
+    runner.build_plan()
+    runner.capture()
+
+    def timed(fn, reps):
+        for _ in range(max(1, args.warmup // 2)):
+            fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record()
+        for r in range(reps):
+            fn()
+            ev[r + 1].record()
+        torch.cuda.synchronize()
+        ctx.sync_error()
+        lat = [ev[r].elapsed_time(ev[r + 1]) for r in range(reps)]
+        return sum(lat) / reps, lat
+
+    reps = max(2, min(args.steps, 8))
+    ms_job, _ = timed(lambda: runner.run_per_job(adam=False), reps)
+    ms_plan, _ = timed(lambda: runner.step(adam=False), reps)
+    ms_graph, lat = timed(lambda: runner.step_graph(adam=False), reps)
+    line = {
+        "metric": "batched multislice fwd+adjoint positions/s (32 mixed scans)",
+        "value": npos / (ms_graph / 1e3), "unit": "positions/s", "n_gpus": 1, "steps": reps,
+        "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "32 scans, N in {64,96,128,192}, S in 1..64, 50..500 positions each, "
+                               "full-batch loss+gradient per iteration", "positions": npos},
+        "per_job_ms": ms_job, "plan_eager_ms": ms_plan, "plan_graph_ms": ms_graph,
+        "speedup_vs_per_job": ms_job / ms_graph,
+        "p50_iter_ms": float(np.percentile(lat, 50)), "p99_iter_ms": float(np.percentile(lat, 99)),
+        "autotune": {str(k): v for k, v in tune.items()}, "prep_s": prep_s,
+    }
+    print(json.dumps(line), flush=True)
+    runner.close()
     ctx.close()
 
 
