@@ -70,8 +70,20 @@ typedef enum {
 enum { ADORYM_LOSS_GAUSSIAN = 0, ADORYM_LOSS_POISSON = 1 };
 enum { ADORYM_OBJ_DELTA_BETA = 0, ADORYM_OBJ_REAL_IMAG = 1 };
 enum {
-  ADORYM_ACCUMULATE_GRADS = 1u  /* add into the gradient arrays instead of overwriting */
+  ADORYM_ACCUMULATE_GRADS = 1u, /* add into the gradient arrays instead of overwriting */
+  ADORYM_DETERMINISTIC = 2u     /* bitwise-reproducible object gradients (see below)  */
 };
+/* Deterministic mode.  By default each position scatters its contribution
+ * to dL/d(object) with float atomics, so the order of the additions (and the
+ * last bits of the result) depends on scheduling.  With ADORYM_DETERMINISTIC
+ * the contributions are staged in the workspace (B*S*2*N*N*4 more bytes) and
+ * a second kernel sums them for every voxel over the positions in index
+ * order, in FP64, rounding once to float32.  Loss, probe and shift gradients
+ * are always reduced in a fixed order.  Deterministic calls use one fixed
+ * split per probe size (k = 1 for N <= 96, 4 for N = 128, 8 for N = 192;
+ * adorym_set_split does not apply), so every output is bitwise
+ * reproducible: run to run, and between a single call and the same job
+ * inside a batched plan next to other jobs. */
 
 /* Geometry and options of one scan. */
 typedef struct {
@@ -86,7 +98,7 @@ typedef struct {
   int32_t obj_repr;     /* ADORYM_OBJ_*                                            */
   int32_t ckpt_every;   /* slice checkpoint interval C (>= 1; 16 is typical)       */
   double eps;           /* loss epsilon (photons)                                  */
-  uint32_t flags;       /* ADORYM_ACCUMULATE_GRADS                                 */
+  uint32_t flags;       /* ADORYM_ACCUMULATE_GRADS | ADORYM_DETERMINISTIC          */
 } adorym_geom;
 
 /* Create a context on HIP device `device` issuing work on `stream`
@@ -102,8 +114,9 @@ int adorym_supports_n(int32_t n);
 
 /* Bytes of device workspace adorym_forward / adorym_loss_grad need for a
  * batch of `batch` positions (probe spectrum, per-position loss, shift and
- * probe partials, slice checkpoints every ckpt_every slices, and the
- * exchange buffers of split workgroups).  0 on bad input. */
+ * probe partials, slice checkpoints every ckpt_every slices, the
+ * exchange buffers of split workgroups and, in deterministic mode, the
+ * staged object-gradient contributions).  0 on bad input. */
 size_t adorym_workspace_size(const adorym_geom* g, int32_t batch);
 
 /* Forward model (Alg. 1 without refinement of anything): predicted

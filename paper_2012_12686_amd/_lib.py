@@ -19,6 +19,7 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ERANGE
 LOSS_GAUSSIAN, LOSS_POISSON = 0, 1
 OBJ_DELTA_BETA, OBJ_REAL_IMAG = 0, 1
 ACCUMULATE_GRADS = 1
+DETERMINISTIC = 2
 
 
 class Geom(ctypes.Structure):

@@ -36,11 +36,13 @@ class Geometry:
     ckpt_every: int = 16
     eps: float = 1e-6
     accumulate: bool = False
+    deterministic: bool = False   # bitwise-reproducible object gradients (FP64 ordered sum)
 
     def to_c(self) -> Geom:
         return Geom(self.n, self.n_slices, self.obj_ny, self.obj_nx, self.wavelength_m, self.pixel_m,
                     self.slice_dz_m, LOSSES[self.loss], REPRS[self.obj_repr], self.ckpt_every, self.eps,
-                    _lib.ACCUMULATE_GRADS if self.accumulate else 0)
+                    (_lib.ACCUMULATE_GRADS if self.accumulate else 0)
+                    | (_lib.DETERMINISTIC if self.deterministic else 0))
 
     @classmethod
     def from_scan(cls, scan, **kw):

@@ -49,6 +49,8 @@ struct MsParams {
   float* intensity;        // [B][N][N] or null
   float* g_a;              // [S][Ly][Lx] or null
   float* g_b;
+  float* gstage;           // [B][S][2][N][N] staged object-gradient contributions
+                           // (deterministic mode), else null
   float2* ckpt;            // [B][nslots][K][R*THREADS]
   float2* gacc;            // [B][N][N] natural, or null (probe-gradient partials)
   double* loss_part;       // [B][K]
@@ -177,6 +179,21 @@ __device__ __forceinline__ rsrc_t slice_rsrc(const float* base, int j, const Chu
   return make_rsrc(base + (size_t)j * (o.slice_bytes / 4), o.slice_bytes);
 }
 
+// Deterministic mode: this position's contribution to one gradient plane of
+// slice j, chunk-local [N][N] (row y, column x), plain stores.
+template <class C>
+__device__ __forceinline__ rsrc_t stage_rsrc(const MsParams& P, int b, int j, int comp) {
+  constexpr int NN = C::N * C::N;
+  return make_rsrc(P.gstage + (((size_t)b * P.S + j) * 2 + comp) * NN, NN * 4);
+}
+template <class C, bool ROW>
+__device__ __forceinline__ void stage_store(rsrc_t r, const Lane<C>& ln, int m, float v) {
+  constexpr int N = C::N;
+  const uint32_t off = ROW ? (uint32_t)((ln.line * N + ln.q) * 4) : (uint32_t)((ln.q * N + ln.line) * 4);
+  const uint32_t step = ROW ? 4 * C::L : 4 * C::L * N;
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off + (uint32_t)m * step, 0, 0);
+}
+
 // Object values of slice j on this thread's elements (layout ROW/COL).
 template <class C, bool ROW>
 __device__ __forceinline__ void load_chunk(float (&ca)[C::R], float (&cb)[C::R], const MsParams& P,
@@ -261,7 +278,9 @@ __device__ __forceinline__ void forward_slice(float2 (&v)[C::R], float (&ca)[C::
 //        lam = dL/dphi_j; ca/cb = slice j's object values when prefetching
 //   out: psi = phi_{j-1} = P^H psi_j, lam = dL/dphi_{j-1} = P^H conj(t_j) lam;
 //        ca/cb = slice j-1's object values when prefetching
-template <class C, int REPR, bool ROW>
+// STAGED (deterministic mode): the slice gradient is stored to this
+// position's staging planes instead of being added to the object gradient.
+template <class C, int REPR, bool ROW, bool STAGED>
 __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam)[C::R], float (&ca)[C::R],
                                                float (&cb)[C::R], const MsParams& P, MsShared<C>& sh, Work<C>& wk,
                                                const ChunkOffsets& o, int j) {
@@ -269,9 +288,15 @@ __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam
   const bool anchored = is_ckpt(j, P.S, P.ckpt_every);
   if (anchored) field_load<C>(psi, ckpt_ptr<C>(P, wk, ckpt_slot(j, P.S, P.ckpt_every)), ln);  // psi_j exactly
   if (!C::PREFETCH) load_chunk<C, ROW>(ca, cb, P, o, j);
-  const bool grads = P.g_a != nullptr;
-  const rsrc_t rga = grads ? slice_rsrc(P.g_a, j, o) : make_rsrc(P.a, 0);
-  const rsrc_t rgb = grads ? slice_rsrc(P.g_b, j, o) : make_rsrc(P.b, 0);
+  const bool grads = STAGED || P.g_a != nullptr;
+  rsrc_t rga, rgb;
+  if constexpr (STAGED) {
+    rga = stage_rsrc<C>(P, wk.b, j, 0);
+    rgb = stage_rsrc<C>(P, wk.b, j, 1);
+  } else {
+    rga = grads ? slice_rsrc(P.g_a, j, o) : make_rsrc(P.a, 0);
+    rgb = grads ? slice_rsrc(P.g_b, j, o) : make_rsrc(P.b, 0);
+  }
   const float kdz = P.kdz;
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
@@ -281,14 +306,22 @@ __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam
     const float2 out_wave = anchored ? cmul(psi[m], t) : psi[m];     // phi_j
     const float2 l = lam[m];
     if (grads) {
+      float ga, gb;
       if constexpr (REPR == ADORYM_OBJ_DELTA_BETA) {
         const float2 z = cmulc(l, out_wave);          // lam conj(phi)
-        chunk_atomic_add<C, ROW>(rga, o, m, kdz * z.y);
-        chunk_atomic_add<C, ROW>(rgb, o, m, -kdz * z.x);
+        ga = kdz * z.y;
+        gb = -kdz * z.x;
       } else {
         const float2 z = cmulc(l, in_wave);           // lam conj(psi)
-        chunk_atomic_add<C, ROW>(rga, o, m, z.x);
-        chunk_atomic_add<C, ROW>(rgb, o, m, z.y);
+        ga = z.x;
+        gb = z.y;
+      }
+      if constexpr (STAGED) {
+        stage_store<C, ROW>(rga, ln, m, ga);
+        stage_store<C, ROW>(rgb, ln, m, gb);
+      } else {
+        chunk_atomic_add<C, ROW>(rga, o, m, ga);
+        chunk_atomic_add<C, ROW>(rgb, o, m, gb);
       }
     }
     lam[m] = cmulc(l, t);                              // conj(t) lam = dL/dpsi_j
@@ -324,7 +357,7 @@ __device__ __forceinline__ void group_of_block(int& b, int& part) {
 
 // Everything one workgroup does for its part of one position.  wk.b, wk.part
 // and the exchange state wk.x are set by the caller.
-template <class C, int REPR, bool LOSS>
+template <class C, int REPR, bool LOSS, bool STAGED>
 __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>& sh, Work<C>& wk) {
   const int b = wk.b, part = wk.part;
   const Lane<C>& ln = wk.ln;
@@ -424,15 +457,15 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
   int j = P.S - 1;
   // the forward sweep left slice S-1's object values in ca/cb
   if (!last_row) {
-    backward_slice<C, REPR, false>(psi, v, ca, cb, P, sh, wk, o, j);
+    backward_slice<C, REPR, false, STAGED>(psi, v, ca, cb, P, sh, wk, o, j);
     --j;
   }
   // now slice j is even (ROW); pairs (j ROW, j-1 COL) down to slice 0
   for (; j >= 1; j -= 2) {
-    backward_slice<C, REPR, true>(psi, v, ca, cb, P, sh, wk, o, j);
-    backward_slice<C, REPR, false>(psi, v, ca, cb, P, sh, wk, o, j - 1);
+    backward_slice<C, REPR, true, STAGED>(psi, v, ca, cb, P, sh, wk, o, j);
+    backward_slice<C, REPR, false, STAGED>(psi, v, ca, cb, P, sh, wk, o, j - 1);
   }
-  if (j == 0) backward_slice<C, REPR, true>(psi, v, ca, cb, P, sh, wk, o, 0);
+  if (j == 0) backward_slice<C, REPR, true, STAGED>(psi, v, ca, cb, P, sh, wk, o, 0);
   // v = dL/d(shifted probe) in ROW layout, natural order.
 
   // FourierShift adjoint: G = DFT(g_pb) in COL layout (kx line, ky spectral).
@@ -466,7 +499,7 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
 }
 
 // One group of K workgroups per position of a single job.
-template <class C, int REPR, bool LOSS>
+template <class C, int REPR, bool LOSS, bool STAGED>
 __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
   __shared__ MsShared<C> sh;
   int b, part;
@@ -481,14 +514,14 @@ __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
   const int cy = P.corner[2 * b], cx = P.corner[2 * b + 1];
   const bool inside = cy >= 0 && cx >= 0 && cy + C::N <= P.Ly && cx + C::N <= P.Lx;
   if (C::K > 1 && inside) exchange_init<C::K>(wk.x, P.xcc + b * C::K, part);
-  process_position<C, REPR, LOSS>(P, sh, wk);
+  process_position<C, REPR, LOSS, STAGED>(P, sh, wk);
 }
 
 // Persistent multi-job kernel: groups of K workgroups take (job, position)
 // items from a device queue until it is empty.  Every member of a group sees
 // the same ticket (member 0 draws it and publishes it behind the group
 // barrier), so all of them leave the loop together.
-template <class C, int REPR>
+template <class C, int REPR, bool STAGED>
 __global__ void __launch_bounds__(C::THREADS) multislice_batched_kernel(const MsParams* __restrict__ jobs,
                                                                         const int2* __restrict__ items,
                                                                         int n_items, int* ticket, int* mailbox,
@@ -522,7 +555,7 @@ __global__ void __launch_bounds__(C::THREADS) multislice_batched_kernel(const Ms
     if (t >= n_items) break;
     const int2 it = items[t];
     wk.b = it.y;
-    process_position<C, REPR, true>(jobs[it.x], sh, wk);
+    process_position<C, REPR, true, STAGED>(jobs[it.x], sh, wk);
   }
 }
 
@@ -629,6 +662,76 @@ static __global__ void fill_kernel(float* __restrict__ p, size_t n, float val) {
   for (; i < n; i += stride) p[i] = val;
 }
 
+// Deterministic object gradient.  One workgroup per 64 x 16 voxel tile of
+// one slice: it lists, in index order, the positions whose chunk covers part
+// of the tile (chunks outside the object are skipped, as in the multislice
+// kernel), then every voxel sums the staged contributions of those positions
+// in that order in FP64 and is written once (rounded to float32).
+constexpr int kDetTx = 64, kDetTy = 16, kDetList = 2048;
+static __global__ void __launch_bounds__(256) det_grad_kernel(const float* __restrict__ stage,
+                                                              const int32_t* __restrict__ corner, int n, int B,
+                                                              int S, int Ly, int Lx, float* __restrict__ g_a,
+                                                              float* __restrict__ g_b, int accumulate) {
+  __shared__ int lb[kDetList], lcy[kDetList], lcx[kDetList];
+  __shared__ int wave_cnt[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tx0 = blockIdx.x * kDetTx, ty0 = blockIdx.y * kDetTy, j = blockIdx.z;
+  const int x = tx0 + lane;
+  const size_t nn = (size_t)n * n;
+  double acc_a[kDetTy / 4], acc_b[kDetTy / 4];
+#pragma unroll
+  for (int r = 0; r < kDetTy / 4; ++r) acc_a[r] = acc_b[r] = 0.0;
+  for (int w0 = 0; w0 < B; w0 += kDetList) {
+    const int w1 = min(B, w0 + kDetList);
+    int count = 0;                                  // uniform over the workgroup
+    for (int p0 = w0; p0 < w1; p0 += 256) {
+      const int p = p0 + threadIdx.x;
+      bool hit = false;
+      int cy = 0, cx = 0;
+      if (p < w1) {
+        cy = corner[2 * p];
+        cx = corner[2 * p + 1];
+        const bool inside = cy >= 0 && cx >= 0 && cy + n <= Ly && cx + n <= Lx;
+        hit = inside && cy < ty0 + kDetTy && cy + n > ty0 && cx < tx0 + kDetTx && cx + n > tx0;
+      }
+      const unsigned long long mask = __ballot(hit);
+      if (lane == 0) wave_cnt[wave] = __popcll(mask);
+      __syncthreads();
+      int at = count + __popcll(mask & ((1ull << lane) - 1ull));
+      for (int w = 0; w < wave; ++w) at += wave_cnt[w];
+      if (hit) { lb[at] = p; lcy[at] = cy; lcx[at] = cx; }
+      count += wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
+      __syncthreads();
+    }
+    for (int i = 0; i < count; ++i) {
+      const int lx = x - lcx[i];
+      if (lx < 0 || lx >= n) continue;
+      const float* sa = stage + ((size_t)lb[i] * S + j) * 2 * nn;
+      const float* sb = sa + nn;
+#pragma unroll
+      for (int r = 0; r < kDetTy / 4; ++r) {
+        const int ly = ty0 + wave + 4 * r - lcy[i];
+        if (ly >= 0 && ly < n) {
+          acc_a[r] += (double)sa[(size_t)ly * n + lx];
+          acc_b[r] += (double)sb[(size_t)ly * n + lx];
+        }
+      }
+    }
+    __syncthreads();                                // the list is rebuilt for the next window
+  }
+  if (x >= Lx) return;
+#pragma unroll
+  for (int r = 0; r < kDetTy / 4; ++r) {
+    const int y = ty0 + wave + 4 * r;
+    if (y >= Ly) continue;
+    const size_t idx = ((size_t)j * Ly + y) * Lx + x;
+    double va = acc_a[r], vb = acc_b[r];
+    if (accumulate) { va += (double)g_a[idx]; vb += (double)g_b[idx]; }
+    g_a[idx] = (float)va;
+    g_b[idx] = (float)vb;
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Host side
 // ----------------------------------------------------------------------------
@@ -637,7 +740,7 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 constexpr int kMaxSplit = 8;   // largest K any kernel uses
 
 struct WsLayout {
-  size_t q, gsum, loss_part, gs_part, counters, xcc, aux, gacc, ckpt, xbuf, total;
+  size_t q, gsum, loss_part, gs_part, counters, xcc, aux, gacc, ckpt, xbuf, stage, total;
   int nslots;
 };
 
@@ -657,6 +760,8 @@ inline WsLayout ws_layout(const adorym_geom* g, int batch) {
   w.gacc = off; off += align256((size_t)batch * nn * sizeof(float2));
   w.ckpt = off; off += align256((size_t)batch * w.nslots * nn * sizeof(float2));
   w.xbuf = off; off += align256((size_t)batch * 4 * nn * sizeof(float2));
+  w.stage = off;
+  if (g->flags & ADORYM_DETERMINISTIC) off += align256((size_t)batch * S * 2 * nn * sizeof(float));
   w.total = off;
   return w;
 }
@@ -692,14 +797,14 @@ inline void fill(hipStream_t st, float* p, size_t n, float v) {
   hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, st, p, n, v);
 }
 
-template <class C, bool LOSS>
+template <class C, bool LOSS, bool STAGED>
 void launch_ms(const MsParams& P, int repr, hipStream_t st) {
   // XCD-aware grid: ceil(B/8) groups per XCD, K slots per group
   const dim3 grid(((P.B + 7) / 8) * 8 * C::K), block(C::THREADS);
   if (repr == ADORYM_OBJ_DELTA_BETA)
-    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, LOSS>), grid, block, 0, st, P);
+    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, LOSS, STAGED>), grid, block, 0, st, P);
   else
-    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, LOSS>), grid, block, 0, st, P);
+    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, LOSS, STAGED>), grid, block, 0, st, P);
 }
 
 // Kernel parameters of one job; `ws` is its workspace (adorym_workspace_size).
@@ -714,6 +819,7 @@ MsParams make_params(adorym_ctx* ctx, const adorym_geom* g, const float* a, cons
   P.q = reinterpret_cast<const float2*>(base + w.q);
   P.corner = corner; P.shift = shift; P.i_meas = i_meas; P.intensity = intensity;
   P.g_a = g_a; P.g_b = g_b;
+  P.gstage = (g_a && (g->flags & ADORYM_DETERMINISTIC)) ? reinterpret_cast<float*>(base + w.stage) : nullptr;
   P.ckpt = reinterpret_cast<float2*>(base + w.ckpt);
   P.gacc = with_probe_grad ? reinterpret_cast<float2*>(base + w.gacc) : nullptr;
   P.loss_part = reinterpret_cast<double*>(base + w.loss_part);
@@ -750,7 +856,8 @@ void launch_prologue(const MsParams& P, const float* probe, const adorym_geom* g
                      reinterpret_cast<const float2*>(probe), const_cast<float2*>(P.q), P.xbuf, aux, aux + 8,
                      P.err);
   const size_t nobj = (size_t)g->n_slices * g->obj_ny * g->obj_nx;
-  if (!(g->flags & ADORYM_ACCUMULATE_GRADS)) {
+  // (the deterministic reduction writes every voxel itself)
+  if (!(g->flags & ADORYM_ACCUMULATE_GRADS) && !P.gstage) {
     if (P.g_a) fill(st, P.g_a, nobj, 0.f);
     if (P.g_b) fill(st, P.g_b, nobj, 0.f);
   }
@@ -771,10 +878,25 @@ void launch_epilogue(const MsParams& P, void* ws, const adorym_geom* g, double* 
   if (g_probe)
     hipLaunchKernelGGL((probe_grad_kernel<PC>), dim3(PC::K), dim3(PC::THREADS), 0, st, gsum,
                        reinterpret_cast<float2*>(g_probe), accumulate, P.xbuf, aux + 1, aux + 16, P.err);
+  if (P.gstage) {
+    const dim3 grid((P.Lx + kDetTx - 1) / kDetTx, (P.Ly + kDetTy - 1) / kDetTy, P.S);
+    hipLaunchKernelGGL(det_grad_kernel, grid, dim3(256), 0, st, P.gstage, P.corner, N, P.B, P.S, P.Ly, P.Lx,
+                       P.g_a, P.g_b, accumulate);
+  }
 }
 
-// One probe size N with lanes-per-line L; C1 is the single-workgroup tile.
-template <int N, int L, int K>
+// Deterministic mode runs with one fixed split per probe size, so that a
+// job's results do not depend on the split chosen for other calls.
+constexpr int det_split(int n) { return n == 192 ? 8 : (n == 128 ? 4 : 1); }
+
+// Whether a loss_grad call stages its object gradient (deterministic mode).
+inline bool staged_call(const adorym_geom* g, bool with_loss, const float* g_a) {
+  return with_loss && g_a != nullptr && (g->flags & ADORYM_DETERMINISTIC) != 0;
+}
+
+// One probe size N with lanes-per-line L and split K.  STAGED instances
+// serve deterministic-mode loss_grad calls only.
+template <int N, int L, int K, bool STAGED>
 adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b, const float* probe,
                   const int32_t* corner, const float* shift, int batch, const float* i_meas, void* ws,
                   double* loss, float* g_a, float* g_b, float* g_probe, float* g_shift, float* intensity,
@@ -787,8 +909,12 @@ adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const f
   const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
   launch_prologue<N, L>(P, probe, g, st);
   if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
-  if (with_loss) launch_ms<C, true>(P, g->obj_repr, st);
-  else launch_ms<C, false>(P, g->obj_repr, st);
+  if constexpr (STAGED) {
+    launch_ms<C, true, true>(P, g->obj_repr, st);
+  } else {
+    if (with_loss) launch_ms<C, true, false>(P, g->obj_repr, st);
+    else launch_ms<C, false, false>(P, g->obj_repr, st);
+  }
   if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
   if (with_loss) launch_epilogue<N, L>(P, ws, g, loss, g_probe, g_shift, st);
   hipError_t e = hipGetLastError();
@@ -798,24 +924,24 @@ adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const f
 
 // The persistent multi-job kernel of one probe-size class (device tables
 // prepared by the plan).
-template <int N, int L, int K>
+template <int N, int L, int K, bool STAGED>
 void launch_batched(const MsParams* jobs, const int2* items, int n_items, int* ticket, int* mailbox, int* counters,
                     int* xcc, float2* xbuf, int* err, int groups, int repr, hipStream_t st) {
   using C = TileCfg<N, L, K>;
   const dim3 grid(groups * K), block(C::THREADS);
   if (repr == ADORYM_OBJ_DELTA_BETA)
-    hipLaunchKernelGGL((multislice_batched_kernel<C, ADORYM_OBJ_DELTA_BETA>), grid, block, 0, st, jobs, items,
+    hipLaunchKernelGGL((multislice_batched_kernel<C, ADORYM_OBJ_DELTA_BETA, STAGED>), grid, block, 0, st, jobs, items,
                        n_items, ticket, mailbox, counters, xcc, xbuf, err);
   else
-    hipLaunchKernelGGL((multislice_batched_kernel<C, ADORYM_OBJ_REAL_IMAG>), grid, block, 0, st, jobs, items,
+    hipLaunchKernelGGL((multislice_batched_kernel<C, ADORYM_OBJ_REAL_IMAG, STAGED>), grid, block, 0, st, jobs, items,
                        n_items, ticket, mailbox, counters, xcc, xbuf, err);
 }
 
 }  // namespace adorym_ms
 
 // Explicit instantiation helpers
-#define ADORYM_BATCHED_SIGNATURE(N_, L_, K_) \
-  void adorym_ms::launch_batched<N_, L_, K_>(const adorym_ms::MsParams*, const int2*, int, int*, int*, int*, int*, \
+#define ADORYM_BATCHED_SIGNATURE(N_, L_, K_, S_) \
+  void adorym_ms::launch_batched<N_, L_, K_, S_>(const adorym_ms::MsParams*, const int2*, int, int*, int*, int*, int*, \
                                               float2*, int*, int, int, hipStream_t)
 #define ADORYM_PROLOGUE_SIGNATURE(N_, L_) \
   void adorym_ms::launch_prologue<N_, L_>(const adorym_ms::MsParams&, const float*, const adorym_geom*, hipStream_t)
@@ -826,7 +952,7 @@ void launch_batched(const MsParams* jobs, const int2* items, int n_items, int* t
   adorym_ms::MsParams adorym_ms::make_params<N_, L_>(adorym_ctx*, const adorym_geom*, const float*, \
                                                         const float*, int, const int32_t*, const float*, \
                                                         const float*, void*, bool, float*, float*, float*)
-#define ADORYM_RUN_SIGNATURE(N_, L_, K_) \
-  adorym_status adorym_ms::run<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, const float*, const float*, \
+#define ADORYM_RUN_SIGNATURE(N_, L_, K_, S_) \
+  adorym_status adorym_ms::run<N_, L_, K_, S_>(adorym_ctx*, const adorym_geom*, const float*, const float*, const float*, \
                                            const int32_t*, const float*, int, const float*, void*, double*, float*, \
                                            float*, float*, float*, float*, bool)

@@ -80,6 +80,10 @@ def test_workspace_size_formula():
     assert expect <= size < expect + 10 * 256
     assert lib.adorym_workspace_size(ctypes.byref(_geom(n_slices=0)), 50) == 0
     assert lib.adorym_workspace_size(ctypes.byref(g), 0) == 0
+    # deterministic mode stages every position's float32 gradient of both planes
+    gd = _geom(flags=_lib.DETERMINISTIC)
+    extra = lib.adorym_workspace_size(ctypes.byref(gd), 50) - size
+    assert 50 * 64 * 2 * 128 * 128 * 4 <= extra < 50 * 64 * 2 * 128 * 128 * 4 + 256
 
 
 def test_supported_sizes():

@@ -232,3 +232,86 @@ def test_batched_plan_equals_individual_calls(ctx):
         for k in ("g_a", "g_b", "g_probe", "g_shift"):
             assert rel_l2(got[k], ref[k]) < 1e-5, k
     plan.close()
+
+
+# ------------------------------------------------------------------ deterministic mode
+
+@pytest.mark.parametrize("n,s,lat,npos,loss", [(64, 5, 100, 6, "poisson"), (96, 9, 120, 4, "gaussian"),
+                                               (128, 18, 150, 5, "poisson"), (192, 4, 230, 3, "gaussian")])
+def test_deterministic_mode_is_bitwise_reproducible_and_matches_oracle(ctx, n, s, lat, npos, loss):
+    """FP64 ordered object-gradient sum: same bits on every run, whatever split
+    the context was told to use, and the same numbers as the atomic path."""
+    sc = synth.small_case(seed=600 + n + s, n=n, n_slices=s, lateral=lat, n_pos=npos, loss=loss, strength=30.0)
+    case = Case(sc, poisson_seed=5 if loss == "poisson" else None)
+    d1 = run_grad(ctx, case, deterministic=True)
+    ctx.set_split(n, 2)                      # must not apply to deterministic calls
+    try:
+        d2 = run_grad(ctx, case, deterministic=True)
+        plain = run_grad(ctx, case)
+    finally:
+        ctx.set_split(n, 0)
+    for k in ("loss", "g_a", "g_b", "g_probe", "g_shift", "intensity"):
+        assert np.array_equal(np.asarray(d1[k]), np.asarray(d2[k])), k
+    # the plain call ran with another split, whose float rounding differs
+    for k in ("g_a", "g_b", "g_probe", "g_shift"):
+        assert rel_l2(d1[k], plain[k]) < 3e-5, k
+    check_grads(d1, case.oracle_loss_grad(), case)
+
+
+def test_deterministic_accumulate_and_out_of_range(ctx):
+    import torch
+    from paper_2012_12686_amd._lib import AdorymError, ERANGE
+    sc = synth.small_case(seed=41, n=64, n_slices=3, lateral=90, n_pos=4, strength=30.0)
+    case = Case(sc)
+    inp, i_meas = case.torch_inputs()
+    g1 = ctx.loss_grad(_geom(case, deterministic=True), **inp, i_meas=i_meas)
+    acc = {k: v.clone() for k, v in g1.items() if k != "loss"}
+    ctx.loss_grad(_geom(case, deterministic=True, accumulate=True), **inp, i_meas=i_meas, out=acc)
+    torch.cuda.synchronize()
+    for k in ("g_a", "g_b", "g_probe", "g_shift"):
+        assert rel_l2(acc[k].cpu().numpy(), 2 * g1[k].cpu().numpy()) < 1e-7, k
+    # a chunk off the object: flagged, and its position contributes nothing
+    bad = inp["corner"].clone()
+    bad[2, 0] = 90 - 64 + 3
+    keep = [0, 1, 3]
+    inp_bad = dict(inp, corner=bad)
+    gb = ctx.loss_grad(_geom(case, deterministic=True), **inp_bad, i_meas=i_meas)
+    with pytest.raises(AdorymError) as ei:
+        ctx.sync_error()
+    assert ei.value.status == ERANGE
+    inp_k = dict(inp, corner=inp["corner"][keep].contiguous(), shift=inp["shift"][keep].contiguous())
+    gk = ctx.loss_grad(_geom(case, deterministic=True), **inp_k, i_meas=i_meas[keep].contiguous())
+    torch.cuda.synchronize()
+    # the loss is a mean over all B N^2 pixels: 3 of 4 positions contribute
+    for k in ("g_a", "g_b"):
+        np.testing.assert_allclose(gb[k].cpu().numpy(), 0.75 * gk[k].cpu().numpy(), rtol=1e-5,
+                                   atol=1e-6 * float(gk[k].abs().max()))
+
+
+def test_deterministic_jobs_in_a_plan_equal_single_calls_bitwise(ctx):
+    """A deterministic job gives the same bits alone and inside a plan next to
+    other jobs (deterministic or not) of several probe sizes."""
+    import torch
+    from paper_2012_12686_amd import Job
+    specs = [(64, 3, 90, 5, "gaussian", True), (96, 6, 120, 4, "poisson", False), (128, 7, 150, 3, "poisson", True),
+             (128, 2, 140, 4, "gaussian", False), (192, 3, 220, 2, "gaussian", True), (64, 8, 100, 3, "poisson", True)]
+    jobs, singles = [], []
+    for i, (n, s, lat, npos, loss, det) in enumerate(specs):
+        sc = synth.small_case(seed=800 + i, n=n, n_slices=s, lateral=lat, n_pos=npos, loss=loss, strength=30.0)
+        case = Case(sc, poisson_seed=3 if loss == "poisson" else None)
+        inp, im = case.torch_inputs()
+        singles.append({k: v.cpu().numpy() for k, v in
+                        ctx.loss_grad(_geom(case, deterministic=det), **inp, i_meas=im).items()})
+        jobs.append((Job(geom=_geom(case, deterministic=det), i_meas=im, **inp), det))
+    plan = ctx.plan([j for j, _ in jobs])
+    plan.run()
+    torch.cuda.synchronize()
+    ctx.sync_error()
+    for (j, det), ref in zip(jobs, singles):
+        got = {k: v.cpu().numpy() for k, v in j.out.items()}
+        for k in ("loss", "g_a", "g_b", "g_probe", "g_shift"):
+            if det:
+                assert np.array_equal(got[k], ref[k]), k
+            else:
+                assert rel_l2(got[k], ref[k]) < 1e-5, k
+    plan.close()
