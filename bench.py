@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--workload", default="multislice", choices=["multislice", "batching", "serving"],
                     help="multislice: the 64-slice minibatch (default line); batching: 32 mixed scans, "
                          "batched vs per-job; serving: the request loop")
+    ap.add_argument("--jobs", type=int, default=200, help="serving: number of requests")
+    ap.add_argument("--rate", type=float, default=4.0, help="serving: Poisson arrival rate (jobs/s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a "

@@ -30,6 +30,17 @@ FLAGS = [
 ]
 
 
+# Per-unit extra flags.  Deterministic-mode units fuse multiply-adds only
+# within one source expression, so that the single-call and the batched
+# kernels (different code around the same arithmetic) round identically.
+UNIT_FLAGS = {"ms_det_": ["-ffp-contract=on"]}
+
+
+def unit_flags(src):
+    name = os.path.basename(src)
+    return [f for prefix, fl in UNIT_FLAGS.items() if name.startswith(prefix) for f in fl]
+
+
 def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
@@ -50,7 +61,7 @@ def build(verbose: bool = True, jobs: int = 0) -> str:
         for src in srcs:
             obj = os.path.join(tmp, os.path.basename(src) + ".o")
             objs.append(obj)
-            cmds.append([HIPCC, *FLAGS, "-c", src, "-o", obj])
+            cmds.append([HIPCC, *FLAGS, *unit_flags(src), "-c", src, "-o", obj])
         if verbose:
             print(f"compiling {len(srcs)} units with {jobs} jobs: {' '.join(cmds[0][:-4])} ...", flush=True)
         with cf.ThreadPoolExecutor(jobs) as ex:

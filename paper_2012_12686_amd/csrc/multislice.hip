@@ -322,9 +322,12 @@ adorym_status adorym_plan_create(adorym_ctx* ctx, const adorym_job* jobs, int32_
     PlanClass c{};
     c.n = key.n; c.repr = key.repr; c.staged = key.staged;
     c.l = key.n == 64 ? 4 : 8;
-    const int forced = split_of(ctx, key.n);
-    c.k = forced > 0 ? forced : (key.n == 192 ? 8 : (key.n == 128 ? 4 : 2));
-    if (c.staged) c.k = det_split(key.n);
+    int class_items = 0;
+    for (const adorym_job& j : plan->jobs)
+      if (same(key_of(j), key)) class_items += j.batch;
+    // the context's split if one was set, else the single-call rule applied
+    // to all positions of the class
+    c.k = c.staged ? det_split(key.n) : pick_split(ctx, key.n, class_items);
     // one workgroup per CU: 256 / K groups, a multiple of 8 (one per XCD slot)
     c.groups = std::max(8, (256 / c.k) / 8 * 8);
     std::vector<std::pair<double, int2>> work;

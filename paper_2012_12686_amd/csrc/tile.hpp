@@ -252,12 +252,15 @@ struct TileCfg {
   static constexpr int LOGL = ilog2(L);
   static constexpr int PITCH = N + 8;           // LDS row pitch in float2 (bank spread)
   static constexpr int LDS_FIELD = K == 1 ? N * PITCH : 1;   // LDS transpose buffer (K == 1 only)
-  // K == 1 workgroups have 1024 threads and 128 registers per lane: fence the
-  // scheduler so table loads are not hoisted early; split tiles have room.
-  static constexpr bool FENCE = (K == 1);
-  // Split tiles with 16 values per lane also have the registers to prefetch
-  // the next slice's chunk.
-  static constexpr bool PREFETCH = (K > 1 && R <= 16);
+  // Registers per lane: a SIMD holds 512 per lane, shared by the waves of
+  // the workgroup that land on it (waves are spread over the 4 SIMDs).
+  static constexpr int WAVES_PER_SIMD = (WAVES + 3) / 4;
+  static constexpr int REGS = 512 / WAVES_PER_SIMD;
+  // With 256 or fewer registers the scheduler is fenced so that table loads
+  // are not hoisted early (they spill otherwise); tiles with the full 512
+  // registers and 16 values per lane also prefetch the next slice's chunk.
+  static constexpr bool FENCE = REGS <= 256;
+  static constexpr bool PREFETCH = REGS >= 512 && R <= 16;
   static_assert(N % L == 0 && LINES % RPW == 0 && WAVES >= 1, "bad tile");
 };
 

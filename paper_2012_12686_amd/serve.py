@@ -19,7 +19,8 @@ positions per tick.  Finished jobs leave at tick boundaries.  Two ticks may
 be in flight, so the host prepares tick t+1 while the device runs tick t.
 
 Latency of an iteration = host time from enqueueing its tick to observing
-the tick's completion event; queue wait = arrival to admission.
+the tick's completion event; queue wait = arrival to admission; job time =
+arrival to the completion of its last iteration.
 
 Tilt-series jobs (Sec. S1.D.2) rotate the object to the iteration's angle
 (R), evaluate the loss on the rotated object, take the gradient back with
@@ -29,6 +30,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import sys
 import time
 from typing import Dict, List, Optional, Sequence, Tuple
 
@@ -404,6 +406,7 @@ class Server:
         ctx.sync_error()
         lat = np.array(latencies) * 1e3
         waits = np.array([r.admitted_s - r.arrival_s for r in records]) * 1e3
+        turn = np.array([r.finished_s - r.arrival_s for r in records]) * 1e3
         first = min(r.arrival_s for r in requests) if requests else 0.0
         return {
             "jobs": len(requests), "ticks": n_ticks, "wall_s": wall,
@@ -412,6 +415,8 @@ class Server:
             "p99_iter_ms": float(np.percentile(lat, 99)) if lat.size else math.nan,
             "p50_wait_ms": float(np.percentile(waits, 50)) if waits.size else math.nan,
             "p99_wait_ms": float(np.percentile(waits, 99)) if waits.size else math.nan,
+            "p50_job_ms": float(np.percentile(turn, 50)) if turn.size else math.nan,
+            "p99_job_ms": float(np.percentile(turn, 99)) if turn.size else math.nan,
             "peak_hbm_bytes": peak_used, "peak_jobs": peak_jobs, "records": records,
         }
 
@@ -467,13 +472,19 @@ def bench_serving(args):
     reqs = serving_requests(templates, n_jobs, rate)
     # warm up every kernel the loop uses (and JIT-free first launches)
     warm = [Request(0.0, templates[k], 2) for k in sorted(templates)]
+    log = lambda msg: print(f"[serving] {msg} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    log("templates ready")
     Server(ctx).run(warm, realtime=False)
+    log("warm-up done")
     served = Server(ctx).run(reqs, realtime=True)
+    log(f"served trace done: {served['positions_per_s']:.0f} pos/s, p50 {served['p50_iter_ms']:.1f} ms")
     per_job = Server(ctx, max_jobs=1, batched=False).run(reqs, realtime=True)
-    sat_served = Server(ctx).run([dataclasses.replace(r, arrival_s=0.0) for r in reqs[:max(8, n_jobs // 4)]],
-                                 realtime=False)
-    sat_per_job = Server(ctx, max_jobs=1, batched=False).run(
-        [dataclasses.replace(r, arrival_s=0.0) for r in reqs[:max(8, n_jobs // 4)]], realtime=False)
+    log(f"per-job trace done: p50 {per_job['p50_iter_ms']:.1f} ms, wait p99 {per_job['p99_wait_ms']:.0f} ms")
+    sat = [dataclasses.replace(r, arrival_s=0.0) for r in reqs[:max(8, n_jobs // 4)]]
+    sat_served = Server(ctx).run(sat, realtime=False)
+    log("saturated served done")
+    sat_per_job = Server(ctx, max_jobs=1, batched=False).run(sat, realtime=False)
+    log("saturated per-job done")
     strip = lambda d: {k: v for k, v in d.items() if k != "records"}
     line = {
         "metric": "served multislice fwd+adjoint positions/s; p50/p99 per-iteration latency",
@@ -484,7 +495,7 @@ def bench_serving(args):
                                "20 iterations each (minibatch or angle + Adam), continuous batching"},
         "p50_iter_ms": served["p50_iter_ms"], "p99_iter_ms": served["p99_iter_ms"],
         "served": strip(served), "per_job_fifo": strip(per_job),
-        "saturated": {"jobs": len(reqs[:max(8, n_jobs // 4)]),
+        "saturated": {"jobs": len(sat),
                       "served_positions_per_s": sat_served["positions_per_s"],
                       "per_job_positions_per_s": sat_per_job["positions_per_s"],
                       "speedup": sat_served["positions_per_s"] / sat_per_job["positions_per_s"]},
