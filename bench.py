@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--workload", default="multislice", choices=["multislice", "batching", "serving"],
                     help="multislice: the 64-slice minibatch (default line); batching: 32 mixed scans, "
                          "batched vs per-job; serving: the request loop")
+    ap.add_argument("--ckpt", type=int, default=16, help="slice checkpoint interval of the adjoint")
+    ap.add_argument("--deterministic", action="store_true", help="FP64 ordered object-gradient sums")
     ap.add_argument("--jobs", type=int, default=200, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=4.0, help="serving: Poisson arrival rate (jobs/s)")
     args = ap.parse_args()
@@ -134,7 +136,7 @@ def main():
     mb = sc.minibatch
     n_mb = len(sc.positions) // mb
     ctx = Context(dev)
-    geom = Geometry.from_scan(sc)
+    geom = Geometry.from_scan(sc, ckpt_every=args.ckpt, deterministic=args.deterministic)
     if args.split:
         ctx.set_split(n, args.split)
 
@@ -188,7 +190,7 @@ def main():
     value = mb * args.steps / elapsed
 
     kern_avg_s = kern_ms / max(kern_n, 1) / 1e3
-    bytes_launch = algorithmic_bytes_per_position(n, s) * mb
+    bytes_launch = algorithmic_bytes_per_position(n, s, args.ckpt) * mb
     achieved_gbs = bytes_launch / kern_avg_s / 1e9
     flops_launch = algorithmic_flops_per_position(n, s) * mb
     achieved_tflops = flops_launch / kern_avg_s / 1e12

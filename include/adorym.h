@@ -73,17 +73,16 @@ enum {
   ADORYM_ACCUMULATE_GRADS = 1u, /* add into the gradient arrays instead of overwriting */
   ADORYM_DETERMINISTIC = 2u     /* bitwise-reproducible object gradients (see below)  */
 };
-/* Deterministic mode.  By default each position scatters its contribution
- * to dL/d(object) with float atomics, so the order of the additions (and the
- * last bits of the result) depends on scheduling.  With ADORYM_DETERMINISTIC
- * the contributions are staged in the workspace (B*S*2*N*N*4 more bytes) and
- * a second kernel sums them for every voxel over the positions in index
- * order, in FP64, rounding once to float32.  Loss, probe and shift gradients
- * are always reduced in a fixed order.  Deterministic calls use one fixed
- * split per probe size (k = 1 for N <= 96, 4 for N = 128, 8 for N = 192;
- * adorym_set_split does not apply), so every output is bitwise
- * reproducible: run to run, and between a single call and the same job
- * inside a batched plan next to other jobs. */
+/* Gradient accumulation.  Each position stores its contribution to
+ * dL/d(object) in the workspace (B*S*2*N*N*4 bytes, no atomics) and a second
+ * kernel sums, for every voxel, the contributions of the positions in index
+ * order in FP64, rounding once to float32; loss, probe and shift gradients
+ * are also reduced in a fixed order.  Every call is therefore reproducible
+ * bit for bit for a given split.  ADORYM_DETERMINISTIC additionally fixes
+ * the split per probe size (k = 1 for N <= 96, 4 for N = 128, 8 for
+ * N = 192; adorym_set_split does not apply), so that results are also the
+ * same bits between a single call and the same job inside a batched plan
+ * next to other jobs, whatever split other calls use. */
 
 /* Geometry and options of one scan. */
 typedef struct {
@@ -112,17 +111,20 @@ adorym_status adorym_set_stream(adorym_ctx* ctx, void* stream);
 /* Probe sizes with a kernel: returns 1 if N is supported. */
 int adorym_supports_n(int32_t n);
 
-/* Bytes of device workspace adorym_forward / adorym_loss_grad need for a
- * batch of `batch` positions (probe spectrum, per-position loss, shift and
- * probe partials, slice checkpoints every ckpt_every slices, the
- * exchange buffers of split workgroups and, in deterministic mode, the
- * staged object-gradient contributions).  0 on bad input. */
+/* Bytes of device workspace adorym_loss_grad needs for a batch of `batch`
+ * positions (probe spectrum, per-position loss, shift and probe partials,
+ * slice checkpoints every ckpt_every slices, the exchange buffers of split
+ * workgroups and the staged object-gradient contributions).  0 on bad
+ * input. */
 size_t adorym_workspace_size(const adorym_geom* g, int32_t batch);
+/* The smaller workspace adorym_forward needs (probe spectrum, exchange
+ * buffers and counters only); adorym_workspace_size also suffices. */
+size_t adorym_forward_workspace_size(const adorym_geom* g, int32_t batch);
 
 /* Forward model (Alg. 1 without refinement of anything): predicted
  * far-field intensities |Psi|^2, float32 [B][N][N], zero frequency at
  * (N/2, N/2).  obj_a/obj_b: delta/beta or real/imag [S][Ly][Lx];
- * probe complex [N][N].  Workspace of adorym_workspace_size bytes. */
+ * probe complex [N][N].  Workspace of adorym_forward_workspace_size bytes. */
 adorym_status adorym_forward(adorym_ctx* ctx, const adorym_geom* g,
                              const float* obj_a, const float* obj_b, const float* probe,
                              const int32_t* corner, const float* shift, int32_t batch,

@@ -57,6 +57,7 @@ SIGNATURES = {
     "adorym_set_stream": (ctypes.c_int, [_P, _P]),
     "adorym_supports_n": (ctypes.c_int, [ctypes.c_int32]),
     "adorym_workspace_size": (ctypes.c_size_t, [_GP, ctypes.c_int32]),
+    "adorym_forward_workspace_size": (ctypes.c_size_t, [_GP, ctypes.c_int32]),
     "adorym_forward": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t]),
     "adorym_loss_grad": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t,
                                         _P, _P, _P, _P, _P, _P]),

@@ -106,11 +106,13 @@ class Context:
         return ms.value, cnt.value
 
     # --------------------------------------------------------------- calls
-    def workspace_size(self, geom: Geometry, batch: int) -> int:
-        return int(load().adorym_workspace_size(ctypes.byref(geom.to_c()), batch))
+    def workspace_size(self, geom: Geometry, batch: int, forward: bool = False) -> int:
+        """Workspace bytes of a loss_grad call (forward=True: of a forward call)."""
+        fn = load().adorym_forward_workspace_size if forward else load().adorym_workspace_size
+        return int(fn(ctypes.byref(geom.to_c()), batch))
 
-    def workspace(self, geom: Geometry, batch: int) -> torch.Tensor:
-        return torch.empty(self.workspace_size(geom, batch), dtype=torch.uint8, device=self.device)
+    def workspace(self, geom: Geometry, batch: int, forward: bool = False) -> torch.Tensor:
+        return torch.empty(self.workspace_size(geom, batch, forward), dtype=torch.uint8, device=self.device)
 
     def _check_inputs(self, geom, obj_a, obj_b, probe, corner, shift):
         n, s, ly, lx = geom.n, geom.n_slices, geom.obj_ny, geom.obj_nx
@@ -132,7 +134,7 @@ class Context:
         self._bind_stream()
         b = self._check_inputs(geom, obj_a, obj_b, probe, corner, shift)
         out = out if out is not None else torch.empty((b, geom.n, geom.n), dtype=torch.float32, device=self.device)
-        ws = workspace if workspace is not None else self.workspace(geom, b)
+        ws = workspace if workspace is not None else self.workspace(geom, b, forward=True)
         st = load().adorym_forward(self._ctx, ctypes.byref(geom.to_c()), _ptr(obj_a), _ptr(obj_b),
                                    _ptr(torch.view_as_real(probe)), _ptr(corner), _ptr(shift), b, _ptr(out),
                                    _ptr(ws), ws.numel())

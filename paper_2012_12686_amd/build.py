@@ -4,7 +4,7 @@ Usage: ``python -m paper_2012_12686_amd.build`` (also run by
 ``__graft_entry__.build()``).  Compiles every ``csrc/*.hip`` unit in
 parallel and links them into one shared library next to this file.
 Packed-FP32 instructions are disabled (``-packed-fp32-ops``); float atomics
-use the hardware instructions.
+use the hardware instructions; multiply-add contraction is per expression.
 """
 from __future__ import annotations
 
@@ -25,20 +25,12 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC",
     f"--offload-arch={ARCH}",
     "-munsafe-fp-atomics",
+    # multiply-adds fused only within one source expression, so that kernels
+    # with different code around the same arithmetic round identically
+    "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
-
-
-# Per-unit extra flags.  Deterministic-mode units fuse multiply-adds only
-# within one source expression, so that the single-call and the batched
-# kernels (different code around the same arithmetic) round identically.
-UNIT_FLAGS = {"ms_det_": ["-ffp-contract=on"]}
-
-
-def unit_flags(src):
-    name = os.path.basename(src)
-    return [f for prefix, fl in UNIT_FLAGS.items() if name.startswith(prefix) for f in fl]
 
 
 def sources():
@@ -61,7 +53,7 @@ def build(verbose: bool = True, jobs: int = 0) -> str:
         for src in srcs:
             obj = os.path.join(tmp, os.path.basename(src) + ".o")
             objs.append(obj)
-            cmds.append([HIPCC, *FLAGS, *unit_flags(src), "-c", src, "-o", obj])
+            cmds.append([HIPCC, *FLAGS, "-c", src, "-o", obj])
         if verbose:
             print(f"compiling {len(srcs)} units with {jobs} jobs: {' '.join(cmds[0][:-4])} ...", flush=True)
         with cf.ThreadPoolExecutor(jobs) as ex:

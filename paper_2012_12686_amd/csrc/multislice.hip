@@ -5,40 +5,32 @@
 
 using namespace adorym_ms;
 
-extern template ADORYM_RUN_SIGNATURE(64, 4, 1, false);
-extern template ADORYM_BATCHED_SIGNATURE(64, 4, 1, false);
-extern template ADORYM_RUN_SIGNATURE(64, 4, 2, false);
-extern template ADORYM_BATCHED_SIGNATURE(64, 4, 2, false);
-extern template ADORYM_RUN_SIGNATURE(64, 4, 4, false);
-extern template ADORYM_BATCHED_SIGNATURE(64, 4, 4, false);
-extern template ADORYM_RUN_SIGNATURE(96, 8, 1, false);
-extern template ADORYM_BATCHED_SIGNATURE(96, 8, 1, false);
-extern template ADORYM_RUN_SIGNATURE(96, 8, 2, false);
-extern template ADORYM_BATCHED_SIGNATURE(96, 8, 2, false);
-extern template ADORYM_RUN_SIGNATURE(96, 8, 4, false);
-extern template ADORYM_BATCHED_SIGNATURE(96, 8, 4, false);
-extern template ADORYM_RUN_SIGNATURE(128, 8, 1, false);
-extern template ADORYM_BATCHED_SIGNATURE(128, 8, 1, false);
-extern template ADORYM_RUN_SIGNATURE(128, 8, 2, false);
-extern template ADORYM_BATCHED_SIGNATURE(128, 8, 2, false);
-extern template ADORYM_RUN_SIGNATURE(128, 8, 4, false);
-extern template ADORYM_BATCHED_SIGNATURE(128, 8, 4, false);
-extern template ADORYM_RUN_SIGNATURE(128, 8, 8, false);
-extern template ADORYM_BATCHED_SIGNATURE(128, 8, 8, false);
-extern template ADORYM_RUN_SIGNATURE(192, 8, 2, false);
-extern template ADORYM_BATCHED_SIGNATURE(192, 8, 2, false);
-extern template ADORYM_RUN_SIGNATURE(192, 8, 4, false);
-extern template ADORYM_BATCHED_SIGNATURE(192, 8, 4, false);
-extern template ADORYM_RUN_SIGNATURE(192, 8, 8, false);
-extern template ADORYM_BATCHED_SIGNATURE(192, 8, 8, false);
-extern template ADORYM_RUN_SIGNATURE(64, 4, 1, true);
-extern template ADORYM_BATCHED_SIGNATURE(64, 4, 1, true);
-extern template ADORYM_RUN_SIGNATURE(96, 8, 1, true);
-extern template ADORYM_BATCHED_SIGNATURE(96, 8, 1, true);
-extern template ADORYM_RUN_SIGNATURE(128, 8, 4, true);
-extern template ADORYM_BATCHED_SIGNATURE(128, 8, 4, true);
-extern template ADORYM_RUN_SIGNATURE(192, 8, 8, true);
-extern template ADORYM_BATCHED_SIGNATURE(192, 8, 8, true);
+extern template ADORYM_RUN_SIGNATURE(64, 4, 1);
+extern template ADORYM_BATCHED_SIGNATURE(64, 4, 1);
+extern template ADORYM_RUN_SIGNATURE(64, 4, 2);
+extern template ADORYM_BATCHED_SIGNATURE(64, 4, 2);
+extern template ADORYM_RUN_SIGNATURE(64, 4, 4);
+extern template ADORYM_BATCHED_SIGNATURE(64, 4, 4);
+extern template ADORYM_RUN_SIGNATURE(96, 8, 1);
+extern template ADORYM_BATCHED_SIGNATURE(96, 8, 1);
+extern template ADORYM_RUN_SIGNATURE(96, 8, 2);
+extern template ADORYM_BATCHED_SIGNATURE(96, 8, 2);
+extern template ADORYM_RUN_SIGNATURE(96, 8, 4);
+extern template ADORYM_BATCHED_SIGNATURE(96, 8, 4);
+extern template ADORYM_RUN_SIGNATURE(128, 8, 1);
+extern template ADORYM_BATCHED_SIGNATURE(128, 8, 1);
+extern template ADORYM_RUN_SIGNATURE(128, 8, 2);
+extern template ADORYM_BATCHED_SIGNATURE(128, 8, 2);
+extern template ADORYM_RUN_SIGNATURE(128, 8, 4);
+extern template ADORYM_BATCHED_SIGNATURE(128, 8, 4);
+extern template ADORYM_RUN_SIGNATURE(128, 8, 8);
+extern template ADORYM_BATCHED_SIGNATURE(128, 8, 8);
+extern template ADORYM_RUN_SIGNATURE(192, 8, 2);
+extern template ADORYM_BATCHED_SIGNATURE(192, 8, 2);
+extern template ADORYM_RUN_SIGNATURE(192, 8, 4);
+extern template ADORYM_BATCHED_SIGNATURE(192, 8, 4);
+extern template ADORYM_RUN_SIGNATURE(192, 8, 8);
+extern template ADORYM_BATCHED_SIGNATURE(192, 8, 8);
 extern template ADORYM_PARAMS_SIGNATURE(64, 4);
 extern template ADORYM_PROLOGUE_SIGNATURE(64, 4);
 extern template ADORYM_EPILOGUE_SIGNATURE(64, 4);
@@ -82,19 +74,10 @@ adorym_status dispatch(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
                        const int32_t* corner, const float* shift, int batch, const float* i_meas, void* ws,
                        double* loss, float* g_a, float* g_b, float* g_probe, float* g_shift, float* intensity,
                        bool with_loss) {
-  const int k = pick_split(ctx, g->n, batch);
-#define ADORYM_RUN_S(N_, L_, K_, S_) \
-  return run<N_, L_, K_, S_>(ctx, g, a, b, probe, corner, shift, batch, i_meas, ws, loss, g_a, g_b, g_probe, \
-                             g_shift, intensity, with_loss)
-#define ADORYM_RUN(N_, L_, K_) ADORYM_RUN_S(N_, L_, K_, false)
-  if (staged_call(g, with_loss, g_a)) {
-    switch (g->n) {
-      case 64: ADORYM_RUN_S(64, 4, det_split(64), true);
-      case 96: ADORYM_RUN_S(96, 8, det_split(96), true);
-      case 128: ADORYM_RUN_S(128, 8, det_split(128), true);
-      case 192: ADORYM_RUN_S(192, 8, det_split(192), true);
-    }
-  }
+  const int k = (g->flags & ADORYM_DETERMINISTIC) ? det_split(g->n) : pick_split(ctx, g->n, batch);
+#define ADORYM_RUN(N_, L_, K_) \
+  return run<N_, L_, K_>(ctx, g, a, b, probe, corner, shift, batch, i_meas, ws, loss, g_a, g_b, g_probe, g_shift, \
+                         intensity, with_loss)
   if (g->n == 64) {
     switch (k) {
       case 1: ADORYM_RUN(64, 4, 1);
@@ -122,7 +105,6 @@ adorym_status dispatch(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
     }
   }
 #undef ADORYM_RUN
-#undef ADORYM_RUN_S
   return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size / split");
 }
 
@@ -132,7 +114,7 @@ adorym_status dispatch(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
 // ----------------------------------------------------------------------------
 struct PlanClass {
   int n, l, k, groups, repr;
-  bool staged;          // deterministic-mode jobs (staged object gradients)
+  bool det;             // deterministic-mode jobs (fixed split)
   int n_items;
   int2* items;          // device [(job, position)] sorted by decreasing cost
   int* state;           // device: ticket, then mailbox[groups], counters[groups], xcc[groups*K]
@@ -184,16 +166,10 @@ void class_launch(const PlanClass& c, const MsParams* d_params, int* err, hipStr
   int* mailbox = c.state + 1;
   int* counters = mailbox + c.groups;
   int* xcc = counters + c.groups;
-#define ADORYM_BATCH_S(N_, L_, K_, S_) \
-  launch_batched<N_, L_, K_, S_>(d_params, c.items, c.n_items, ticket, mailbox, counters, xcc, c.xbuf, err, \
-                                 c.groups, c.repr, st)
-#define ADORYM_BATCH(N_, L_, K_) ADORYM_BATCH_S(N_, L_, K_, false)
-  if (c.staged) {
-    if (c.n == 64) ADORYM_BATCH_S(64, 4, det_split(64), true);
-    else if (c.n == 96) ADORYM_BATCH_S(96, 8, det_split(96), true);
-    else if (c.n == 128) ADORYM_BATCH_S(128, 8, det_split(128), true);
-    else ADORYM_BATCH_S(192, 8, det_split(192), true);
-  } else if (c.n == 64) {
+#define ADORYM_BATCH(N_, L_, K_) \
+  launch_batched<N_, L_, K_>(d_params, c.items, c.n_items, ticket, mailbox, counters, xcc, c.xbuf, err, c.groups, \
+                             c.repr, st)
+  if (c.n == 64) {
     if (c.k == 1) ADORYM_BATCH(64, 4, 1); else if (c.k == 2) ADORYM_BATCH(64, 4, 2); else ADORYM_BATCH(64, 4, 4);
   } else if (c.n == 96) {
     if (c.k == 1) ADORYM_BATCH(96, 8, 1); else if (c.k == 2) ADORYM_BATCH(96, 8, 2); else ADORYM_BATCH(96, 8, 4);
@@ -206,7 +182,6 @@ void class_launch(const PlanClass& c, const MsParams* d_params, int* err, hipStr
     if (c.k == 2) ADORYM_BATCH(192, 8, 2); else if (c.k == 4) ADORYM_BATCH(192, 8, 4); else ADORYM_BATCH(192, 8, 8);
   }
 #undef ADORYM_BATCH
-#undef ADORYM_BATCH_S
 }
 
 }  // namespace
@@ -248,6 +223,11 @@ size_t adorym_workspace_size(const adorym_geom* g, int32_t batch) {
   return ws_layout(g, batch).total;
 }
 
+size_t adorym_forward_workspace_size(const adorym_geom* g, int32_t batch) {
+  if (!g || batch < 1 || g->n < 1 || g->n_slices < 1 || g->ckpt_every < 1) return 0;
+  return ws_layout(g, batch, true).total;
+}
+
 adorym_status adorym_forward(adorym_ctx* ctx, const adorym_geom* g, const float* obj_a, const float* obj_b,
                              const float* probe, const int32_t* corner, const float* shift, int32_t batch,
                              float* intensity, void* workspace, size_t ws_bytes) {
@@ -255,7 +235,8 @@ adorym_status adorym_forward(adorym_ctx* ctx, const adorym_geom* g, const float*
   if (st != ADORYM_OK) return st;
   if (!obj_a || !obj_b || !probe || !corner || !shift || !intensity || !workspace)
     return set_err(ctx, ADORYM_EINVAL, "NULL array argument");
-  if (ws_bytes < adorym_workspace_size(g, batch)) return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
+  if (ws_bytes < adorym_forward_workspace_size(g, batch))
+    return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
   return dispatch(ctx, g, obj_a, obj_b, probe, corner, shift, batch, nullptr, workspace, nullptr, nullptr, nullptr,
                   nullptr, nullptr, intensity, false);
 }
@@ -308,9 +289,11 @@ adorym_status adorym_plan_create(adorym_ctx* ctx, const adorym_job* jobs, int32_
     if (st != ADORYM_OK) { delete plan; return st; }
   }
   // classes: one per (probe size, object representation, deterministic mode)
-  struct Key { int n, repr; bool staged; };
-  auto key_of = [](const adorym_job& j) { return Key{j.g.n, j.g.obj_repr, staged_call(&j.g, true, j.g_a)}; };
-  auto same = [](const Key& x, const Key& y) { return x.n == y.n && x.repr == y.repr && x.staged == y.staged; };
+  struct Key { int n, repr; bool det; };
+  auto key_of = [](const adorym_job& j) {
+    return Key{j.g.n, j.g.obj_repr, (j.g.flags & ADORYM_DETERMINISTIC) != 0};
+  };
+  auto same = [](const Key& x, const Key& y) { return x.n == y.n && x.repr == y.repr && x.det == y.det; };
   std::vector<Key> keys;
   for (const adorym_job& j : plan->jobs) {
     bool seen = false;
@@ -320,14 +303,14 @@ adorym_status adorym_plan_create(adorym_ctx* ctx, const adorym_job* jobs, int32_
   plan->params.resize(n_jobs);
   for (const Key& key : keys) {
     PlanClass c{};
-    c.n = key.n; c.repr = key.repr; c.staged = key.staged;
+    c.n = key.n; c.repr = key.repr; c.det = key.det;
     c.l = key.n == 64 ? 4 : 8;
     int class_items = 0;
     for (const adorym_job& j : plan->jobs)
       if (same(key_of(j), key)) class_items += j.batch;
     // the context's split if one was set, else the single-call rule applied
     // to all positions of the class
-    c.k = c.staged ? det_split(key.n) : pick_split(ctx, key.n, class_items);
+    c.k = c.det ? det_split(key.n) : pick_split(ctx, key.n, class_items);
     // one workgroup per CU: 256 / K groups, a multiple of 8 (one per XCD slot)
     c.groups = std::max(8, (256 / c.k) / 8 * 8);
     std::vector<std::pair<double, int2>> work;

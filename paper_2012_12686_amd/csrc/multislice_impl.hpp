@@ -11,8 +11,11 @@
 //   and the reverse sweep giving dL/d(object), dL/d(probe), dL/d(shift).
 // Steps follow Alg. 1 (TakeObjectChunk, FourierShift, MultislicePropagate,
 // FarFieldPropagate).  The wave stays in registers for the whole sweep; the
-// object is read straight from HBM slice by slice and its gradient is
-// scattered with float atomics.  The reverse sweep rebuilds the wave
+// object is read straight from HBM slice by slice.  Each position stores
+// its contribution to the object gradient in its own staging planes (plain
+// stores, no atomics); a second kernel sums the contributions of all
+// positions for every voxel in position order, in FP64.  The reverse sweep
+// rebuilds the wave
 // entering each slice by stepping the forward recursion backwards
 // (psi_{j-1} = t_{j-1}^{-1} P^H psi_j), and re-anchors it on checkpoints of
 // the forward sweep stored every ckpt_every slices.
@@ -49,8 +52,8 @@ struct MsParams {
   float* intensity;        // [B][N][N] or null
   float* g_a;              // [S][Ly][Lx] or null
   float* g_b;
-  float* gstage;           // [B][S][2][N][N] staged object-gradient contributions
-                           // (deterministic mode), else null
+  float* gstage;           // [B][S][2][N][N] per-position object-gradient contributions,
+                           // null when no object gradient is wanted
   float2* ckpt;            // [B][nslots][K][R*THREADS]
   float2* gacc;            // [B][N][N] natural, or null (probe-gradient partials)
   double* loss_part;       // [B][K]
@@ -169,18 +172,13 @@ template <class C, bool ROW>
 __device__ __forceinline__ float chunk_load(rsrc_t r, const ChunkOffsets& o, int m) {
   return ROW ? bload(r, o.row_off + 4 * C::L * m, 0) : bload(r, o.col_off, (uint32_t)m * o.col_step);
 }
-template <class C, bool ROW>
-__device__ __forceinline__ void chunk_atomic_add(rsrc_t r, const ChunkOffsets& o, int m, float v) {
-  if (ROW) batomic_add(r, v, o.row_off + 4 * C::L * m, 0);
-  else batomic_add(r, v, o.col_off, (uint32_t)m * o.col_step);
-}
 
 __device__ __forceinline__ rsrc_t slice_rsrc(const float* base, int j, const ChunkOffsets& o) {
   return make_rsrc(base + (size_t)j * (o.slice_bytes / 4), o.slice_bytes);
 }
 
-// Deterministic mode: this position's contribution to one gradient plane of
-// slice j, chunk-local [N][N] (row y, column x), plain stores.
+// This position's contribution to one object-gradient plane of slice j,
+// chunk-local [N][N] (row y, column x), plain stores.
 template <class C>
 __device__ __forceinline__ rsrc_t stage_rsrc(const MsParams& P, int b, int j, int comp) {
   constexpr int NN = C::N * C::N;
@@ -278,9 +276,8 @@ __device__ __forceinline__ void forward_slice(float2 (&v)[C::R], float (&ca)[C::
 //        lam = dL/dphi_j; ca/cb = slice j's object values when prefetching
 //   out: psi = phi_{j-1} = P^H psi_j, lam = dL/dphi_{j-1} = P^H conj(t_j) lam;
 //        ca/cb = slice j-1's object values when prefetching
-// STAGED (deterministic mode): the slice gradient is stored to this
-// position's staging planes instead of being added to the object gradient.
-template <class C, int REPR, bool ROW, bool STAGED>
+// The slice gradient goes to this position's staging planes.
+template <class C, int REPR, bool ROW>
 __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam)[C::R], float (&ca)[C::R],
                                                float (&cb)[C::R], const MsParams& P, MsShared<C>& sh, Work<C>& wk,
                                                const ChunkOffsets& o, int j) {
@@ -288,15 +285,9 @@ __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam
   const bool anchored = is_ckpt(j, P.S, P.ckpt_every);
   if (anchored) field_load<C>(psi, ckpt_ptr<C>(P, wk, ckpt_slot(j, P.S, P.ckpt_every)), ln);  // psi_j exactly
   if (!C::PREFETCH) load_chunk<C, ROW>(ca, cb, P, o, j);
-  const bool grads = STAGED || P.g_a != nullptr;
-  rsrc_t rga, rgb;
-  if constexpr (STAGED) {
-    rga = stage_rsrc<C>(P, wk.b, j, 0);
-    rgb = stage_rsrc<C>(P, wk.b, j, 1);
-  } else {
-    rga = grads ? slice_rsrc(P.g_a, j, o) : make_rsrc(P.a, 0);
-    rgb = grads ? slice_rsrc(P.g_b, j, o) : make_rsrc(P.b, 0);
-  }
+  const bool grads = P.gstage != nullptr;
+  const rsrc_t rga = grads ? stage_rsrc<C>(P, wk.b, j, 0) : make_rsrc(P.a, 0);
+  const rsrc_t rgb = grads ? stage_rsrc<C>(P, wk.b, j, 1) : make_rsrc(P.b, 0);
   const float kdz = P.kdz;
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
@@ -316,13 +307,8 @@ __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam
         ga = z.x;
         gb = z.y;
       }
-      if constexpr (STAGED) {
-        stage_store<C, ROW>(rga, ln, m, ga);
-        stage_store<C, ROW>(rgb, ln, m, gb);
-      } else {
-        chunk_atomic_add<C, ROW>(rga, o, m, ga);
-        chunk_atomic_add<C, ROW>(rgb, o, m, gb);
-      }
+      stage_store<C, ROW>(rga, ln, m, ga);
+      stage_store<C, ROW>(rgb, ln, m, gb);
     }
     lam[m] = cmulc(l, t);                              // conj(t) lam = dL/dpsi_j
     psi[m] = in_wave;
@@ -357,7 +343,7 @@ __device__ __forceinline__ void group_of_block(int& b, int& part) {
 
 // Everything one workgroup does for its part of one position.  wk.b, wk.part
 // and the exchange state wk.x are set by the caller.
-template <class C, int REPR, bool LOSS, bool STAGED>
+template <class C, int REPR, bool LOSS>
 __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>& sh, Work<C>& wk) {
   const int b = wk.b, part = wk.part;
   const Lane<C>& ln = wk.ln;
@@ -457,15 +443,15 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
   int j = P.S - 1;
   // the forward sweep left slice S-1's object values in ca/cb
   if (!last_row) {
-    backward_slice<C, REPR, false, STAGED>(psi, v, ca, cb, P, sh, wk, o, j);
+    backward_slice<C, REPR, false>(psi, v, ca, cb, P, sh, wk, o, j);
     --j;
   }
   // now slice j is even (ROW); pairs (j ROW, j-1 COL) down to slice 0
   for (; j >= 1; j -= 2) {
-    backward_slice<C, REPR, true, STAGED>(psi, v, ca, cb, P, sh, wk, o, j);
-    backward_slice<C, REPR, false, STAGED>(psi, v, ca, cb, P, sh, wk, o, j - 1);
+    backward_slice<C, REPR, true>(psi, v, ca, cb, P, sh, wk, o, j);
+    backward_slice<C, REPR, false>(psi, v, ca, cb, P, sh, wk, o, j - 1);
   }
-  if (j == 0) backward_slice<C, REPR, true, STAGED>(psi, v, ca, cb, P, sh, wk, o, 0);
+  if (j == 0) backward_slice<C, REPR, true>(psi, v, ca, cb, P, sh, wk, o, 0);
   // v = dL/d(shifted probe) in ROW layout, natural order.
 
   // FourierShift adjoint: G = DFT(g_pb) in COL layout (kx line, ky spectral).
@@ -499,7 +485,7 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
 }
 
 // One group of K workgroups per position of a single job.
-template <class C, int REPR, bool LOSS, bool STAGED>
+template <class C, int REPR, bool LOSS>
 __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
   __shared__ MsShared<C> sh;
   int b, part;
@@ -514,14 +500,14 @@ __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
   const int cy = P.corner[2 * b], cx = P.corner[2 * b + 1];
   const bool inside = cy >= 0 && cx >= 0 && cy + C::N <= P.Ly && cx + C::N <= P.Lx;
   if (C::K > 1 && inside) exchange_init<C::K>(wk.x, P.xcc + b * C::K, part);
-  process_position<C, REPR, LOSS, STAGED>(P, sh, wk);
+  process_position<C, REPR, LOSS>(P, sh, wk);
 }
 
 // Persistent multi-job kernel: groups of K workgroups take (job, position)
 // items from a device queue until it is empty.  Every member of a group sees
 // the same ticket (member 0 draws it and publishes it behind the group
 // barrier), so all of them leave the loop together.
-template <class C, int REPR, bool STAGED>
+template <class C, int REPR>
 __global__ void __launch_bounds__(C::THREADS) multislice_batched_kernel(const MsParams* __restrict__ jobs,
                                                                         const int2* __restrict__ items,
                                                                         int n_items, int* ticket, int* mailbox,
@@ -555,7 +541,7 @@ __global__ void __launch_bounds__(C::THREADS) multislice_batched_kernel(const Ms
     if (t >= n_items) break;
     const int2 it = items[t];
     wk.b = it.y;
-    process_position<C, REPR, true, STAGED>(jobs[it.x], sh, wk);
+    process_position<C, REPR, true>(jobs[it.x], sh, wk);
   }
 }
 
@@ -590,37 +576,52 @@ static __global__ void reset_ints_kernel(int* p, int n) {
 }
 
 // Sums of the per-position partials: probe-gradient spectrum (natural
-// order, fixed order over positions), loss (block 0), shift gradients.
-static __global__ void reduce_partials_kernel(const float2* __restrict__ gacc, int nb, int nn, float2* __restrict__ gsum,
-                                       const double* __restrict__ loss_part, const double* __restrict__ gs_part,
-                                       int k, double* __restrict__ loss, float* __restrict__ g_shift,
-                                       int accumulate) {
+// order, positions in index order), loss (block 0: a fixed-order strided
+// sum per thread, then a fixed-order tree), shift gradients (block 0).
+static __global__ void __launch_bounds__(256) reduce_partials_kernel(
+    const float2* __restrict__ gacc, int nb, int nn, float2* __restrict__ gsum, const double* __restrict__ loss_part,
+    const double* __restrict__ gs_part, int k, double* __restrict__ loss, float* __restrict__ g_shift,
+    int accumulate) {
+  __shared__ double red[256];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (gacc && i < nn) {
     float sx = 0.f, sy = 0.f;
-    for (int bb = 0; bb < nb; ++bb) {
+    int bb = 0;
+    for (; bb + 8 <= nb; bb += 8) {           // eight loads in flight, added in order
+      float2 t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = gacc[(size_t)(bb + u) * nn + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) { sx += t[u].x; sy += t[u].y; }
+    }
+    for (; bb < nb; ++bb) {
       const float2 t = gacc[(size_t)bb * nn + i];
       sx += t.x;
       sy += t.y;
     }
     gsum[i] = make_float2(sx, sy);
   }
-  if (blockIdx.x == 0) {
-    if (threadIdx.x == 0 && loss) {
-      double s = 0.0;
-      for (int t = 0; t < nb * k; ++t) s += loss_part[t];
-      *loss = s;
+  if (blockIdx.x != 0) return;
+  if (loss) {
+    double s = 0.0;
+    for (int t = threadIdx.x; t < nb * k; t += blockDim.x) s += loss_part[t];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+      if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
     }
-    if (g_shift) {
-      for (int bb = threadIdx.x; bb < nb; bb += blockDim.x) {
-        double sy = 0.0, sx = 0.0;
-        for (int p = 0; p < k; ++p) {
-          sy += gs_part[2 * (bb * k + p)];
-          sx += gs_part[2 * (bb * k + p) + 1];
-        }
-        if (accumulate) { g_shift[2 * bb] += (float)sy; g_shift[2 * bb + 1] += (float)sx; }
-        else { g_shift[2 * bb] = (float)sy; g_shift[2 * bb + 1] = (float)sx; }
+    if (threadIdx.x == 0) *loss = red[0];
+  }
+  if (g_shift) {
+    for (int bb = threadIdx.x; bb < nb; bb += blockDim.x) {
+      double sy = 0.0, sx = 0.0;
+      for (int p = 0; p < k; ++p) {
+        sy += gs_part[2 * (bb * k + p)];
+        sx += gs_part[2 * (bb * k + p) + 1];
       }
+      if (accumulate) { g_shift[2 * bb] += (float)sy; g_shift[2 * bb + 1] += (float)sx; }
+      else { g_shift[2 * bb] = (float)sy; g_shift[2 * bb + 1] = (float)sx; }
     }
   }
 }
@@ -656,33 +657,33 @@ __global__ void __launch_bounds__(C::THREADS) probe_grad_kernel(const float2* __
   }
 }
 
-static __global__ void fill_kernel(float* __restrict__ p, size_t n, float val) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) p[i] = val;
-}
 
-// Deterministic object gradient.  One workgroup per 64 x 16 voxel tile of
-// one slice: it lists, in index order, the positions whose chunk covers part
-// of the tile (chunks outside the object are skipped, as in the multislice
-// kernel), then every voxel sums the staged contributions of those positions
-// in that order in FP64 and is written once (rounded to float32).
-constexpr int kDetTx = 64, kDetTy = 16, kDetList = 2048;
-static __global__ void __launch_bounds__(256) det_grad_kernel(const float* __restrict__ stage,
-                                                              const int32_t* __restrict__ corner, int n, int B,
-                                                              int S, int Ly, int Lx, float* __restrict__ g_a,
-                                                              float* __restrict__ g_b, int accumulate) {
-  __shared__ int lb[kDetList], lcy[kDetList], lcx[kDetList];
+// Object gradient from the staged per-position contributions.  One
+// workgroup per 64 x 16 voxel tile of one slice: it lists, in index order,
+// the positions whose chunk overlaps the tile (chunks outside the object are
+// skipped, as in the multislice kernel); every voxel then sums the
+// contributions of those positions in that order in FP64 and is written once,
+// rounded to float32.  Loads of kRedUnroll positions are issued together;
+// voxels a chunk does not cover read 0 through the buffer range check (an
+// added +0.0 leaves an FP64 sum unchanged).
+constexpr int kRedTx = 64, kRedTy = 16, kRedList = 2048, kRedUnroll = 8;
+constexpr uint32_t kRedOutside = 0xFFFFFFF0u;   // beyond any plane: reads 0
+static __global__ void __launch_bounds__(256) grad_reduce_kernel(const float* __restrict__ stage,
+                                                                 const int32_t* __restrict__ corner, int n, int B,
+                                                                 int S, int Ly, int Lx, float* __restrict__ g_a,
+                                                                 float* __restrict__ g_b, int accumulate) {
+  __shared__ int lb[kRedList], lcy[kRedList], lcx[kRedList];
   __shared__ int wave_cnt[4];
+  constexpr int RY = kRedTy / 4;                  // rows per thread
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tx0 = blockIdx.x * kDetTx, ty0 = blockIdx.y * kDetTy, j = blockIdx.z;
+  const int tx0 = blockIdx.x * kRedTx, ty0 = blockIdx.y * kRedTy, j = blockIdx.z;
   const int x = tx0 + lane;
-  const size_t nn = (size_t)n * n;
-  double acc_a[kDetTy / 4], acc_b[kDetTy / 4];
+  const uint32_t plane_bytes = (uint32_t)(n * n * 4);
+  double acc_a[RY], acc_b[RY];
 #pragma unroll
-  for (int r = 0; r < kDetTy / 4; ++r) acc_a[r] = acc_b[r] = 0.0;
-  for (int w0 = 0; w0 < B; w0 += kDetList) {
-    const int w1 = min(B, w0 + kDetList);
+  for (int r = 0; r < RY; ++r) acc_a[r] = acc_b[r] = 0.0;
+  for (int w0 = 0; w0 < B; w0 += kRedList) {
+    const int w1 = min(B, w0 + kRedList);
     int count = 0;                                  // uniform over the workgroup
     for (int p0 = w0; p0 < w1; p0 += 256) {
       const int p = p0 + threadIdx.x;
@@ -692,7 +693,7 @@ static __global__ void __launch_bounds__(256) det_grad_kernel(const float* __res
         cy = corner[2 * p];
         cx = corner[2 * p + 1];
         const bool inside = cy >= 0 && cx >= 0 && cy + n <= Ly && cx + n <= Lx;
-        hit = inside && cy < ty0 + kDetTy && cy + n > ty0 && cx < tx0 + kDetTx && cx + n > tx0;
+        hit = inside && cy < ty0 + kRedTy && cy + n > ty0 && cx < tx0 + kRedTx && cx + n > tx0;
       }
       const unsigned long long mask = __ballot(hit);
       if (lane == 0) wave_cnt[wave] = __popcll(mask);
@@ -703,25 +704,41 @@ static __global__ void __launch_bounds__(256) det_grad_kernel(const float* __res
       count += wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
       __syncthreads();
     }
-    for (int i = 0; i < count; ++i) {
-      const int lx = x - lcx[i];
-      if (lx < 0 || lx >= n) continue;
-      const float* sa = stage + ((size_t)lb[i] * S + j) * 2 * nn;
-      const float* sb = sa + nn;
+    for (int i0 = 0; i0 < count; i0 += kRedUnroll) {
+      float va[kRedUnroll][RY], vb[kRedUnroll][RY];
 #pragma unroll
-      for (int r = 0; r < kDetTy / 4; ++r) {
-        const int ly = ty0 + wave + 4 * r - lcy[i];
-        if (ly >= 0 && ly < n) {
-          acc_a[r] += (double)sa[(size_t)ly * n + lx];
-          acc_b[r] += (double)sb[(size_t)ly * n + lx];
+      for (int u = 0; u < kRedUnroll; ++u) {
+        const int i = min(i0 + u, count - 1);
+        const bool live = i0 + u < count;
+        const int pb = __builtin_amdgcn_readfirstlane(lb[i]);
+        const int cy = __builtin_amdgcn_readfirstlane(lcy[i]);
+        const int cx = __builtin_amdgcn_readfirstlane(lcx[i]);
+        const float* base = stage + ((size_t)pb * S + j) * 2 * (size_t)n * n;
+        const rsrc_t ra = make_rsrc(base, plane_bytes);
+        const rsrc_t rb = make_rsrc(base + (size_t)n * n, plane_bytes);
+        const int lx = x - cx;
+        const bool xin = live && lx >= 0 && lx < n;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+          const int ly = ty0 + wave + 4 * r - cy;
+          const uint32_t off = (xin && ly >= 0 && ly < n) ? (uint32_t)(ly * n + lx) * 4 : kRedOutside;
+          va[u][r] = bload(ra, off, 0);
+          vb[u][r] = bload(rb, off, 0);
         }
       }
+#pragma unroll
+      for (int u = 0; u < kRedUnroll; ++u)
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+          acc_a[r] += (double)va[u][r];
+          acc_b[r] += (double)vb[u][r];
+        }
     }
     __syncthreads();                                // the list is rebuilt for the next window
   }
   if (x >= Lx) return;
 #pragma unroll
-  for (int r = 0; r < kDetTy / 4; ++r) {
+  for (int r = 0; r < RY; ++r) {
     const int y = ty0 + wave + 4 * r;
     if (y >= Ly) continue;
     const size_t idx = ((size_t)j * Ly + y) * Lx + x;
@@ -744,7 +761,9 @@ struct WsLayout {
   int nslots;
 };
 
-inline WsLayout ws_layout(const adorym_geom* g, int batch) {
+// Workspace of a loss+gradient call; forward_only: of a forward call (no
+// checkpoints, partials or staging).
+inline WsLayout ws_layout(const adorym_geom* g, int batch, bool forward_only = false) {
   WsLayout w{};
   const size_t nn = (size_t)g->n * g->n;
   const int S = g->n_slices, C = g->ckpt_every;
@@ -757,11 +776,10 @@ inline WsLayout ws_layout(const adorym_geom* g, int batch) {
   w.counters = off; off += align256((size_t)batch * sizeof(int));
   w.xcc = off; off += align256((size_t)batch * kMaxSplit * sizeof(int));
   w.aux = off; off += align256(64 * sizeof(int));   // probe kernels: 2 counters + XCD ids
-  w.gacc = off; off += align256((size_t)batch * nn * sizeof(float2));
-  w.ckpt = off; off += align256((size_t)batch * w.nslots * nn * sizeof(float2));
   w.xbuf = off; off += align256((size_t)batch * 4 * nn * sizeof(float2));
-  w.stage = off;
-  if (g->flags & ADORYM_DETERMINISTIC) off += align256((size_t)batch * S * 2 * nn * sizeof(float));
+  w.gacc = off; if (!forward_only) off += align256((size_t)batch * nn * sizeof(float2));
+  w.ckpt = off; if (!forward_only) off += align256((size_t)batch * w.nslots * nn * sizeof(float2));
+  w.stage = off; if (!forward_only) off += align256((size_t)batch * S * 2 * nn * sizeof(float));
   w.total = off;
   return w;
 }
@@ -791,20 +809,15 @@ inline adorym_status check_geom(adorym_ctx* ctx, const adorym_geom* g, int batch
   return ADORYM_OK;
 }
 
-inline void fill(hipStream_t st, float* p, size_t n, float v) {
-  if (!p || n == 0) return;
-  int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, st, p, n, v);
-}
 
-template <class C, bool LOSS, bool STAGED>
+template <class C, bool LOSS>
 void launch_ms(const MsParams& P, int repr, hipStream_t st) {
   // XCD-aware grid: ceil(B/8) groups per XCD, K slots per group
   const dim3 grid(((P.B + 7) / 8) * 8 * C::K), block(C::THREADS);
   if (repr == ADORYM_OBJ_DELTA_BETA)
-    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, LOSS, STAGED>), grid, block, 0, st, P);
+    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, LOSS>), grid, block, 0, st, P);
   else
-    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, LOSS, STAGED>), grid, block, 0, st, P);
+    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, LOSS>), grid, block, 0, st, P);
 }
 
 // Kernel parameters of one job; `ws` is its workspace (adorym_workspace_size).
@@ -819,7 +832,7 @@ MsParams make_params(adorym_ctx* ctx, const adorym_geom* g, const float* a, cons
   P.q = reinterpret_cast<const float2*>(base + w.q);
   P.corner = corner; P.shift = shift; P.i_meas = i_meas; P.intensity = intensity;
   P.g_a = g_a; P.g_b = g_b;
-  P.gstage = (g_a && (g->flags & ADORYM_DETERMINISTIC)) ? reinterpret_cast<float*>(base + w.stage) : nullptr;
+  P.gstage = g_a ? reinterpret_cast<float*>(base + w.stage) : nullptr;
   P.ckpt = reinterpret_cast<float2*>(base + w.ckpt);
   P.gacc = with_probe_grad ? reinterpret_cast<float2*>(base + w.gacc) : nullptr;
   P.loss_part = reinterpret_cast<double*>(base + w.loss_part);
@@ -838,13 +851,13 @@ MsParams make_params(adorym_ctx* ctx, const adorym_geom* g, const float* a, cons
   return P;
 }
 
-// Tile of the one-group probe kernels: the whole field in one workgroup when
-// it fits, else split in four.
+// Tile of the one-group probe kernels: the whole field in one workgroup for
+// small probes, else split over four workgroups (four CUs).
 template <int N, int L>
-using ProbeCfg = TileCfg<N, L, (N > 128 ? 4 : 1)>;
+using ProbeCfg = TileCfg<N, L, (N >= 128 ? 4 : 1)>;
 
 // Per-job work before the multislice kernel: clear the barrier counters,
-// probe spectrum, and, unless accumulating, zeroed object gradients.
+// probe spectrum.
 template <int N, int L>
 void launch_prologue(const MsParams& P, const float* probe, const adorym_geom* g, hipStream_t st) {
   using PC = ProbeCfg<N, L>;
@@ -855,12 +868,6 @@ void launch_prologue(const MsParams& P, const float* probe, const adorym_geom* g
   hipLaunchKernelGGL((probe_spectrum_kernel<PC>), dim3(PC::K), dim3(PC::THREADS), 0, st,
                      reinterpret_cast<const float2*>(probe), const_cast<float2*>(P.q), P.xbuf, aux, aux + 8,
                      P.err);
-  const size_t nobj = (size_t)g->n_slices * g->obj_ny * g->obj_nx;
-  // (the deterministic reduction writes every voxel itself)
-  if (!(g->flags & ADORYM_ACCUMULATE_GRADS) && !P.gstage) {
-    if (P.g_a) fill(st, P.g_a, nobj, 0.f);
-    if (P.g_b) fill(st, P.g_b, nobj, 0.f);
-  }
 }
 
 // Per-job work after it: loss, shift gradients, probe gradient.
@@ -879,8 +886,8 @@ void launch_epilogue(const MsParams& P, void* ws, const adorym_geom* g, double* 
     hipLaunchKernelGGL((probe_grad_kernel<PC>), dim3(PC::K), dim3(PC::THREADS), 0, st, gsum,
                        reinterpret_cast<float2*>(g_probe), accumulate, P.xbuf, aux + 1, aux + 16, P.err);
   if (P.gstage) {
-    const dim3 grid((P.Lx + kDetTx - 1) / kDetTx, (P.Ly + kDetTy - 1) / kDetTy, P.S);
-    hipLaunchKernelGGL(det_grad_kernel, grid, dim3(256), 0, st, P.gstage, P.corner, N, P.B, P.S, P.Ly, P.Lx,
+    const dim3 grid((P.Lx + kRedTx - 1) / kRedTx, (P.Ly + kRedTy - 1) / kRedTy, P.S);
+    hipLaunchKernelGGL(grad_reduce_kernel, grid, dim3(256), 0, st, P.gstage, P.corner, N, P.B, P.S, P.Ly, P.Lx,
                        P.g_a, P.g_b, accumulate);
   }
 }
@@ -889,14 +896,8 @@ void launch_epilogue(const MsParams& P, void* ws, const adorym_geom* g, double* 
 // job's results do not depend on the split chosen for other calls.
 constexpr int det_split(int n) { return n == 192 ? 8 : (n == 128 ? 4 : 1); }
 
-// Whether a loss_grad call stages its object gradient (deterministic mode).
-inline bool staged_call(const adorym_geom* g, bool with_loss, const float* g_a) {
-  return with_loss && g_a != nullptr && (g->flags & ADORYM_DETERMINISTIC) != 0;
-}
-
-// One probe size N with lanes-per-line L and split K.  STAGED instances
-// serve deterministic-mode loss_grad calls only.
-template <int N, int L, int K, bool STAGED>
+// One probe size N with lanes-per-line L and split K.
+template <int N, int L, int K>
 adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b, const float* probe,
                   const int32_t* corner, const float* shift, int batch, const float* i_meas, void* ws,
                   double* loss, float* g_a, float* g_b, float* g_probe, float* g_shift, float* intensity,
@@ -909,12 +910,8 @@ adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const f
   const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
   launch_prologue<N, L>(P, probe, g, st);
   if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
-  if constexpr (STAGED) {
-    launch_ms<C, true, true>(P, g->obj_repr, st);
-  } else {
-    if (with_loss) launch_ms<C, true, false>(P, g->obj_repr, st);
-    else launch_ms<C, false, false>(P, g->obj_repr, st);
-  }
+  if (with_loss) launch_ms<C, true>(P, g->obj_repr, st);
+  else launch_ms<C, false>(P, g->obj_repr, st);
   if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
   if (with_loss) launch_epilogue<N, L>(P, ws, g, loss, g_probe, g_shift, st);
   hipError_t e = hipGetLastError();
@@ -924,24 +921,24 @@ adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const f
 
 // The persistent multi-job kernel of one probe-size class (device tables
 // prepared by the plan).
-template <int N, int L, int K, bool STAGED>
+template <int N, int L, int K>
 void launch_batched(const MsParams* jobs, const int2* items, int n_items, int* ticket, int* mailbox, int* counters,
                     int* xcc, float2* xbuf, int* err, int groups, int repr, hipStream_t st) {
   using C = TileCfg<N, L, K>;
   const dim3 grid(groups * K), block(C::THREADS);
   if (repr == ADORYM_OBJ_DELTA_BETA)
-    hipLaunchKernelGGL((multislice_batched_kernel<C, ADORYM_OBJ_DELTA_BETA, STAGED>), grid, block, 0, st, jobs, items,
+    hipLaunchKernelGGL((multislice_batched_kernel<C, ADORYM_OBJ_DELTA_BETA>), grid, block, 0, st, jobs, items,
                        n_items, ticket, mailbox, counters, xcc, xbuf, err);
   else
-    hipLaunchKernelGGL((multislice_batched_kernel<C, ADORYM_OBJ_REAL_IMAG, STAGED>), grid, block, 0, st, jobs, items,
+    hipLaunchKernelGGL((multislice_batched_kernel<C, ADORYM_OBJ_REAL_IMAG>), grid, block, 0, st, jobs, items,
                        n_items, ticket, mailbox, counters, xcc, xbuf, err);
 }
 
 }  // namespace adorym_ms
 
 // Explicit instantiation helpers
-#define ADORYM_BATCHED_SIGNATURE(N_, L_, K_, S_) \
-  void adorym_ms::launch_batched<N_, L_, K_, S_>(const adorym_ms::MsParams*, const int2*, int, int*, int*, int*, int*, \
+#define ADORYM_BATCHED_SIGNATURE(N_, L_, K_) \
+  void adorym_ms::launch_batched<N_, L_, K_>(const adorym_ms::MsParams*, const int2*, int, int*, int*, int*, int*, \
                                               float2*, int*, int, int, hipStream_t)
 #define ADORYM_PROLOGUE_SIGNATURE(N_, L_) \
   void adorym_ms::launch_prologue<N_, L_>(const adorym_ms::MsParams&, const float*, const adorym_geom*, hipStream_t)
@@ -952,7 +949,7 @@ void launch_batched(const MsParams* jobs, const int2* items, int n_items, int* t
   adorym_ms::MsParams adorym_ms::make_params<N_, L_>(adorym_ctx*, const adorym_geom*, const float*, \
                                                         const float*, int, const int32_t*, const float*, \
                                                         const float*, void*, bool, float*, float*, float*)
-#define ADORYM_RUN_SIGNATURE(N_, L_, K_, S_) \
-  adorym_status adorym_ms::run<N_, L_, K_, S_>(adorym_ctx*, const adorym_geom*, const float*, const float*, const float*, \
+#define ADORYM_RUN_SIGNATURE(N_, L_, K_) \
+  adorym_status adorym_ms::run<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, const float*, const float*, \
                                            const int32_t*, const float*, int, const float*, void*, double*, float*, \
                                            float*, float*, float*, float*, bool)

@@ -73,17 +73,19 @@ def test_workspace_size_formula():
     slots = 63 // 16 + 1 + 1            # slices 0, 16, 32, 48 and the last (63)
     # probe spectrum + its gradient sum, loss and shift partials for up to 8
     # workgroups per position, barrier counters and XCD ids, probe-kernel counters,
-    # probe-gradient partials,
-    # checkpoints, and two double-buffered exchange fields per position
-    expect = (2 * nn + 50 * 8 * 8 + 50 * 8 * 2 * 8 + 50 * 4 + 50 * 8 * 4 + 64 * 4 + 50 * nn + 50 * slots * nn
-              + 50 * 4 * nn)
-    assert expect <= size < expect + 10 * 256
+    # probe-gradient partials, checkpoints, two double-buffered exchange fields
+    # per position, and every position's float32 object gradient of both planes
+    small = 2 * nn + 50 * 8 * 8 + 50 * 8 * 2 * 8 + 50 * 4 + 50 * 8 * 4 + 64 * 4 + 50 * 4 * nn
+    expect = small + 50 * nn + 50 * slots * nn + 50 * 64 * 2 * 128 * 128 * 4
+    assert expect <= size < expect + 12 * 256
     assert lib.adorym_workspace_size(ctypes.byref(_geom(n_slices=0)), 50) == 0
     assert lib.adorym_workspace_size(ctypes.byref(g), 0) == 0
-    # deterministic mode stages every position's float32 gradient of both planes
+    # a forward call needs no checkpoints, partials or staging
+    fwd = lib.adorym_forward_workspace_size(ctypes.byref(g), 50)
+    assert small <= fwd < small + 12 * 256
+    # the deterministic flag does not change the workspace
     gd = _geom(flags=_lib.DETERMINISTIC)
-    extra = lib.adorym_workspace_size(ctypes.byref(gd), 50) - size
-    assert 50 * 64 * 2 * 128 * 128 * 4 <= extra < 50 * 64 * 2 * 128 * 128 * 4 + 256
+    assert lib.adorym_workspace_size(ctypes.byref(gd), 50) == size
 
 
 def test_supported_sizes():
