@@ -101,6 +101,27 @@ __device__ __forceinline__ void transmission(float kdz, float a, float b, float2
   }
 }
 
+// Transmission of one slice on this thread's elements, computed ahead of
+// its use: t, and for the reverse sweep g2 = |t|^-2 (t^-1 = conj(t) g2).
+template <class C, int REPR, bool INV>
+__device__ __forceinline__ void make_trans(float2 (&t)[C::R], float (&g2)[C::R], const float (&ca)[C::R],
+                                           const float (&cb)[C::R], float kdz) {
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    if constexpr (REPR == ADORYM_OBJ_DELTA_BETA) {
+      float s, c;
+      sincos_f32(kdz * ca[m], s, c);
+      const float v = kdz * cb[m];
+      const float att = exp_f32(-v);
+      t[m] = make_float2(c * att, s * att);
+      if (INV) g2[m] = exp_f32(2.0f * v);
+    } else {
+      t[m] = make_float2(ca[m], cb[m]);
+      if (INV) g2[m] = 1.0f / (ca[m] * ca[m] + cb[m] * cb[m]);
+    }
+  }
+}
+
 // Shared memory of the multislice kernel.
 template <class C>
 struct MsShared {
@@ -135,6 +156,23 @@ __device__ __forceinline__ void xfer2(float2 (&v0)[C::R], float2 (&v1)[C::R], Ms
   } else {
     transpose_global<C, 2>(v0, v1, wk.x, wk.ln, src_spec, dst_spec);
   }
+}
+
+// Split-phase transposes of one (NF = 1) or two fields: xfer_begin ...
+// independent work ... xfer_end.  K == 1 transposes through LDS at once.
+template <class C, int NF>
+__device__ __forceinline__ void xfer_begin(float2 (&v0)[C::R], float2 (&v1)[C::R], MsShared<C>& sh, Work<C>& wk,
+                                           bool src_spec, bool dst_spec) {
+  if constexpr (C::K == 1) {
+    if constexpr (NF == 2) xfer2<C>(v0, v1, sh, wk, src_spec, dst_spec);
+    else xfer<C>(v0, sh, wk, src_spec, dst_spec);
+  } else {
+    transpose_global_begin<C, NF>(v0, v1, wk.x, wk.ln, src_spec);
+  }
+}
+template <class C, int NF>
+__device__ __forceinline__ void xfer_end(float2 (&v0)[C::R], float2 (&v1)[C::R], Work<C>& wk, bool dst_spec) {
+  if constexpr (C::K > 1) transpose_global_end<C, NF>(v0, v1, wk.x, wk.ln, dst_spec);
 }
 
 template <class C>
@@ -251,18 +289,16 @@ __device__ __forceinline__ void place_probe(float2 (&v)[C::R], const MsParams& P
   ifft_line<C, +1>(v, sh.tb, ln);                 // along x -> natural
 }
 
-// One forward slice step: (store) modulate, and propagate to slice j + 1.
-// ca/cb hold slice j's object values on entry (loaded ahead of time when
-// the tile prefetches) and slice j+1's on exit when prefetching.
+// One forward slice step of tiles that do not prefetch: (store) load the
+// slice's object values, modulate, and propagate to slice j + 1.
 template <class C, int REPR, bool ROW, bool CKPT>
 __device__ __forceinline__ void forward_slice(float2 (&v)[C::R], float (&ca)[C::R], float (&cb)[C::R],
                                               const MsParams& P, MsShared<C>& sh, Work<C>& wk,
                                               const ChunkOffsets& o, int j) {
   if (CKPT && is_ckpt(j, P.S, P.ckpt_every)) field_store<C>(v, ckpt_ptr<C>(P, wk, ckpt_slot(j, P.S, P.ckpt_every)), wk.ln);
-  if (!C::PREFETCH) load_chunk<C, ROW>(ca, cb, P, o, j);
+  load_chunk<C, ROW>(ca, cb, P, o, j);
   modulate<C, REPR>(v, ca, cb, P.kdz);
   if (j < P.S - 1) {
-    if (C::PREFETCH) load_chunk<C, !ROW>(ca, cb, P, o, j + 1);   // in flight during the propagation
     propagate_line<C, false>(v, sh.tb, wk.ln);
     xfer<C>(v, sh, wk, false, false);
     propagate_line<C, false>(v, sh.tb, wk.ln);
@@ -273,10 +309,10 @@ __device__ __forceinline__ void forward_slice(float2 (&v)[C::R], float (&ca)[C::
 // fields are taken back to slice j-1 by the adjoint propagator.
 //   in : psi = phi_j (the wave leaving slice j, rebuilt by the backward
 //        recursion) unless slice j is anchored on a checkpoint;
-//        lam = dL/dphi_j; ca/cb = slice j's object values when prefetching
-//   out: psi = phi_{j-1} = P^H psi_j, lam = dL/dphi_{j-1} = P^H conj(t_j) lam;
-//        ca/cb = slice j-1's object values when prefetching
-// The slice gradient goes to this position's staging planes.
+//        lam = dL/dphi_j
+//   out: psi = phi_{j-1} = P^H psi_j, lam = dL/dphi_{j-1} = P^H conj(t_j) lam
+// The slice gradient goes to this position's staging planes.  (Tiles that
+// do not prefetch; backward_slice_pf below is the prefetching form.)
 template <class C, int REPR, bool ROW>
 __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam)[C::R], float (&ca)[C::R],
                                                float (&cb)[C::R], const MsParams& P, MsShared<C>& sh, Work<C>& wk,
@@ -284,7 +320,7 @@ __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam
   const Lane<C>& ln = wk.ln;
   const bool anchored = is_ckpt(j, P.S, P.ckpt_every);
   if (anchored) field_load<C>(psi, ckpt_ptr<C>(P, wk, ckpt_slot(j, P.S, P.ckpt_every)), ln);  // psi_j exactly
-  if (!C::PREFETCH) load_chunk<C, ROW>(ca, cb, P, o, j);
+  load_chunk<C, ROW>(ca, cb, P, o, j);
   const bool grads = P.gstage != nullptr;
   const rsrc_t rga = grads ? stage_rsrc<C>(P, wk.b, j, 0) : make_rsrc(P.a, 0);
   const rsrc_t rgb = grads ? stage_rsrc<C>(P, wk.b, j, 1) : make_rsrc(P.b, 0);
@@ -314,7 +350,6 @@ __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam
     psi[m] = in_wave;
   }
   if (j > 0) {
-    if (C::PREFETCH) load_chunk<C, !ROW>(ca, cb, P, o, j - 1);   // in flight during the propagation
     const bool need_psi = !is_ckpt(j - 1, P.S, P.ckpt_every);
     if (need_psi) {
       propagate_line<C, true>(psi, sh.tb, ln);
@@ -325,6 +360,85 @@ __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam
     } else {
       propagate_line<C, true>(lam, sh.tb, ln);
       xfer<C>(lam, sh, wk, false, false);
+      propagate_line<C, true>(lam, sh.tb, ln);
+    }
+  }
+}
+
+// Slice steps of tiles that prefetch (C::PREFETCH): the object values of
+// the next slice are loaded during the propagation, and its transmission is
+// computed while the transpose's exchange is in flight (between the two
+// halves of the split barrier).  t/g2 carry the transmission of the current
+// slice from step to step.
+template <class C, int REPR, bool ROW, bool CKPT>
+__device__ __forceinline__ void forward_slice_pf(float2 (&v)[C::R], float2 (&t)[C::R], float (&g2)[C::R],
+                                                 const MsParams& P, MsShared<C>& sh, Work<C>& wk,
+                                                 const ChunkOffsets& o, int j) {
+  if (CKPT && is_ckpt(j, P.S, P.ckpt_every)) field_store<C>(v, ckpt_ptr<C>(P, wk, ckpt_slot(j, P.S, P.ckpt_every)), wk.ln);
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) v[m] = cmul(v[m], t[m]);
+  if (j < P.S - 1) {
+    float ca[C::R], cb[C::R];
+    load_chunk<C, !ROW>(ca, cb, P, o, j + 1);   // in flight during the propagation
+    propagate_line<C, false>(v, sh.tb, wk.ln);
+    xfer_begin<C, 1>(v, v, sh, wk, false, false);
+    make_trans<C, REPR, false>(t, g2, ca, cb, P.kdz);
+    xfer_end<C, 1>(v, v, wk, false);
+    propagate_line<C, false>(v, sh.tb, wk.ln);
+  }
+}
+
+template <class C, int REPR, bool ROW>
+__device__ __forceinline__ void backward_slice_pf(float2 (&psi)[C::R], float2 (&lam)[C::R], float2 (&t)[C::R],
+                                                  float (&g2)[C::R], const MsParams& P, MsShared<C>& sh,
+                                                  Work<C>& wk, const ChunkOffsets& o, int j) {
+  const Lane<C>& ln = wk.ln;
+  const bool anchored = is_ckpt(j, P.S, P.ckpt_every);
+  if (anchored) field_load<C>(psi, ckpt_ptr<C>(P, wk, ckpt_slot(j, P.S, P.ckpt_every)), ln);  // psi_j exactly
+  const bool grads = P.gstage != nullptr;
+  const rsrc_t rga = grads ? stage_rsrc<C>(P, wk.b, j, 0) : make_rsrc(P.a, 0);
+  const rsrc_t rgb = grads ? stage_rsrc<C>(P, wk.b, j, 1) : make_rsrc(P.b, 0);
+  const float kdz = P.kdz;
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    const float2 tm = t[m];
+    const float2 in_wave = anchored ? psi[m] : cscale(cmulc(psi[m], tm), g2[m]);   // psi_j = phi_j / t_j
+    const float2 out_wave = anchored ? cmul(psi[m], tm) : psi[m];                  // phi_j
+    const float2 l = lam[m];
+    if (grads) {
+      float ga, gb;
+      if constexpr (REPR == ADORYM_OBJ_DELTA_BETA) {
+        const float2 z = cmulc(l, out_wave);          // lam conj(phi)
+        ga = kdz * z.y;
+        gb = -kdz * z.x;
+      } else {
+        const float2 z = cmulc(l, in_wave);           // lam conj(psi)
+        ga = z.x;
+        gb = z.y;
+      }
+      stage_store<C, ROW>(rga, ln, m, ga);
+      stage_store<C, ROW>(rgb, ln, m, gb);
+    }
+    lam[m] = cmulc(l, tm);                             // conj(t) lam = dL/dpsi_j
+    psi[m] = in_wave;
+  }
+  if (j > 0) {
+    float ca[C::R], cb[C::R];
+    load_chunk<C, !ROW>(ca, cb, P, o, j - 1);   // in flight during the propagation
+    const bool need_psi = !is_ckpt(j - 1, P.S, P.ckpt_every);
+    if (need_psi) {
+      propagate_line<C, true>(psi, sh.tb, ln);
+      propagate_line<C, true>(lam, sh.tb, ln);
+      xfer_begin<C, 2>(psi, lam, sh, wk, false, false);
+      make_trans<C, REPR, true>(t, g2, ca, cb, kdz);
+      xfer_end<C, 2>(psi, lam, wk, false);
+      propagate_line<C, true>(psi, sh.tb, ln);
+      propagate_line<C, true>(lam, sh.tb, ln);
+    } else {
+      propagate_line<C, true>(lam, sh.tb, ln);
+      xfer_begin<C, 1>(lam, lam, sh, wk, false, false);
+      make_trans<C, REPR, true>(t, g2, ca, cb, kdz);
+      xfer_end<C, 1>(lam, lam, wk, false);
       propagate_line<C, true>(lam, sh.tb, ln);
     }
   }
@@ -376,14 +490,28 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
   const ChunkOffsets o = chunk_offsets<C>(ln, wk.cy, wk.cx, P.Ly, P.Lx);
 
   float2 v[C::R];
+  // object values of the current slice (tiles that do not prefetch), or the
+  // current slice's transmission (tiles that do)
   float ca[C::R], cb[C::R];
-  if (C::PREFETCH) load_chunk<C, true>(ca, cb, P, o, 0);
+  float2 tr[C::R];
+  float g2[C::R];
+  if constexpr (C::PREFETCH) {
+    load_chunk<C, true>(ca, cb, P, o, 0);
+#pragma unroll
+    for (int m = 0; m < C::R; ++m) g2[m] = 1.0f;   // slice S-1 is always anchored: no inverse needed
+    make_trans<C, REPR, false>(tr, g2, ca, cb, P.kdz);
+  }
   place_probe<C>(v, P, sh, wk);
 
   // MultislicePropagate: even slices in ROW layout, odd slices in COL layout.
   for (int j = 0; j < P.S; j += 2) {
-    forward_slice<C, REPR, true, LOSS>(v, ca, cb, P, sh, wk, o, j);
-    if (j + 1 < P.S) forward_slice<C, REPR, false, LOSS>(v, ca, cb, P, sh, wk, o, j + 1);
+    if constexpr (C::PREFETCH) {
+      forward_slice_pf<C, REPR, true, LOSS>(v, tr, g2, P, sh, wk, o, j);
+      if (j + 1 < P.S) forward_slice_pf<C, REPR, false, LOSS>(v, tr, g2, P, sh, wk, o, j + 1);
+    } else {
+      forward_slice<C, REPR, true, LOSS>(v, ca, cb, P, sh, wk, o, j);
+      if (j + 1 < P.S) forward_slice<C, REPR, false, LOSS>(v, ca, cb, P, sh, wk, o, j + 1);
+    }
   }
   const bool last_row = ((P.S - 1) & 1) == 0;
 
@@ -441,17 +569,30 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
 
   float2 psi[C::R];
   int j = P.S - 1;
-  // the forward sweep left slice S-1's object values in ca/cb
-  if (!last_row) {
-    backward_slice<C, REPR, false>(psi, v, ca, cb, P, sh, wk, o, j);
-    --j;
+  // the forward sweep left slice S-1's object values in ca/cb (or its
+  // transmission in tr)
+  if constexpr (C::PREFETCH) {
+    if (!last_row) {
+      backward_slice_pf<C, REPR, false>(psi, v, tr, g2, P, sh, wk, o, j);
+      --j;
+    }
+    for (; j >= 1; j -= 2) {
+      backward_slice_pf<C, REPR, true>(psi, v, tr, g2, P, sh, wk, o, j);
+      backward_slice_pf<C, REPR, false>(psi, v, tr, g2, P, sh, wk, o, j - 1);
+    }
+    if (j == 0) backward_slice_pf<C, REPR, true>(psi, v, tr, g2, P, sh, wk, o, 0);
+  } else {
+    if (!last_row) {
+      backward_slice<C, REPR, false>(psi, v, ca, cb, P, sh, wk, o, j);
+      --j;
+    }
+    // now slice j is even (ROW); pairs (j ROW, j-1 COL) down to slice 0
+    for (; j >= 1; j -= 2) {
+      backward_slice<C, REPR, true>(psi, v, ca, cb, P, sh, wk, o, j);
+      backward_slice<C, REPR, false>(psi, v, ca, cb, P, sh, wk, o, j - 1);
+    }
+    if (j == 0) backward_slice<C, REPR, true>(psi, v, ca, cb, P, sh, wk, o, 0);
   }
-  // now slice j is even (ROW); pairs (j ROW, j-1 COL) down to slice 0
-  for (; j >= 1; j -= 2) {
-    backward_slice<C, REPR, true>(psi, v, ca, cb, P, sh, wk, o, j);
-    backward_slice<C, REPR, false>(psi, v, ca, cb, P, sh, wk, o, j - 1);
-  }
-  if (j == 0) backward_slice<C, REPR, true>(psi, v, ca, cb, P, sh, wk, o, 0);
   // v = dL/d(shifted probe) in ROW layout, natural order.
 
   // FourierShift adjoint: G = DFT(g_pb) in COL layout (kx line, ky spectral).

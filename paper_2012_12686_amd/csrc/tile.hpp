@@ -492,11 +492,15 @@ __device__ __forceinline__ void wait_stores() {
   __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's memory operations have completed
 }
 
-__device__ __forceinline__ void group_barrier(int* counter, int target, int* err) {
+// The barrier in two halves, so that work that touches no exchanged data can
+// run between the arrival and the wait.
+__device__ __forceinline__ void group_arrive(int* counter) {
   wait_stores();
   __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void group_wait(int* counter, int target, int* err) {
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int spins = 0;
     while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
@@ -507,6 +511,10 @@ __device__ __forceinline__ void group_barrier(int* counter, int target, int* err
     }
   }
   __syncthreads();
+}
+__device__ __forceinline__ void group_barrier(int* counter, int target, int* err) {
+  group_arrive(counter);
+  group_wait(counter, target, err);
 }
 
 // Exchange state of one field group: two alternating N x N halves per field
@@ -571,6 +579,49 @@ __device__ __forceinline__ void transpose_global(float2 (&v0)[C::R], float2 (&v1
                                                  const Lane<C>& ln, bool src_spec, bool dst_spec) {
   if (x.local) transpose_global_impl<C, NF, kL1Bypass, 0>(v0, v1, x, ln, src_spec, dst_spec);
   else transpose_global_impl<C, NF, kCoherent, kCoherent>(v0, v1, x, ln, src_spec, dst_spec);
+}
+
+// The same transpose in two halves: begin stores this workgroup's lines and
+// arrives at the group barrier; end waits and loads the transposed lines.
+// Between the two the caller may do work that touches neither field.
+template <class C, int NF, int ST>
+__device__ __forceinline__ void transpose_begin_impl(const float2 (&v0)[C::R], const float2 (&v1)[C::R], Exchange& x,
+                                                     const Lane<C>& ln, bool src_spec) {
+  constexpr int NN = C::N * C::N;
+  const rsrc_t r = make_rsrc(x.buf + (size_t)(x.phase & 1) * 2 * NN, 2 * NN * 8);
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    const uint32_t off = (uint32_t)(ln.line * C::N + ln.pos(m, src_spec)) * 8;
+    bstore2<ST>(r, v0[m], off, 0);
+    if (NF == 2) bstore2<ST>(r, v1[m], off, NN * 8);
+  }
+  ++x.phase;
+  group_arrive(x.counter);
+}
+template <class C, int NF, int LD>
+__device__ __forceinline__ void transpose_end_impl(float2 (&v0)[C::R], float2 (&v1)[C::R], Exchange& x,
+                                                   const Lane<C>& ln, bool dst_spec) {
+  constexpr int NN = C::N * C::N;
+  group_wait(x.counter, C::K * x.phase, x.err);
+  const rsrc_t r = make_rsrc(x.buf + (size_t)((x.phase - 1) & 1) * 2 * NN, 2 * NN * 8);
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    const uint32_t off = (uint32_t)(ln.pos(m, dst_spec) * C::N + ln.line) * 8;
+    v0[m] = bload2<LD>(r, off, 0);
+    if (NF == 2) v1[m] = bload2<LD>(r, off, NN * 8);
+  }
+}
+template <class C, int NF>
+__device__ __forceinline__ void transpose_global_begin(const float2 (&v0)[C::R], const float2 (&v1)[C::R],
+                                                       Exchange& x, const Lane<C>& ln, bool src_spec) {
+  if (x.local) transpose_begin_impl<C, NF, 0>(v0, v1, x, ln, src_spec);
+  else transpose_begin_impl<C, NF, kCoherent>(v0, v1, x, ln, src_spec);
+}
+template <class C, int NF>
+__device__ __forceinline__ void transpose_global_end(float2 (&v0)[C::R], float2 (&v1)[C::R], Exchange& x,
+                                                     const Lane<C>& ln, bool dst_spec) {
+  if (x.local) transpose_end_impl<C, NF, kL1Bypass>(v0, v1, x, ln, dst_spec);
+  else transpose_end_impl<C, NF, kCoherent>(v0, v1, x, ln, dst_spec);
 }
 
 // ----------------------------------------------------------------------------
