@@ -158,6 +158,16 @@ __device__ __forceinline__ void xfer2(float2 (&v0)[C::R], float2 (&v1)[C::R], Ms
   }
 }
 
+// Fresnel propagation of one field along the thread's lines; the input is
+// stashed in the thread's own cells of the LDS field buffer.  K == 1 tiles
+// share that buffer with the transposes, so they wait first: other waves may
+// still be reading the row from the last transpose.
+template <class C, bool CONJ>
+__device__ __forceinline__ void prop(float2 (&v)[C::R], MsShared<C>& sh, const Lane<C>& ln) {
+  if constexpr (C::K == 1) __syncthreads();
+  propagate_line<C, CONJ>(v, sh.tb, ln, sh.buf + (ln.w * C::RPW + ln.g) * C::PITCH);
+}
+
 // Split-phase transposes of one (NF = 1) or two fields: xfer_begin ...
 // independent work ... xfer_end.  K == 1 transposes through LDS at once.
 template <class C, int NF>
@@ -299,9 +309,9 @@ __device__ __forceinline__ void forward_slice(float2 (&v)[C::R], float (&ca)[C::
   load_chunk<C, ROW>(ca, cb, P, o, j);
   modulate<C, REPR>(v, ca, cb, P.kdz);
   if (j < P.S - 1) {
-    propagate_line<C, false>(v, sh.tb, wk.ln);
+    prop<C, false>(v, sh, wk.ln);
     xfer<C>(v, sh, wk, false, false);
-    propagate_line<C, false>(v, sh.tb, wk.ln);
+    prop<C, false>(v, sh, wk.ln);
   }
 }
 
@@ -352,15 +362,15 @@ __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam
   if (j > 0) {
     const bool need_psi = !is_ckpt(j - 1, P.S, P.ckpt_every);
     if (need_psi) {
-      propagate_line<C, true>(psi, sh.tb, ln);
-      propagate_line<C, true>(lam, sh.tb, ln);
+      prop<C, true>(psi, sh, ln);
+      prop<C, true>(lam, sh, ln);
       xfer2<C>(psi, lam, sh, wk, false, false);
-      propagate_line<C, true>(psi, sh.tb, ln);
-      propagate_line<C, true>(lam, sh.tb, ln);
+      prop<C, true>(psi, sh, ln);
+      prop<C, true>(lam, sh, ln);
     } else {
-      propagate_line<C, true>(lam, sh.tb, ln);
+      prop<C, true>(lam, sh, ln);
       xfer<C>(lam, sh, wk, false, false);
-      propagate_line<C, true>(lam, sh.tb, ln);
+      prop<C, true>(lam, sh, ln);
     }
   }
 }
@@ -380,11 +390,11 @@ __device__ __forceinline__ void forward_slice_pf(float2 (&v)[C::R], float2 (&t)[
   if (j < P.S - 1) {
     float ca[C::R], cb[C::R];
     load_chunk<C, !ROW>(ca, cb, P, o, j + 1);   // in flight during the propagation
-    propagate_line<C, false>(v, sh.tb, wk.ln);
+    prop<C, false>(v, sh, wk.ln);
     xfer_begin<C, 1>(v, v, sh, wk, false, false);
     make_trans<C, REPR, false>(t, g2, ca, cb, P.kdz);
     xfer_end<C, 1>(v, v, wk, false);
-    propagate_line<C, false>(v, sh.tb, wk.ln);
+    prop<C, false>(v, sh, wk.ln);
   }
 }
 
@@ -427,19 +437,19 @@ __device__ __forceinline__ void backward_slice_pf(float2 (&psi)[C::R], float2 (&
     load_chunk<C, !ROW>(ca, cb, P, o, j - 1);   // in flight during the propagation
     const bool need_psi = !is_ckpt(j - 1, P.S, P.ckpt_every);
     if (need_psi) {
-      propagate_line<C, true>(psi, sh.tb, ln);
-      propagate_line<C, true>(lam, sh.tb, ln);
+      prop<C, true>(psi, sh, ln);
+      prop<C, true>(lam, sh, ln);
       xfer_begin<C, 2>(psi, lam, sh, wk, false, false);
       make_trans<C, REPR, true>(t, g2, ca, cb, kdz);
       xfer_end<C, 2>(psi, lam, wk, false);
-      propagate_line<C, true>(psi, sh.tb, ln);
-      propagate_line<C, true>(lam, sh.tb, ln);
+      prop<C, true>(psi, sh, ln);
+      prop<C, true>(lam, sh, ln);
     } else {
-      propagate_line<C, true>(lam, sh.tb, ln);
+      prop<C, true>(lam, sh, ln);
       xfer_begin<C, 1>(lam, lam, sh, wk, false, false);
       make_trans<C, REPR, true>(t, g2, ca, cb, kdz);
       xfer_end<C, 1>(lam, lam, wk, false);
-      propagate_line<C, true>(lam, sh.tb, ln);
+      prop<C, true>(lam, sh, ln);
     }
   }
 }

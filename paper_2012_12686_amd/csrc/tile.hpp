@@ -251,7 +251,9 @@ struct TileCfg {
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int LOGL = ilog2(L);
   static constexpr int PITCH = N + 8;           // LDS row pitch in float2 (bank spread)
-  static constexpr int LDS_FIELD = K == 1 ? N * PITCH : 1;   // LDS transpose buffer (K == 1 only)
+  // LDS field buffer: the transpose buffer (K == 1), else one row per own
+  // line for the propagation's stash.
+  static constexpr int LDS_FIELD = (K == 1 ? N : LINES) * PITCH;
   // Registers per lane: a SIMD holds 512 per lane, shared by the waves of
   // the workgroup that land on it (waves are spread over the 4 SIMDs).
   static constexpr int WAVES_PER_SIMD = (WAVES + 3) / 4;
@@ -288,7 +290,7 @@ template <class C>
 struct Tables {
   float2 wn[C::N];          // W_N^e = exp(-2 pi i e / N), e in [0, N)
   float2 tw[C::R * C::L];   // entry k2*L + q: W_N^{q k2} (inter-stage twiddles)
-  float2 h[C::N];           // 1D Fresnel kernel / N at spectral slot m*L + k1 (frequency R*k1 + m)
+  float2 h[C::N];           // (1D Fresnel kernel - 1) / N at spectral slot m*L + k1 (frequency R*k1 + m)
 };
 
 template <class C>
@@ -306,8 +308,9 @@ __device__ void build_twiddles(Tables<C>& tb, int tid) {
   }
 }
 
-// 1D Fresnel kernel exp(i pi (lambda dz / dx^2) f^2) / N, f = fftfreq(N),
-// stored so that the L lanes of a line read L consecutive entries.
+// 1D Fresnel kernel minus one, (exp(i pi (lambda dz / dx^2) f^2) - 1) / N,
+// f = fftfreq(N), stored so that the L lanes of a line read L consecutive
+// entries.  The real part is -2 sin^2(theta/2), exact for small phases.
 template <class C>
 __device__ void build_fresnel(Tables<C>& tb, int tid, double chirp /* lambda dz / dx^2 */) {
   for (int idx = tid; idx < C::N; idx += C::THREADS) {
@@ -315,9 +318,9 @@ __device__ void build_fresnel(Tables<C>& tb, int tid, double chirp /* lambda dz 
     const int k = C::R * k1 + m;
     int kk = (k < (C::N + 1) / 2) ? k : k - C::N;
     double f = double(kk) / double(C::N);
-    double s, c;
-    sincospi(chirp * f * f, &s, &c);
-    tb.h[idx] = make_float2(float(c / C::N), float(s / C::N));
+    const double x = chirp * f * f;          // phase / pi
+    const double sh = sinpi(0.5 * x);
+    tb.h[idx] = make_float2(float(-2.0 * sh * sh / C::N), float(sinpi(x) / C::N));
   }
 }
 
@@ -395,18 +398,32 @@ __device__ __forceinline__ void ifft_line(float2 (&v)[C::R], const Tables<C>& tb
   Dft<C::R, SIGN, 1, 0, C::R>::run(v);
 }
 
-// Fresnel propagation along the line (CONJ: adjoint kernel).
+// Fresnel propagation along the line (CONJ: adjoint kernel), written as
+// v + IDFT((h - 1) DFT(v)) / N: the transforms carry only the small change
+// the propagation makes (|h - 1| is about 1e-2 for these distances), so
+// their float32 rounding is relative to that change rather than to the wave.
+// K == 1 tiles keep the input in the thread's own cells of the LDS transpose
+// buffer (stash: the line's row) instead of registers.
 template <class C, bool CONJ>
-__device__ __forceinline__ void propagate_line(float2 (&v)[C::R], const Tables<C>& tb, const Lane<C>& ln) {
+__device__ __forceinline__ void propagate_line(float2 (&v)[C::R], const Tables<C>& tb, const Lane<C>& ln,
+                                               float2* stash = nullptr) {
+  float2 v0[C::R];
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    if (stash) stash[ln.pos_nat(m)] = v[m];
+    else v0[m] = v[m];
+  }
   fft_line<C, -1>(v, tb, ln);
   if (C::FENCE) sched_fence();
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
-    float2 h = tb.h[m * C::L + ln.k1];     // kernel at frequency R*k1 + m
+    float2 h = tb.h[m * C::L + ln.k1];     // kernel - 1 at frequency R*k1 + m
     v[m] = CONJ ? cmulc(v[m], h) : cmul(v[m], h);
     if (C::FENCE && (m & 3) == 3) sched_fence();
   }
   ifft_line<C, +1>(v, tb, ln);
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) v[m] = cadd(v[m], stash ? stash[ln.pos_nat(m)] : v0[m]);
 }
 
 // ----------------------------------------------------------------------------

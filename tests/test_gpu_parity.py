@@ -315,3 +315,53 @@ def test_deterministic_jobs_in_a_plan_equal_single_calls_bitwise(ctx):
             else:
                 assert rel_l2(got[k], ref[k]) < 1e-5, k
     plan.close()
+
+
+def test_config3_full_minibatch_sampled_positions(ctx):
+    """512x512x128 object, 128 probe, a full minibatch of 200 positions, C = 16.
+
+    The oracle evaluates three sampled positions one by one: their intensities
+    and shift gradients depend on no other position (the loss is a mean over
+    all B N^2 pixels, so the oracle's gradient is rescaled from 3 to 200
+    positions).  The measured data of the other positions are copies of a
+    sampled position's (they do not enter the sampled outputs).  The autograd
+    front end must give the call's numbers bit for bit.
+    """
+    import torch
+    from paper_2012_12686_amd import Geometry, multislice_loss
+    from tests.fp32_model import loss_grad_fp32
+    sc = synth.config3()
+    bsz, sample = 200, np.array([0, 101, 199])
+    case = Case(sc, idx=sample)
+    pos_all = np.asarray(sc.eval_positions, dtype=np.float64)[:bsz]
+    corner, shift = synth.split_positions(pos_all)
+    i_meas = np.repeat(case.i_meas[:1], bsz, axis=0)
+    i_meas[sample] = case.i_meas
+    dev = torch.device("cuda")
+    t = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device=dev)
+    inp = dict(obj_a=t(case.a, torch.float32), obj_b=t(case.b, torch.float32), probe=t(case.p, torch.complex64),
+               corner=t(corner, torch.int32), shift=t(shift, torch.float32))
+    geom = Geometry.from_scan(sc, ckpt_every=16)
+    im = t(i_meas, torch.float32)
+    out = ctx.loss_grad(geom, **inp, i_meas=im, intensity=True)
+    torch.cuda.synchronize()
+    ctx.sync_error()
+    got_i = out["intensity"].cpu().numpy()[sample]
+    err_i = rel_l2(got_i, case.oracle_forward())
+    print("c3 sampled intensity rel-L2", err_i)
+    assert err_i <= TOL_I
+    scale = len(sample) / bsz
+    ref_gs = case.oracle_loss_grad()[4] * scale
+    f32_gs = loss_grad_fp32(case.geom, case.a, case.b, case.p, case.pos, case.i_meas)[4] * scale
+    got_gs = out["g_shift"].cpu().numpy()[sample]
+    e_gpu, e_f32 = rel_l2(got_gs, ref_gs), rel_l2(f32_gs, ref_gs)
+    print(f"c3 sampled shift gradients: GPU rel-L2 {e_gpu:.3e}, float32-model floor {e_f32:.3e}")
+    assert e_gpu <= max(TOL_G, 3.0 * e_f32)
+    # the autograd front end on the same inputs
+    a = inp["obj_a"].clone().requires_grad_(True)
+    pos_t = (inp["corner"].double() + inp["shift"].double()).requires_grad_(True)
+    loss = multislice_loss(a, inp["obj_b"], inp["probe"], pos_t, im, geom, ctx)
+    loss.backward()
+    assert float(loss) == float(out["loss"])
+    assert torch.equal(a.grad, out["g_a"])
+    assert torch.equal(pos_t.grad.float(), out["g_shift"])
