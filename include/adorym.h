@@ -79,7 +79,7 @@ enum {
  * order in FP64, rounding once to float32; loss, probe and shift gradients
  * are also reduced in a fixed order.  Every call is therefore reproducible
  * bit for bit for a given split.  ADORYM_DETERMINISTIC additionally fixes
- * the split per probe size (k = 1 for N <= 96, 4 for N = 128, 8 for
+ * the split per probe size (k = 1 for N <= 96, 4 for N = 128, 6 for
  * N = 192; adorym_set_split does not apply), so that results are also the
  * same bits between a single call and the same job inside a batched plan
  * next to other jobs, whatever split other calls use. */
@@ -194,9 +194,10 @@ const char* adorym_last_error_message(adorym_ctx* ctx);
  * n: k = 1 keeps the field in one workgroup (transposes through LDS);
  * k > 1 splits its lines over k workgroups that exchange through L2.
  * k = 0 restores the automatic choice (enough workgroups to cover the
- * CUs).  Supported: n = 64 and n = 96 with k in {1, 2, 4}; n = 128 with
- * k in {1, 2, 4, 8}; n = 192 with k in {2, 4, 8} (its field does not fit one
- * workgroup); else ADORYM_EUNSUPPORTED.  Results do not depend on k
+ * CUs).  Supported: n = 64 with k in {1, 2, 4}; n = 96 with k in
+ * {1, 2, 3, 4}; n = 128 with k in {1, 2, 4, 8}; n = 192 with k in
+ * {2, 4, 6, 8} (its field does not fit one workgroup); else
+ * ADORYM_EUNSUPPORTED.  Results do not depend on k
  * beyond float rounding of the gradient atomics. */
 adorym_status adorym_set_split(adorym_ctx* ctx, int32_t n, int32_t k);
 

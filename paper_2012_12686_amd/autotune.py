@@ -17,7 +17,7 @@ import torch
 
 from .api import Context, Job
 
-SPLITS = {64: (1, 2, 4), 96: (1, 2, 4), 128: (1, 2, 4, 8), 192: (2, 4, 8)}
+SPLITS = {64: (1, 2, 4), 96: (1, 2, 3, 4), 128: (1, 2, 4, 8), 192: (2, 4, 6, 8)}
 
 
 def _key(device_name: str, n: int, jobs: List[Job]) -> str:

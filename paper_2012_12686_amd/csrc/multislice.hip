@@ -29,6 +29,10 @@ extern template ADORYM_RUN_SIGNATURE(192, 8, 2);
 extern template ADORYM_BATCHED_SIGNATURE(192, 8, 2);
 extern template ADORYM_RUN_SIGNATURE(192, 8, 4);
 extern template ADORYM_BATCHED_SIGNATURE(192, 8, 4);
+extern template ADORYM_RUN_SIGNATURE(192, 8, 6);
+extern template ADORYM_BATCHED_SIGNATURE(192, 8, 6);
+extern template ADORYM_RUN_SIGNATURE(96, 8, 3);
+extern template ADORYM_BATCHED_SIGNATURE(96, 8, 3);
 extern template ADORYM_RUN_SIGNATURE(192, 8, 8);
 extern template ADORYM_BATCHED_SIGNATURE(192, 8, 8);
 extern template ADORYM_PARAMS_SIGNATURE(64, 4);
@@ -61,8 +65,8 @@ int split_of(const adorym_ctx* ctx, int n) {
 int pick_split(const adorym_ctx* ctx, int n, int batch) {
   const int forced = split_of(ctx, n);
   if (forced > 0) return forced;
-  // N = 192: eight workgroups of 3 waves (the only split without spills)
-  if (n == 192) return 8;
+  // N = 192: six workgroups of four waves (one wave per SIMD; fastest)
+  if (n == 192) return 6;
   // largest power-of-two split that keeps the grid within one workgroup per CU
   const int kmax = n == 128 ? 8 : 4;
   int k = 1;
@@ -88,6 +92,7 @@ adorym_status dispatch(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
     switch (k) {
       case 1: ADORYM_RUN(96, 8, 1);
       case 2: ADORYM_RUN(96, 8, 2);
+      case 3: ADORYM_RUN(96, 8, 3);
       case 4: ADORYM_RUN(96, 8, 4);
     }
   } else if (g->n == 128) {
@@ -101,6 +106,7 @@ adorym_status dispatch(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
     switch (k) {
       case 2: ADORYM_RUN(192, 8, 2);
       case 4: ADORYM_RUN(192, 8, 4);
+      case 6: ADORYM_RUN(192, 8, 6);
       case 8: ADORYM_RUN(192, 8, 8);
     }
   }
@@ -172,14 +178,20 @@ void class_launch(const PlanClass& c, const MsParams* d_params, int* err, hipStr
   if (c.n == 64) {
     if (c.k == 1) ADORYM_BATCH(64, 4, 1); else if (c.k == 2) ADORYM_BATCH(64, 4, 2); else ADORYM_BATCH(64, 4, 4);
   } else if (c.n == 96) {
-    if (c.k == 1) ADORYM_BATCH(96, 8, 1); else if (c.k == 2) ADORYM_BATCH(96, 8, 2); else ADORYM_BATCH(96, 8, 4);
+    if (c.k == 1) ADORYM_BATCH(96, 8, 1);
+    else if (c.k == 2) ADORYM_BATCH(96, 8, 2);
+    else if (c.k == 3) ADORYM_BATCH(96, 8, 3);
+    else ADORYM_BATCH(96, 8, 4);
   } else if (c.n == 128) {
     if (c.k == 1) ADORYM_BATCH(128, 8, 1);
     else if (c.k == 2) ADORYM_BATCH(128, 8, 2);
     else if (c.k == 4) ADORYM_BATCH(128, 8, 4);
     else ADORYM_BATCH(128, 8, 8);
   } else {
-    if (c.k == 2) ADORYM_BATCH(192, 8, 2); else if (c.k == 4) ADORYM_BATCH(192, 8, 4); else ADORYM_BATCH(192, 8, 8);
+    if (c.k == 2) ADORYM_BATCH(192, 8, 2);
+    else if (c.k == 4) ADORYM_BATCH(192, 8, 4);
+    else if (c.k == 6) ADORYM_BATCH(192, 8, 6);
+    else ADORYM_BATCH(192, 8, 8);
   }
 #undef ADORYM_BATCH
 }
@@ -373,9 +385,10 @@ adorym_status adorym_plan_destroy(adorym_plan* plan) {
 
 adorym_status adorym_set_split(adorym_ctx* ctx, int32_t n, int32_t k) {
   if (!ctx) return ADORYM_EINVAL;
-  const bool ok = k == 0 || ((n == 64 || n == 96) && (k == 1 || k == 2 || k == 4)) ||
+  const bool ok = k == 0 || (n == 64 && (k == 1 || k == 2 || k == 4)) ||
+                  (n == 96 && (k == 1 || k == 2 || k == 3 || k == 4)) ||
                   (n == 128 && (k == 1 || k == 2 || k == 4 || k == 8)) ||
-                  (n == 192 && (k == 2 || k == 4 || k == 8));
+                  (n == 192 && (k == 2 || k == 4 || k == 6 || k == 8));
   if (!ok) return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size / split");
   if (n == 64) ctx->split64 = k;
   else if (n == 96) ctx->split96 = k;

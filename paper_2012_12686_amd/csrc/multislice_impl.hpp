@@ -1045,7 +1045,7 @@ void launch_epilogue(const MsParams& P, void* ws, const adorym_geom* g, double* 
 
 // Deterministic mode runs with one fixed split per probe size, so that a
 // job's results do not depend on the split chosen for other calls.
-constexpr int det_split(int n) { return n == 192 ? 8 : (n == 128 ? 4 : 1); }
+constexpr int det_split(int n) { return n == 192 ? 6 : (n == 128 ? 4 : 1); }
 
 // One probe size N with lanes-per-line L and split K.
 template <int N, int L, int K>

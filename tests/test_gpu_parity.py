@@ -121,8 +121,9 @@ def test_loss_grad_matches_oracle(ctx, n, s, lat, npos, repr_, loss, ckpt):
     check_grads(got, ref, case)
 
 
-@pytest.mark.parametrize("n,k", [(64, 1), (64, 2), (64, 4), (96, 1), (96, 2), (96, 4),
-                                 (128, 1), (128, 2), (128, 4), (128, 8), (192, 2), (192, 4), (192, 8)])
+@pytest.mark.parametrize("n,k", [(64, 1), (64, 2), (64, 4), (96, 1), (96, 2), (96, 3), (96, 4),
+                                 (128, 1), (128, 2), (128, 4), (128, 8), (192, 2), (192, 4), (192, 6),
+                                 (192, 8)])
 def test_every_split_matches_oracle(ctx, n, k):
     """Fields split over k cooperating workgroups give the same results."""
     sc = synth.small_case(seed=300 + n + k, n=n, n_slices=7, lateral=n + 30, n_pos=3, strength=30.0)
