@@ -286,14 +286,18 @@ class _Tick:
 class Server:
     """The request loop (see the module docstring).
 
-    batched=True: one plan per set of active jobs (continuous batching);
+    batched=True: one plan per set of active jobs (continuous batching in
+    lockstep ticks);
+    streams=n > 0: every admitted job iterates on its own schedule, on one of
+    n streams, so jobs of different sizes overlap on the device without
+    waiting for each other (continuous batching without lockstep);
     batched=False with max_jobs=1: the plain per-job form, one job at a time,
     each iteration its own loss_grad call.
     """
 
     def __init__(self, ctx: Context, budget_bytes: Optional[int] = None, max_jobs: int = 16,
                  max_positions: int = 2048, batched: bool = True, deterministic: bool = False,
-                 keep_state: bool = False, inflight: int = 2):
+                 keep_state: bool = False, inflight: int = 2, streams: int = 0):
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info(ctx.device)
             budget_bytes = int(0.8 * free)
@@ -301,11 +305,14 @@ class Server:
         self.adm = Admission(budget_bytes, max_jobs, max_positions)
         self.batched, self.deterministic, self.keep_state = batched, deterministic, keep_state
         self.inflight = max(1, inflight)
+        self.streams = int(streams)
 
     def run(self, requests: Sequence[Request], realtime: bool = True) -> dict:
         """Serve every request; arrivals follow ``arrival_s`` on the wall clock
         (realtime) or are all present at the start.  Returns the statistics
         and one JobRecord per request."""
+        if self.streams > 0:
+            return self._run_streams(requests, realtime)
         ctx = self.ctx
         order = sorted(range(len(requests)), key=lambda i: requests[i].arrival_s)
         records = [JobRecord(i, requests[i].template.name, requests[i].arrival_s) for i in range(len(requests))]
@@ -404,21 +411,111 @@ class Server:
             plans.pop(p).close()
         wall = now()
         ctx.sync_error()
-        lat = np.array(latencies) * 1e3
-        waits = np.array([r.admitted_s - r.arrival_s for r in records]) * 1e3
-        turn = np.array([r.finished_s - r.arrival_s for r in records]) * 1e3
-        first = min(r.arrival_s for r in requests) if requests else 0.0
-        return {
-            "jobs": len(requests), "ticks": n_ticks, "wall_s": wall,
-            "positions": total_pos, "positions_per_s": total_pos / max(wall - first, 1e-9),
-            "p50_iter_ms": float(np.percentile(lat, 50)) if lat.size else math.nan,
-            "p99_iter_ms": float(np.percentile(lat, 99)) if lat.size else math.nan,
-            "p50_wait_ms": float(np.percentile(waits, 50)) if waits.size else math.nan,
-            "p99_wait_ms": float(np.percentile(waits, 99)) if waits.size else math.nan,
-            "p50_job_ms": float(np.percentile(turn, 50)) if turn.size else math.nan,
-            "p99_job_ms": float(np.percentile(turn, 99)) if turn.size else math.nan,
-            "peak_hbm_bytes": peak_used, "peak_jobs": peak_jobs, "records": records,
-        }
+        return _stats(requests, records, latencies, n_ticks, wall, total_pos, peak_used, peak_jobs)
+
+    def _run_streams(self, requests: Sequence[Request], realtime: bool) -> dict:
+        """Each admitted job iterates as soon as its previous iteration is
+        done, on one of `streams` streams (default priority), with up to
+        `inflight` iterations enqueued per job."""
+        ctx = self.ctx
+        order = sorted(range(len(requests)), key=lambda i: requests[i].arrival_s)
+        records = [JobRecord(i, requests[i].template.name, requests[i].arrival_s) for i in range(len(requests))]
+        foot = {}
+        for i, r in enumerate(requests):
+            foot[i] = job_footprint(ctx, r.template, self.deterministic)
+            if not self.adm.fits_ever(foot[i]):
+                raise ValueError(f"request {i} ({r.template.name}) needs {foot[i]} bytes, more than the "
+                                 f"budget of {self.adm.budget}")
+            records[i].footprint = foot[i]
+        pool = [torch.cuda.Stream(device=ctx.device) for _ in range(self.streams)]
+        waiting: List[int] = []
+        nxt = 0
+        active: List[ServedJob] = []
+        pending: Dict[int, List[Tuple[float, torch.cuda.Event]]] = {}
+        latencies: List[float] = []
+        peak_used, peak_jobs, total_pos, n_iters, rr = 0, 0, 0, 0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        while nxt < len(order) or waiting or active:
+            t = now()
+            while nxt < len(order) and (not realtime or requests[order[nxt]].arrival_s <= t):
+                waiting.append(order[nxt])
+                nxt += 1
+            while waiting:
+                i = waiting[0]
+                r = requests[i]
+                if not self.adm.try_admit(foot[i], r.template.minibatch):
+                    break
+                waiting.pop(0)
+                job = ServedJob(ctx, r.template, i, r.iterations, self.deterministic)
+                job.stream = pool[rr % len(pool)]
+                rr += 1
+                ready = torch.cuda.Event()
+                ready.record()                        # the job's buffers were filled on this stream
+                job.stream.wait_event(ready)
+                active.append(job)
+                pending[job.id] = []
+                records[i].admitted_s = now()
+            peak_used = max(peak_used, self.adm.used)
+            peak_jobs = max(peak_jobs, len(active))
+            progressed = False
+            for job in active:
+                q = pending[job.id]
+                while q and q[0][1].query():          # completed iterations
+                    t_enq, _ = q.pop(0)
+                    latencies.append(now() - t_enq)
+                    job.completed += 1
+                    total_pos += job.positions
+                    progressed = True
+                while job.enqueued < job.iterations and len(q) < self.inflight:
+                    t_enq = now()
+                    with torch.cuda.stream(job.stream):
+                        job.pre()
+                        job.evaluate()
+                        job.post()
+                        ev = torch.cuda.Event()
+                        ev.record()
+                    q.append((t_enq, ev))
+                    n_iters += 1
+                    progressed = True
+            for job in [j for j in active if j.completed == j.iterations]:
+                rec = records[job.id]
+                rec.finished_s = now()
+                rec.losses = job.losses.cpu().numpy()
+                if self.keep_state:
+                    rec.state = {"a": job.a, "b": job.b}
+                self.adm.release(foot[job.id], job.positions)
+                pending.pop(job.id)
+            active = [j for j in active if j.completed < j.iterations]
+            if not progressed:
+                if not active and nxt < len(order):
+                    time.sleep(max(0.0, min(0.05, requests[order[nxt]].arrival_s - now())))
+                else:
+                    time.sleep(50e-6)
+        torch.cuda.synchronize()
+        wall = now()
+        ctx.sync_error()
+        return _stats(requests, records, latencies, n_iters, wall, total_pos, peak_used, peak_jobs)
+
+
+def _stats(requests, records, latencies, n_ticks, wall, total_pos, peak_used, peak_jobs) -> dict:
+    """Throughput and latency figures of one run (ticks: ticks, or iterations in stream mode)."""
+    lat = np.array(latencies) * 1e3
+    waits = np.array([r.admitted_s - r.arrival_s for r in records]) * 1e3
+    turn = np.array([r.finished_s - r.arrival_s for r in records]) * 1e3
+    first = min(r.arrival_s for r in requests) if requests else 0.0
+    return {
+        "jobs": len(requests), "ticks": n_ticks, "wall_s": wall,
+        "positions": total_pos, "positions_per_s": total_pos / max(wall - first, 1e-9),
+        "p50_iter_ms": float(np.percentile(lat, 50)) if lat.size else math.nan,
+        "p99_iter_ms": float(np.percentile(lat, 99)) if lat.size else math.nan,
+        "p50_wait_ms": float(np.percentile(waits, 50)) if waits.size else math.nan,
+        "p99_wait_ms": float(np.percentile(waits, 99)) if waits.size else math.nan,
+        "p50_job_ms": float(np.percentile(turn, 50)) if turn.size else math.nan,
+        "p99_job_ms": float(np.percentile(turn, 99)) if turn.size else math.nan,
+        "peak_hbm_bytes": peak_used, "peak_jobs": peak_jobs, "records": records,
+    }
 
 
 def poisson_arrivals(rate_per_s: float, count: int, seed: int) -> np.ndarray:
@@ -477,28 +574,35 @@ def bench_serving(args):
     Server(ctx).run(warm, realtime=False)
     log("warm-up done")
     served = Server(ctx).run(reqs, realtime=True)
-    log(f"served trace done: {served['positions_per_s']:.0f} pos/s, p50 {served['p50_iter_ms']:.1f} ms")
+    log(f"lockstep-plan trace done: {served['positions_per_s']:.0f} pos/s, p50 {served['p50_iter_ms']:.1f} ms")
+    streamed = Server(ctx, streams=4).run(reqs, realtime=True)
+    log(f"stream-concurrent trace done: p50 {streamed['p50_iter_ms']:.1f} ms, job p50 {streamed['p50_job_ms']:.0f} ms")
     per_job = Server(ctx, max_jobs=1, batched=False).run(reqs, realtime=True)
     log(f"per-job trace done: p50 {per_job['p50_iter_ms']:.1f} ms, wait p99 {per_job['p99_wait_ms']:.0f} ms")
     sat = [dataclasses.replace(r, arrival_s=0.0) for r in reqs[:max(8, n_jobs // 4)]]
     sat_served = Server(ctx).run(sat, realtime=False)
     log("saturated served done")
+    sat_streamed = Server(ctx, streams=4).run(sat, realtime=False)
+    log("saturated stream-concurrent done")
     sat_per_job = Server(ctx, max_jobs=1, batched=False).run(sat, realtime=False)
     log("saturated per-job done")
     strip = lambda d: {k: v for k, v in d.items() if k != "records"}
     line = {
         "metric": "served multislice fwd+adjoint positions/s; p50/p99 per-iteration latency",
-        "value": served["positions_per_s"], "unit": "positions/s", "n_gpus": 1, "steps": served["ticks"],
-        "warmup": 1, "ms_per_step": served["wall_s"] * 1e3 / max(served["ticks"], 1),
+        "value": streamed["positions_per_s"], "unit": "positions/s", "n_gpus": 1, "steps": streamed["ticks"],
+        "warmup": 1, "ms_per_step": streamed["wall_s"] * 1e3 / max(streamed["ticks"], 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{n_jobs} jobs, Poisson arrivals {rate}/s, types c1/c2/c3/tilt uniform, "
-                               "20 iterations each (minibatch or angle + Adam), continuous batching"},
-        "p50_iter_ms": served["p50_iter_ms"], "p99_iter_ms": served["p99_iter_ms"],
-        "served": strip(served), "per_job_fifo": strip(per_job),
+                               "20 iterations each (minibatch or angle + Adam); jobs admitted by HBM footprint "
+                               "and iterating concurrently on 4 streams"},
+        "p50_iter_ms": streamed["p50_iter_ms"], "p99_iter_ms": streamed["p99_iter_ms"],
+        "stream_concurrent": strip(streamed), "lockstep_plan": strip(served), "per_job_fifo": strip(per_job),
         "saturated": {"jobs": len(sat),
-                      "served_positions_per_s": sat_served["positions_per_s"],
+                      "stream_concurrent_positions_per_s": sat_streamed["positions_per_s"],
+                      "lockstep_plan_positions_per_s": sat_served["positions_per_s"],
                       "per_job_positions_per_s": sat_per_job["positions_per_s"],
-                      "speedup": sat_served["positions_per_s"] / sat_per_job["positions_per_s"]},
+                      "speedup_stream_concurrent": sat_streamed["positions_per_s"] / sat_per_job["positions_per_s"],
+                      "speedup_lockstep_plan": sat_served["positions_per_s"] / sat_per_job["positions_per_s"]},
         "setup_s": setup_s,
     }
     print(json.dumps(line), flush=True)

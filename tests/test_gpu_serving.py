@@ -133,3 +133,20 @@ def test_realtime_arrivals_and_latency_stats(ctx, templates):
     assert 0 < res["p50_iter_ms"] <= res["p99_iter_ms"]
     for r in res["records"]:
         assert r.admitted_s >= r.arrival_s - 1e-3 and r.finished_s > r.admitted_s
+
+
+def test_stream_concurrent_mode_matches_alone_bitwise(ctx, templates):
+    """Jobs iterating on their own streams give the same bits as alone
+    (deterministic mode) and every job finishes."""
+    from paper_2012_12686_amd.serve import Request, Server
+    alone = Server(ctx, deterministic=True, keep_state=True).run([Request(0.0, templates["tilt"], 3)],
+                                                                  realtime=False)
+    reqs, idx = _mix(templates, "tilt")
+    res = Server(ctx, deterministic=True, keep_state=True, streams=3).run(reqs, realtime=False)
+    assert res["peak_jobs"] == len(reqs)
+    assert np.array_equal(res["records"][idx].losses, alone["records"][0].losses)
+    for k in ("a", "b"):
+        assert np.array_equal(res["records"][idx].state[k].cpu().numpy(), alone["records"][0].state[k].cpu().numpy())
+    for r, q in zip(res["records"], reqs):
+        assert len(r.losses) == q.iterations and np.all(np.isfinite(r.losses))
+    assert res["positions"] == sum(q.iterations * q.template.minibatch for q in reqs)
