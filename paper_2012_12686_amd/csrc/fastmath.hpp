@@ -15,6 +15,22 @@
 
 namespace adorym {
 
+// sin r, cos r for |r| <= pi/4 (no argument reduction).
+__device__ __forceinline__ void sincos_small_f32(float r, float& s, float& c) {
+  const float r2 = r * r;
+  float ps = fmaf(r2, -2.5052108385441718775e-8f, 2.7557319223985890653e-6f);
+  ps = fmaf(r2, ps, -1.9841269841269841270e-4f);
+  ps = fmaf(r2, ps, 8.3333333333333333333e-3f);
+  ps = fmaf(r2, ps, -1.6666666666666666667e-1f);
+  s = fmaf(r * r2, ps, r);
+  float pc = fmaf(r2, 2.0876756987868098979e-9f, -2.7557319223985890653e-7f);
+  pc = fmaf(r2, pc, 2.4801587301587301587e-5f);
+  pc = fmaf(r2, pc, -1.3888888888888888889e-3f);
+  pc = fmaf(r2, pc, 4.1666666666666666667e-2f);
+  pc = fmaf(r2, pc, -0.5f);
+  c = fmaf(r2, pc, 1.0f);
+}
+
 // sin(x), cos(x) for |x| < 2^15.
 __device__ __forceinline__ void sincos_f32(float x, float& s, float& c) {
   // pi/2 split: hi has 8 trailing zero bits so k*hi is exact for |k| < 2^16.
@@ -67,6 +83,13 @@ __device__ __forceinline__ float exp_f32(float x) {
   p = fmaf(r, p, 1.0f);
   p = fmaf(r, p, 1.0f);
   return ldexpf(p, (int)kf);
+}
+
+// exp(x) through the hardware base-2 exponential (1 ulp) of x log2(e); the
+// rounding of the product adds |x| * 2^-24 relative error, negligible for
+// the attenuations here (|x| << 1).  Flushes to 0 / inf outside the range.
+__device__ __forceinline__ float exp_hw(float x) {
+  return __builtin_amdgcn_exp2f(1.44269504088896340736f * x);
 }
 
 }  // namespace adorym

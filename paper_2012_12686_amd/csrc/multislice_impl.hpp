@@ -91,7 +91,7 @@ __device__ __forceinline__ void transmission(float kdz, float a, float b, float2
     float s, c;
     sincos_f32(kdz * a, s, c);
     const float v = kdz * b;
-    const float att = exp_f32(-v), gain = exp_f32(v);
+    const float att = exp_hw(-v), gain = __builtin_amdgcn_rcpf(att);
     t = make_float2(c * att, s * att);
     tinv = make_float2(c * gain, -s * gain);
   } else {
@@ -106,15 +106,25 @@ __device__ __forceinline__ void transmission(float kdz, float a, float b, float2
 template <class C, int REPR, bool INV>
 __device__ __forceinline__ void make_trans(float2 (&t)[C::R], float (&g2)[C::R], const float (&ca)[C::R],
                                            const float (&cb)[C::R], float kdz) {
+  // phases within +-pi/4 on the whole wave (the usual case: k dz delta is a
+  // few milliradians) skip the argument reduction
+  bool small = true;
+  if constexpr (REPR == ADORYM_OBJ_DELTA_BETA) {
+    float mx = 0.f;
+#pragma unroll
+    for (int m = 0; m < C::R; ++m) mx = fmaxf(mx, fabsf(kdz * ca[m]));
+    small = __all(mx <= 0.78f);
+  }
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
     if constexpr (REPR == ADORYM_OBJ_DELTA_BETA) {
       float s, c;
-      sincos_f32(kdz * ca[m], s, c);
+      if (small) sincos_small_f32(kdz * ca[m], s, c);
+      else sincos_f32(kdz * ca[m], s, c);
       const float v = kdz * cb[m];
-      const float att = exp_f32(-v);
+      const float att = exp_hw(-v);
       t[m] = make_float2(c * att, s * att);
-      if (INV) g2[m] = exp_f32(2.0f * v);
+      if (INV) g2[m] = __builtin_amdgcn_rcpf(att * att);
     } else {
       t[m] = make_float2(ca[m], cb[m]);
       if (INV) g2[m] = 1.0f / (ca[m] * ca[m] + cb[m] * cb[m]);
