@@ -284,6 +284,19 @@ def loss_grad(geom, obj_a, obj_b, probe, positions, i_meas):
     g_shift [B][2]).  ``g_shift`` is dL/ds for the residual shift s of each
     position, which equals dL/dr for the float position r.
     """
+    i_pred = forward(geom, obj_a, obj_b, probe, positions)
+    n_norm = i_pred.size
+    value = loss_value(geom.loss, i_pred, i_meas, geom.eps, n_norm)
+    d_di = loss_dI(geom.loss, i_pred, i_meas, geom.eps, n_norm)
+    return (value,) + reverse_sweep(geom, obj_a, obj_b, probe, positions, d_di)
+
+
+def reverse_sweep(geom, obj_a, obj_b, probe, positions, d_di):
+    """Gradient of a loss whose derivative with respect to the predicted
+    intensity I = |Psi|^2 of this probe is d_di [B][N][N]: the far-field
+    residual g = 2 d_di Psi is pulled back through the Fraunhofer transform,
+    each slice, the Fourier shift and the chunk gather.  Returns (g_a, g_b,
+    g_probe, g_shift) as in loss_grad."""
     corners, shifts = split_position(positions)
     n, s = geom.n, geom.n_slices
     kdz = geom.kdz
@@ -293,11 +306,8 @@ def loss_grad(geom, obj_a, obj_b, probe, positions, i_meas):
     t = transmission(ta, tb, geom.obj_repr, kdz)
     exit_phi, psis, phis = exit_waves(geom, obj_a, obj_b, probe, positions, keep_slices=True)
     psi_det = far_field(exit_phi)
-    i_pred = np.abs(psi_det) ** 2
-    n_norm = i_pred.size
-    value = loss_value(geom.loss, i_pred, i_meas, geom.eps, n_norm)
 
-    g_det = 2.0 * loss_dI(geom.loss, i_pred, i_meas, geom.eps, n_norm) * psi_det
+    g_det = 2.0 * d_di * psi_det
     lam = far_field_adjoint(g_det)                       # dL/dphi_{S-1}
     g_ta = np.empty_like(ta)
     g_tb = np.empty_like(tb)
@@ -330,4 +340,40 @@ def loss_grad(geom, obj_a, obj_b, probe, positions, i_meas):
 
     g_a = scatter_chunks(g_ta, corners, obj_a.shape)
     g_b = scatter_chunks(g_tb, corners, obj_b.shape)
-    return value, g_a, g_b, g_probe, g_shift
+    return g_a, g_b, g_probe, g_shift
+
+
+# ---------------------------------------------------------------------------
+# Several mutually incoherent probe modes (Eq. multimode)
+# ---------------------------------------------------------------------------
+
+def forward_modes(geom, obj_a, obj_b, probes, positions):
+    """Predicted intensity with probe modes probes [M][N][N]: each mode goes
+    through the object on its own and the detector adds their intensities,
+    I = sum_m |Psi_m|^2 (Eq. multimode)."""
+    return sum(forward(geom, obj_a, obj_b, p, positions) for p in probes)
+
+
+def loss_modes(geom, obj_a, obj_b, probes, positions, i_meas):
+    return loss_value(geom.loss, forward_modes(geom, obj_a, obj_b, probes, positions), i_meas, geom.eps)
+
+
+def loss_grad_modes(geom, obj_a, obj_b, probes, positions, i_meas):
+    """Loss of the summed intensity and its gradient.
+
+    dL/dI is taken at the summed intensity; each mode's reverse sweep starts
+    from 2 dL/dI Psi_m.  Object and shift gradients add over the modes (every
+    mode sees the same object and moves with the same position); the probe
+    gradient is per mode, [M][N][N].
+    """
+    i_pred = forward_modes(geom, obj_a, obj_b, probes, positions)
+    n_norm = i_pred.size
+    value = loss_value(geom.loss, i_pred, i_meas, geom.eps, n_norm)
+    d_di = loss_dI(geom.loss, i_pred, i_meas, geom.eps, n_norm)
+    g_a = g_b = g_shift = 0.0
+    g_probe = []
+    for p in probes:
+        ga, gb, gp, gs = reverse_sweep(geom, obj_a, obj_b, p, positions, d_di)
+        g_a, g_b, g_shift = g_a + ga, g_b + gb, g_shift + gs
+        g_probe.append(gp)
+    return value, g_a, g_b, np.stack(g_probe), g_shift

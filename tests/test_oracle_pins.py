@@ -421,3 +421,92 @@ def test_adam_first_step_closed_form():
     # constant gradient: bias-corrected moments stay exactly g and g^2
     x2, m, v = oadam.adam_step(x1, g, m, v, 2, lr=1e-3)
     assert np.allclose(x2, x1 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------- probe modes (Eq. multimode)
+
+def _modes_case(loss="gaussian", n_modes=3):
+    geom, a, b, p, pos, _ = _fd_case(loss, "delta_beta")
+    rng = np.random.default_rng(7)
+    probes = np.stack([p] + [0.4 * p * np.exp(1j * rng.uniform(-1, 1, p.shape)) for _ in range(n_modes - 1)])
+    sc = synth.config3_fd_subcase()
+    i_true = om.forward_modes(geom, sc.obj_a, sc.obj_b, probes * 1.1, sc.positions)
+    i_meas = i_true if loss == "gaussian" else rng.poisson(i_true).astype(float)
+    return geom, a, b, probes, pos, i_meas
+
+
+def test_one_mode_is_the_single_probe_model():
+    geom, a, b, probes, pos, i_meas = _modes_case(n_modes=1)
+    p = probes[0]
+    assert np.array_equal(om.forward_modes(geom, a, b, probes, pos), om.forward(geom, a, b, p, pos))
+    one = om.loss_grad(geom, a, b, p, pos, i_meas)
+    many = om.loss_grad_modes(geom, a, b, probes, pos, i_meas)
+    assert many[0] == one[0]
+    for x, y in zip(many[1:], one[1:]):
+        assert np.allclose(np.squeeze(x), y, rtol=0, atol=1e-15 * np.max(np.abs(y)))
+
+
+def test_two_halves_of_one_probe_equal_that_probe():
+    """p/sqrt2 twice carries the same power: I, L, object and shift gradients
+    equal the single-probe ones; each mode's probe gradient is g_p / sqrt2."""
+    for loss in ("gaussian", "poisson"):
+        geom, a, b, probes, pos, i_meas = _modes_case(loss, n_modes=1)
+        p = probes[0]
+        half = np.stack([p, p]) / np.sqrt(2.0)
+        L1, ga1, gb1, gp1, gs1 = om.loss_grad(geom, a, b, p, pos, i_meas)
+        L2, ga2, gb2, gp2, gs2 = om.loss_grad_modes(geom, a, b, half, pos, i_meas)
+        assert rel(om.forward_modes(geom, a, b, half, pos), om.forward(geom, a, b, p, pos)) < 1e-14
+        assert L2 == pytest.approx(L1, rel=1e-13)
+        for x, y in ((ga2, ga1), (gb2, gb1), (gs2, gs1), (gp2[0], gp1 / np.sqrt(2)), (gp2[1], gp1 / np.sqrt(2))):
+            assert rel(x, y) < 1e-12
+
+
+def test_intensity_is_invariant_under_unitary_mixing_of_modes():
+    """The incoherent sum over modes depends only on the modes' span with its
+    metric: p'_m = sum_k U_mk p_k with U unitary leaves I unchanged (a model
+    that added amplitudes instead of intensities would not)."""
+    geom, a, b, probes, pos, _ = _modes_case(n_modes=3)
+    rng = np.random.default_rng(21)
+    u, _ = np.linalg.qr(crand(3, 3, rng=rng))
+    mixed = np.einsum("mk,kyx->myx", u, probes)
+    assert rel(om.forward_modes(geom, a, b, mixed, pos), om.forward_modes(geom, a, b, probes, pos)) < 1e-13
+    single = om.forward(geom, a, b, probes.sum(axis=0), pos)
+    assert rel(single, om.forward_modes(geom, a, b, probes, pos)) > 1e-3
+
+
+@pytest.mark.parametrize("loss", ["gaussian", "poisson"])
+def test_mode_gradients_match_central_finite_differences(loss):
+    geom, a, b, probes, pos, i_meas = _modes_case(loss, n_modes=3)
+    L, ga, gb, gp, gs = om.loss_grad_modes(geom, a, b, probes, pos, i_meas)
+
+    def f(a_=a, probes_=probes, pos_=pos):
+        return om.loss_modes(geom, a_, b, probes_, pos_, i_meas)
+
+    rng = np.random.default_rng(5)
+    hu = 1e-3
+    checks = []
+    corners, _ = om.split_position(pos)
+    for _ in range(6):
+        k = rng.integers(len(corners))
+        z, y, x = rng.integers(geom.n_slices), corners[k, 0] + rng.integers(geom.n), corners[k, 1] + rng.integers(geom.n)
+        ap, am = a.copy(), a.copy()
+        ap[z, y, x] += hu / geom.kdz
+        am[z, y, x] -= hu / geom.kdz
+        checks.append(((f(a_=ap) - f(a_=am)) / (2 * hu / geom.kdz), ga[z, y, x]))
+    hp = hu * np.max(np.abs(probes))
+    for m in range(len(probes)):
+        iy, ix = rng.integers(geom.n, size=2)
+        for unit, comp in ((1.0, np.real), (1j, np.imag)):
+            pp, pm = probes.copy(), probes.copy()
+            pp[m, iy, ix] += unit * hp
+            pm[m, iy, ix] -= unit * hp
+            checks.append(((f(probes_=pp) - f(probes_=pm)) / (2 * hp), comp(gp[m, iy, ix])))
+    for k in range(len(pos)):
+        for ax in range(2):
+            pp, pm = pos.copy(), pos.copy()
+            pp[k, ax] += hu
+            pm[k, ax] -= hu
+            checks.append(((f(pos_=pp) - f(pos_=pm)) / (2 * hu), gs[k, ax]))
+    fd = np.array([c[0] for c in checks])
+    an = np.array([c[1] for c in checks])
+    assert np.max(np.abs(fd - an)) < 2e-5 * np.max(np.abs(an)), (fd, an)
