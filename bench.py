@@ -101,6 +101,7 @@ def main():
                          "batched vs per-job; serving: the request loop")
     ap.add_argument("--ckpt", type=int, default=16, help="slice checkpoint interval of the adjoint")
     ap.add_argument("--deterministic", action="store_true", help="FP64 ordered object-gradient sums")
+    ap.add_argument("--modes", type=int, default=1, help="incoherent probe modes (Eq. multimode)")
     ap.add_argument("--jobs", type=int, default=200, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=4.0, help="serving: Poisson arrival rate (jobs/s)")
     args = ap.parse_args()
@@ -142,11 +143,14 @@ def main():
 
     to_t = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device=dev)
     true_a, true_b = to_t(sc.obj_a, torch.float32), to_t(sc.obj_b, torch.float32)
-    probe = to_t(sc.probe, torch.complex64)
+    n_modes = args.modes
+    probes = to_t(synth.probe_modes(sc.probe, n_modes, seed=11), torch.complex64)
+    probe = probes[0]
     corner, shift = split_positions(to_t(sc.positions, torch.float64))
     # synthetic measurements: Poisson counts of the forward model at the truth
-    i_true = torch.cat([ctx.forward(geom, true_a, true_b, probe, corner[k * mb:(k + 1) * mb],
-                                    shift[k * mb:(k + 1) * mb]) for k in range(n_mb)])
+    # (summed over the probe modes)
+    i_true = torch.cat([sum(ctx.forward(geom, true_a, true_b, p, corner[k * mb:(k + 1) * mb],
+                                        shift[k * mb:(k + 1) * mb]) for p in probes) for k in range(n_mb)])
     rng = np.random.default_rng(2)
     i_meas_np = rng.poisson(i_true.cpu().numpy().astype(np.float64)).astype(np.float32)
     i_meas = to_t(i_meas_np, torch.float32)
@@ -154,14 +158,21 @@ def main():
     # evaluation point: delta = beta = 0
     a = torch.zeros_like(true_a)
     b = torch.zeros_like(true_b)
-    ws = ctx.workspace(geom, mb)
+    if n_modes == 1:
+        ws = ctx.workspace(geom, mb)
+    else:
+        ws = torch.empty(ctx.modes_workspace_size(geom, mb, n_modes), dtype=torch.uint8, device=dev)
     out = {"loss": torch.empty((), dtype=torch.float64, device=dev),
            "g_a": torch.empty_like(a), "g_b": torch.empty_like(b),
-           "g_probe": torch.empty_like(probe), "g_shift": torch.empty((mb, 2), dtype=torch.float32, device=dev)}
+           "g_probe": torch.empty_like(probe if n_modes == 1 else probes),
+           "g_shift": torch.empty((mb, 2), dtype=torch.float32, device=dev)}
 
     def step(k):
         sl = slice((k % n_mb) * mb, (k % n_mb + 1) * mb)
-        ctx.loss_grad(geom, a, b, probe, corner[sl], shift[sl], i_meas[sl], out=out, workspace=ws)
+        if n_modes == 1:
+            ctx.loss_grad(geom, a, b, probe, corner[sl], shift[sl], i_meas[sl], out=out, workspace=ws)
+        else:
+            ctx.loss_grad_modes(geom, a, b, probes, corner[sl], shift[sl], i_meas[sl], out=out, workspace=ws)
 
     for k in range(args.warmup):
         step(k)
@@ -170,7 +181,7 @@ def main():
 
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ctx.profile_start(args.steps + 8)
+    ctx.profile_start(args.steps * 2 * n_modes + 8)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -191,6 +202,11 @@ def main():
 
     kern_avg_s = kern_ms / max(kern_n, 1) / 1e3
     bytes_launch = algorithmic_bytes_per_position(n, s, args.ckpt) * mb
+    if n_modes > 1:
+        # M forward launches (object read, intensity written) and M
+        # loss+adjoint launches (which also read the summed intensity)
+        fwd = 8 * n * n * s + 4 * n * n
+        bytes_launch = (fwd + algorithmic_bytes_per_position(n, s, args.ckpt) + 4 * n * n) * mb / 2
     achieved_gbs = bytes_launch / kern_avg_s / 1e9
     flops_launch = algorithmic_flops_per_position(n, s) * mb
     achieved_tflops = flops_launch / kern_avg_s / 1e12
@@ -209,18 +225,21 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "multislice ptychography N=128 S=64 object 256x256x64 (10 nm, 10 keV), "
-                               "minibatch 50 of 400 positions, Poisson 1e4 photons, fwd+loss+adjoint",
+                               "minibatch 50 of 400 positions, Poisson 1e4 photons, fwd+loss+adjoint"
+                               + (f", {n_modes} incoherent probe modes" if n_modes > 1 else ""),
                    "global_batch": mb, "seq_len": s, "parallelism": "none"},
         "p50_iter_ms": p50,
         "p99_iter_ms": p99,
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "multislice_kernel<N=128, delta/beta, Poisson, loss+adjoint>",
+                     "frac": achieved_gbs / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if n_modes == 1 else None,
+                     "kernel": "multislice_kernel<N=128, delta/beta, Poisson, loss+adjoint>" if n_modes == 1 else
+                               "multislice_kernel<N=128>: forward and loss+adjoint launches, averaged",
                      "kernel_avg_ms": kern_avg_s * 1e3, "kernel_launches": kern_n,
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "fp32_tflops": achieved_tflops, "fp32_frac": achieved_tflops / FP32_PEAK_TFLOPS},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and n_modes == 1:
         line["cpu_baseline"] = cpu_baseline(sc, slice(0, mb), i_meas_np[:mb].astype(np.float64))
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -143,6 +143,26 @@ adorym_status adorym_loss_grad(adorym_ctx* ctx, const adorym_geom* g,
                                double* loss, float* g_a, float* g_b, float* g_probe,
                                float* g_shift, float* intensity);
 
+/* ---- Several mutually incoherent probe modes (Eq. multimode) ----------
+ * The detector records the sum over modes m of |Psi_m|^2, each mode
+ * propagated through the same object at the same positions; the loss is the
+ * one of adorym_loss_grad evaluated at that summed intensity.
+ * probes: complex [M][N][N].  Outputs as adorym_loss_grad, except g_probe
+ * complex [M][N][N] (one gradient per mode) and `intensity`, if given, the
+ * summed intensity.  g_a, g_b and g_shift are sums over the modes.
+ * Runs M forward passes (the summed intensity), then M loss-and-gradient
+ * passes, all on the context's stream.  Workspace of
+ * adorym_modes_workspace_size(g, batch, M) bytes: two intensity planes
+ * [B][N][N] and one adorym_loss_grad workspace.  With M = 1 the results
+ * equal those of adorym_loss_grad. */
+size_t adorym_modes_workspace_size(const adorym_geom* g, int32_t batch, int32_t n_modes);
+adorym_status adorym_loss_grad_modes(adorym_ctx* ctx, const adorym_geom* g,
+                                     const float* obj_a, const float* obj_b, const float* probes,
+                                     int32_t n_modes, const int32_t* corner, const float* shift,
+                                     int32_t batch, const float* i_meas, void* workspace, size_t ws_bytes,
+                                     double* loss, float* g_a, float* g_b, float* g_probe,
+                                     float* g_shift, float* intensity);
+
 /* Tilt rotation of a slice-major float32 object [lz][ly][lx] about the y
  * axis (Sec. S1.D.2, Eq. rotation_transform): every xz-plane is resampled
  * by bilinear interpolation at (x0, z0) = R(theta)(x_t - cx, z_t - cz) + c,

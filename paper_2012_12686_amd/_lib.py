@@ -61,6 +61,9 @@ SIGNATURES = {
     "adorym_forward": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t]),
     "adorym_loss_grad": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t,
                                         _P, _P, _P, _P, _P, _P]),
+    "adorym_modes_workspace_size": (ctypes.c_size_t, [_GP, ctypes.c_int32, ctypes.c_int32]),
+    "adorym_loss_grad_modes": (ctypes.c_int, [_P, _GP, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P,
+                                              ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),
     "adorym_rotate": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                      ctypes.c_int]),
     "adorym_adam": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_size_t, ctypes.c_double, ctypes.c_double,

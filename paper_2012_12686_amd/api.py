@@ -174,6 +174,45 @@ class Context:
         check(st, self._ctx)
         return out
 
+    def modes_workspace_size(self, geom: Geometry, batch: int, n_modes: int) -> int:
+        return int(load().adorym_modes_workspace_size(ctypes.byref(geom.to_c()), batch, n_modes))
+
+    def loss_grad_modes(self, geom, obj_a, obj_b, probes, corner, shift, i_meas, grads=True, intensity=False,
+                        out=None, workspace=None):
+        """Loss and gradients for M incoherent probe modes ``probes`` complex64 [M][N][N]
+        (Eq. multimode): the loss sees the intensity summed over the modes.
+
+        Same outputs as :meth:`loss_grad`, with ``g_probe`` [M][N][N] and
+        ``intensity`` the summed intensity.
+        """
+        self._bind_stream()
+        if probes.dim() != 3 or probes.dtype != torch.complex64 or not probes.is_contiguous():
+            raise ValueError("probes: expected contiguous complex64 [M][N][N]")
+        m = probes.shape[0]
+        b = self._check_inputs(geom, obj_a, obj_b, probes[0], corner, shift)
+        if tuple(i_meas.shape) != (b, geom.n, geom.n) or i_meas.dtype != torch.float32 or not i_meas.is_contiguous():
+            raise ValueError("i_meas: expected contiguous float32 [B][N][N]")
+        out = dict(out or {})
+        dev = self.device
+        if "loss" not in out:
+            out["loss"] = torch.empty((), dtype=torch.float64, device=dev)
+        if grads:
+            for name, shape, dt in (("g_a", obj_a.shape, torch.float32), ("g_b", obj_b.shape, torch.float32),
+                                    ("g_probe", probes.shape, torch.complex64), ("g_shift", (b, 2), torch.float32)):
+                if name not in out:
+                    out[name] = (torch.zeros if geom.accumulate else torch.empty)(shape, dtype=dt, device=dev)
+        if intensity and "intensity" not in out:
+            out["intensity"] = torch.empty((b, geom.n, geom.n), dtype=torch.float32, device=dev)
+        ws = workspace if workspace is not None else torch.empty(self.modes_workspace_size(geom, b, m),
+                                                                 dtype=torch.uint8, device=dev)
+        gp = out.get("g_probe")
+        st = load().adorym_loss_grad_modes(
+            self._ctx, ctypes.byref(geom.to_c()), _ptr(obj_a), _ptr(obj_b), _ptr(torch.view_as_real(probes)), m,
+            _ptr(corner), _ptr(shift), b, _ptr(i_meas), _ptr(ws), ws.numel(), _ptr(out["loss"]),
+            _ptr(out.get("g_a")), _ptr(out.get("g_b")), _ptr(torch.view_as_real(gp) if gp is not None else None),
+            _ptr(out.get("g_shift")), _ptr(out.get("intensity")))
+        check(st, self._ctx)
+        return out
 
     def rotate(self, obj: torch.Tensor, theta: float, transpose: bool = False, out=None) -> torch.Tensor:
         """Rotate a float32 [Z][Y][X] object about y by theta (radians); transpose=True is R^T."""

@@ -15,4 +15,8 @@ struct adorym_ctx {
   bool prof = false;
   // workgroups per position (0 = automatic) for N = 64, 96, 128 and 192
   int split64 = 0, split96 = 0, split128 = 0, split192 = 0;
+  // summed intensity of all probe modes [B][N][N] while adorym_loss_grad_modes
+  // runs one mode's loss and gradient (the loss is taken at this intensity);
+  // null otherwise
+  const float* i_total = nullptr;
 };

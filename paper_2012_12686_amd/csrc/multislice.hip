@@ -196,6 +196,16 @@ void class_launch(const PlanClass& c, const MsParams* d_params, int* err, hipStr
 #undef ADORYM_BATCH
 }
 
+// dst += src (n floats); dst = 0 (n floats)
+__global__ void add_into_kernel(float* __restrict__ dst, const float* __restrict__ src, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] += src[i];
+}
+__global__ void zero_kernel(float* __restrict__ dst, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = 0.f;
+}
+
 }  // namespace
 
 extern "C" {
@@ -265,6 +275,63 @@ adorym_status adorym_loss_grad(adorym_ctx* ctx, const adorym_geom* g, const floa
   if (ws_bytes < adorym_workspace_size(g, batch)) return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
   return dispatch(ctx, g, obj_a, obj_b, probe, corner, shift, batch, i_meas, workspace, loss, g_a, g_b, g_probe,
                   g_shift, intensity, true);
+}
+
+// ---- Several incoherent probe modes --------------------------------------
+size_t adorym_modes_workspace_size(const adorym_geom* g, int32_t batch, int32_t n_modes) {
+  const size_t one = adorym_workspace_size(g, batch);
+  if (one == 0 || n_modes < 1) return 0;
+  const size_t plane = align256((size_t)batch * g->n * g->n * sizeof(float));
+  return 2 * plane + one;
+}
+
+adorym_status adorym_loss_grad_modes(adorym_ctx* ctx, const adorym_geom* g, const float* obj_a, const float* obj_b,
+                                     const float* probes, int32_t n_modes, const int32_t* corner, const float* shift,
+                                     int32_t batch, const float* i_meas, void* workspace, size_t ws_bytes,
+                                     double* loss, float* g_a, float* g_b, float* g_probe, float* g_shift,
+                                     float* intensity) {
+  adorym_status st = check_geom(ctx, g, batch);
+  if (st != ADORYM_OK) return st;
+  if (n_modes < 1) return set_err(ctx, ADORYM_EINVAL, "n_modes must be >= 1");
+  if (!obj_a || !obj_b || !probes || !corner || !shift || !i_meas || !workspace || !loss)
+    return set_err(ctx, ADORYM_EINVAL, "NULL array argument");
+  if ((g_a == nullptr) != (g_b == nullptr)) return set_err(ctx, ADORYM_EINVAL, "g_a and g_b must both be given");
+  if (ws_bytes < adorym_modes_workspace_size(g, batch, n_modes))
+    return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
+  const size_t nn = (size_t)g->n * g->n, nb = (size_t)batch * nn;
+  const size_t plane = align256(nb * sizeof(float));
+  float* i_tot = static_cast<float*>(workspace);
+  float* i_mode = reinterpret_cast<float*>(static_cast<char*>(workspace) + plane);
+  void* ws = static_cast<char*>(workspace) + 2 * plane;
+  hipStream_t s = ctx->stream;
+  const int blocks = (int)std::min<size_t>((nb + 255) / 256, 4096);
+  // 1. every mode's intensity, summed
+  for (int m = 0; m < n_modes; ++m) {
+    st = dispatch(ctx, g, obj_a, obj_b, probes + (size_t)m * 2 * nn, corner, shift, batch, nullptr, ws, nullptr,
+                  nullptr, nullptr, nullptr, nullptr, m == 0 ? i_tot : i_mode, false);
+    if (st != ADORYM_OK) return st;
+    if (m > 0) hipLaunchKernelGGL(add_into_kernel, dim3(blocks), dim3(256), 0, s, i_tot, i_mode, nb);
+  }
+  // 2. every mode's reverse sweep from the loss at the summed intensity;
+  //    object and shift gradients add up over the modes, the probe gradient
+  //    is per mode
+  adorym_geom gm = *g;
+  ctx->i_total = i_tot;
+  for (int m = 0; m < n_modes && st == ADORYM_OK; ++m) {
+    if (m > 0) gm.flags |= ADORYM_ACCUMULATE_GRADS;
+    float* gp = g_probe ? g_probe + (size_t)m * 2 * nn : nullptr;
+    if (gp && m > 0 && !(g->flags & ADORYM_ACCUMULATE_GRADS))
+      hipLaunchKernelGGL(zero_kernel, dim3((int)std::min<size_t>((2 * nn + 255) / 256, 4096)), dim3(256), 0, s,
+                         gp, 2 * nn);
+    st = dispatch(ctx, &gm, obj_a, obj_b, probes + (size_t)m * 2 * nn, corner, shift, batch, i_meas, ws, loss, g_a,
+                  g_b, gp, g_shift, nullptr, true);
+  }
+  ctx->i_total = nullptr;
+  if (st != ADORYM_OK) return st;
+  if (intensity) (void)hipMemcpyAsync(intensity, i_tot, nb * sizeof(float), hipMemcpyDeviceToDevice, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
+  return ADORYM_OK;
 }
 
 adorym_status adorym_sync_error(adorym_ctx* ctx) {

@@ -49,6 +49,7 @@ struct MsParams {
   const int32_t* corner;   // [B][2]
   const float* shift;      // [B][2]
   const float* i_meas;     // [B][N][N]
+  const float* i_total;    // [B][N][N] intensity summed over probe modes, or null (one mode)
   float* intensity;        // [B][N][N] or null
   float* g_a;              // [S][Ly][Lx] or null
   float* g_b;
@@ -547,6 +548,7 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
   const float eps = (float)P.eps;
   const float inv_n = (float)P.inv_n;
   const rsrc_t rim = make_rsrc(LOSS ? (const void*)(P.i_meas + (size_t)b * NN) : (const void*)P.q, NN * 4);
+  const rsrc_t rtot = make_rsrc(P.i_total ? (const void*)(P.i_total + (size_t)b * NN) : (const void*)P.q, NN * 4);
   const rsrc_t rint = make_rsrc(P.intensity ? (const void*)(P.intensity + (size_t)b * NN) : (const void*)P.q, NN * 4);
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
@@ -559,14 +561,17 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
     if (P.intensity) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, ip), rint, det, 0, 0);
     if (LOSS) {
       const float imv = bload(rim, det, 0);
+      // the loss is a function of the detector intensity: with several probe
+      // modes that is their sum (Eq. multimode), this mode's own otherwise
+      const float it = P.i_total ? bload(rtot, det, 0) : ip;
       float term, dldi;
       if (P.loss == ADORYM_LOSS_GAUSSIAN) {
-        const float sp = sqrtf(ip + eps), sm = sqrtf(imv + eps);
+        const float sp = sqrtf(it + eps), sm = sqrtf(imv + eps);
         term = (sp - sm) * (sp - sm);
         dldi = (1.0f - sm / sp) * inv_n;
       } else {
-        term = ip - imv * logf(ip + eps);
-        dldi = (1.0f - imv / (ip + eps)) * inv_n;
+        term = it - imv * logf(it + eps);
+        dldi = (1.0f - imv / (it + eps)) * inv_n;
       }
       lsum += (double)term;
       // far-field residual 2 dL/dI Psi, scaled by 1/N for the adjoint DFT
@@ -699,10 +704,13 @@ __global__ void __launch_bounds__(C::THREADS) multislice_batched_kernel(const Ms
       group_barrier(wk.x.counter, C::K * wk.x.phase, wk.x.err);
       t = __hip_atomic_load(mailbox + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    // the ticket is the same for the whole workgroup: make that visible so
+    // the item and the job's parameters are loaded into scalar registers
+    t = __builtin_amdgcn_readfirstlane(t);
     if (t >= n_items) break;
     const int2 it = items[t];
-    wk.b = it.y;
-    process_position<C, REPR, true>(jobs[it.x], sh, wk);
+    wk.b = __builtin_amdgcn_readfirstlane(it.y);
+    process_position<C, REPR, true>(jobs[__builtin_amdgcn_readfirstlane(it.x)], sh, wk);
   }
 }
 
@@ -992,6 +1000,7 @@ MsParams make_params(adorym_ctx* ctx, const adorym_geom* g, const float* a, cons
   P.a = a; P.b = b;
   P.q = reinterpret_cast<const float2*>(base + w.q);
   P.corner = corner; P.shift = shift; P.i_meas = i_meas; P.intensity = intensity;
+  P.i_total = ctx->i_total;
   P.g_a = g_a; P.g_b = g_b;
   P.gstage = g_a ? reinterpret_cast<float*>(base + w.stage) : nullptr;
   P.ckpt = reinterpret_cast<float2*>(base + w.ckpt);

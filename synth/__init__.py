@@ -305,3 +305,15 @@ def small_case(seed: int, n: int, n_slices: int, lateral: int, n_pos: int,
                 wavelength_m=wavelength_from_energy(10000.0), pixel_m=10e-9, slice_dz_m=10e-9,
                 obj_repr=obj_repr, loss=loss, minibatch=n_pos, photons=photons,
                 eval_obj_a=ea, eval_obj_b=eb, eval_probe=eprobe, eval_positions=epos)
+
+
+def probe_modes(probe: np.ndarray, n_modes: int, seed: int, weight: float = 0.4) -> np.ndarray:
+    """[M][N][N] probe modes: the given probe first, then weaker copies of it
+    with a smooth random phase each (partial coherence; random inputs only)."""
+    rng = np.random.default_rng(seed)
+    n = probe.shape[0]
+    modes = [np.asarray(probe, dtype=np.complex128)]
+    for _ in range(n_modes - 1):
+        ph = smooth_random_field(rng, (1, n, n), 2.0, -4 * np.pi, 4 * np.pi)[0]
+        modes.append(weight * modes[0] * np.exp(1j * ph))
+    return np.stack(modes)

@@ -24,7 +24,8 @@ def _c64(x):
     return np.asarray(x).astype(C64)
 
 
-def loss_grad_fp32(geom, a, b, p, pos, i_meas):
+def _forward(geom, a, b, p, pos):
+    """Every slice's wave and the detector field of one probe, in float32."""
     n, s = geom.n, geom.n_slices
     corner = np.floor(pos + 0.5).astype(np.int64)
     shift = (pos - corner).astype(F32)
@@ -51,7 +52,10 @@ def loss_grad_fp32(geom, a, b, p, pos, i_meas):
         if j < s - 1:
             psi = sfft.ifft2(sfft.fft2(phi, norm="ortho") * h, norm="ortho")
     det = np.fft.fftshift(sfft.ifft2(phi, norm="ortho"), axes=(-2, -1))
-    ip = (det.real ** 2 + det.imag ** 2).astype(F32)
+    return dict(corner=corner, f=f, h=h, kdz=kdz, t=t, e=e, pf=pf, psis=psis, phis=phis, det=det)
+
+
+def _loss(geom, ip, i_meas):
     im = i_meas.astype(F32)
     eps = F32(geom.eps)
     nn = F32(ip.size)
@@ -62,6 +66,13 @@ def loss_grad_fp32(geom, a, b, p, pos, i_meas):
     else:
         value = float(np.sum((ip - im * np.log(ip + eps)).astype(np.float64))) / ip.size
         dldi = (F32(1) - im / (ip + eps)) / nn
+    return value, dldi
+
+
+def _reverse(geom, st, a, b, dldi):
+    n, s = geom.n, geom.n_slices
+    corner, f, h, kdz, t, e, pf = (st[k] for k in ("corner", "f", "h", "kdz", "t", "e", "pf"))
+    psis, phis, det = st["psis"], st["phis"], st["det"]
     lam = sfft.fft2(np.fft.ifftshift((F32(2) * dldi * det).astype(C64), axes=(-2, -1)), norm="ortho")
     ga = np.zeros(a.shape, F32)
     gb = np.zeros(b.shape, F32)
@@ -83,4 +94,31 @@ def loss_grad_fp32(geom, a, b, p, pos, i_meas):
     z = np.conj(big_g) * pf[None] * e
     gs = np.stack([2 * np.pi * np.sum(f[None, :, None] * z.imag, axis=(1, 2)),
                    2 * np.pi * np.sum(f[None, None, :] * z.imag, axis=(1, 2))], axis=1)
-    return value, ga, gb, gp, gs
+    return ga, gb, gp, gs
+
+
+def _intensity(det):
+    return (det.real ** 2 + det.imag ** 2).astype(F32)
+
+
+def loss_grad_fp32(geom, a, b, p, pos, i_meas):
+    st = _forward(geom, a, b, p, pos)
+    value, dldi = _loss(geom, _intensity(st["det"]), i_meas)
+    return (value,) + _reverse(geom, st, a, b, dldi)
+
+
+def loss_grad_fp32_modes(geom, a, b, probes, pos, i_meas):
+    """Several incoherent probe modes: the loss at the summed intensity,
+    object and shift gradients summed over modes, one probe gradient each."""
+    sts = [_forward(geom, a, b, p, pos) for p in probes]
+    ip = sts[0]["det"].real * 0
+    for st in sts:
+        ip = ip + _intensity(st["det"])
+    value, dldi = _loss(geom, ip.astype(F32), i_meas)
+    ga = gb = gs = 0
+    gps = []
+    for st in sts:
+        a_, b_, p_, s_ = _reverse(geom, st, a, b, dldi)
+        ga, gb, gs = ga + a_, gb + b_, gs + s_
+        gps.append(p_)
+    return value, ga, gb, np.stack(gps), gs

@@ -1,0 +1,138 @@
+"""GPU parity of several incoherent probe modes (Eq. multimode) against the
+FP64 oracle, through the C ABI (adorym_loss_grad_modes).
+
+Tolerances as in the single-probe parity tests: summed intensity rel-L2
+<= 1e-5; loss within the intensity tolerance pushed through the loss; every
+gradient (g_probe now [M][N][N]) rel-L2 <= 1e-4 or <= 3x the float32 model's
+own error at that point.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_helpers import Case, f32, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL_I = 1e-5
+TOL_G = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_12686_amd import Context
+    c = Context()
+    yield c
+    c.close()
+
+
+class ModesCase(Case):
+    """A scan with M probe modes; the measurement is the oracle's summed
+    intensity at the true object, positions and modes."""
+
+    def __init__(self, scan, n_modes, seed, poisson_seed=None):
+        super().__init__(scan)
+        from oracle import multislice as om
+        self.probes = f32(synth.probe_modes(self.p, n_modes, seed))
+        true_modes = synth.probe_modes(scan.probe, n_modes, seed)
+        i_true = om.forward_modes(self.geom, scan.obj_a, scan.obj_b, true_modes, np.asarray(scan.positions))
+        if poisson_seed is not None:
+            i_true = np.random.default_rng(poisson_seed).poisson(i_true).astype(np.float64)
+        self.i_meas = f32(i_true)
+
+    def run(self, ctx, **kw):
+        import torch
+        from paper_2012_12686_amd import Geometry
+        inp, i_meas = self.torch_inputs()
+        inp.pop("probe")
+        probes = torch.as_tensor(self.probes, dtype=torch.complex64, device="cuda").contiguous()
+        out = ctx.loss_grad_modes(Geometry.from_scan(self.scan, **kw), probes=probes, i_meas=i_meas,
+                                  intensity=True, **inp)
+        torch.cuda.synchronize()
+        ctx.sync_error()
+        return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def check(got, case):
+    from oracle import multislice as om
+    from tests.fp32_model import loss_grad_fp32_modes
+    i_ref = om.forward_modes(case.geom, case.a, case.b, case.probes, case.pos)
+    e_i = rel_l2(got["intensity"], i_ref)
+    print(f"summed intensity rel-L2 {e_i:.3e}")
+    assert e_i <= TOL_I
+    L, ga, gb, gp, gs = om.loss_grad_modes(case.geom, case.a, case.b, case.probes, case.pos, case.i_meas)
+    dldi = om.loss_dI(case.geom.loss, i_ref, case.i_meas, case.geom.eps, i_ref.size)
+    tol_l = 2 * TOL_I * np.linalg.norm(i_ref) * np.linalg.norm(dldi)
+    assert abs(float(got["loss"]) - L) <= tol_l, (float(got["loss"]), L, tol_l)
+    model = loss_grad_fp32_modes(case.geom, case.a, case.b, case.probes, case.pos, case.i_meas)
+    for name, r, m in zip(("g_a", "g_b", "g_probe", "g_shift"), (ga, gb, gp, gs), model[1:]):
+        e_gpu, e_f32 = rel_l2(got[name], r), rel_l2(m, r)
+        print(f"{name}: GPU rel-L2 {e_gpu:.3e}   float32-model floor {e_f32:.3e}")
+        assert e_gpu <= max(TOL_G, 3.0 * e_f32), (name, e_gpu, e_f32)
+    # every mode's probe gradient on its own, not only their stack
+    for m in range(case.probes.shape[0]):
+        assert rel_l2(got["g_probe"][m], gp[m]) <= max(TOL_G, 3.0 * rel_l2(model[3][m], gp[m])), m
+
+
+@pytest.mark.parametrize("n,s,lat,npos,m,repr_,loss", [
+    (64, 4, 96, 5, 3, "delta_beta", "gaussian"),
+    (64, 3, 90, 3, 2, "real_imag", "gaussian"),
+    (96, 7, 130, 3, 2, "delta_beta", "poisson"),
+    (128, 18, 150, 3, 2, "delta_beta", "gaussian"),
+    (128, 5, 150, 2, 4, "delta_beta", "poisson"),
+    (192, 3, 220, 2, 2, "delta_beta", "gaussian"),
+])
+def test_modes_loss_grad_matches_oracle(ctx, n, s, lat, npos, m, repr_, loss):
+    sc = synth.small_case(seed=700 + n + s, n=n, n_slices=s, lateral=lat, n_pos=npos, obj_repr=repr_, loss=loss,
+                          strength=30.0)
+    case = ModesCase(sc, m, seed=17 + m, poisson_seed=9 if loss == "poisson" else None)
+    check(case.run(ctx), case)
+
+
+def test_one_mode_equals_the_single_probe_call(ctx):
+    import torch
+    from paper_2012_12686_amd import Geometry
+    sc = synth.small_case(seed=731, n=128, n_slices=9, lateral=150, n_pos=3, strength=30.0, loss="poisson")
+    case = Case(sc, poisson_seed=3)
+    inp, i_meas = case.torch_inputs()
+    g = Geometry.from_scan(sc)
+    one = ctx.loss_grad(g, **inp, i_meas=i_meas, intensity=True)
+    probe = inp.pop("probe")
+    many = ctx.loss_grad_modes(g, probes=probe[None].contiguous(), i_meas=i_meas, intensity=True, **inp)
+    torch.cuda.synchronize()
+    for k in ("loss", "g_a", "g_b", "g_shift", "intensity"):
+        a, b = one[k].cpu().numpy(), many[k].cpu().numpy()
+        print(k, "bitwise" if np.array_equal(a, b) else f"rel-L2 {rel_l2(a, b):.2e}")
+        # same kernels, same split, same order of operations: the same bits
+        assert np.array_equal(a, b), k
+    assert np.array_equal(one["g_probe"].cpu().numpy(), many["g_probe"][0].cpu().numpy())
+
+
+def test_modes_accumulate_and_deterministic(ctx):
+    """ACCUMULATE adds every output onto what the caller passed; the
+    deterministic mode gives the same bits twice."""
+    import torch
+    from paper_2012_12686_amd import Geometry
+    sc = synth.small_case(seed=741, n=64, n_slices=5, lateral=100, n_pos=4, strength=30.0)
+    case = ModesCase(sc, 3, seed=5)
+    inp, i_meas = case.torch_inputs()
+    inp.pop("probe")
+    probes = torch.as_tensor(case.probes, dtype=torch.complex64, device="cuda").contiguous()
+    g = Geometry.from_scan(sc, deterministic=True)
+    r1 = ctx.loss_grad_modes(g, probes=probes, i_meas=i_meas, **inp)
+    r2 = ctx.loss_grad_modes(g, probes=probes, i_meas=i_meas, **inp)
+    base = {k: torch.randn_like(v) if k != "loss" else v for k, v in r1.items()}
+    acc = {k: v.clone() for k, v in base.items()}
+    acc["loss"] = torch.empty_like(r1["loss"])
+    ctx.loss_grad_modes(Geometry.from_scan(sc, deterministic=True, accumulate=True), probes=probes,
+                        i_meas=i_meas, out=acc, **inp)
+    torch.cuda.synchronize()
+    for k in ("loss", "g_a", "g_b", "g_probe", "g_shift"):
+        assert torch.equal(r1[k], r2[k]), k
+    for k in ("g_a", "g_b", "g_probe", "g_shift"):
+        want = (base[k] + r1[k]).cpu().numpy()
+        assert rel_l2(acc[k].cpu().numpy(), want) <= 1e-6, k
+    assert float(acc["loss"]) == float(r1["loss"])
