@@ -167,7 +167,7 @@ class Geometry:
     """Physical parameters of one scan."""
 
     def __init__(self, n, n_slices, wavelength_m, pixel_m, slice_dz_m, obj_repr="delta_beta",
-                 loss="gaussian", eps=1e-6):
+                 loss="gaussian", eps=1e-6, gaps=None):
         self.n = int(n)
         self.n_slices = int(n_slices)
         self.wavelength_m = float(wavelength_m)
@@ -176,6 +176,23 @@ class Geometry:
         self.obj_repr = obj_repr
         self.loss = loss
         self.eps = float(eps)
+        # Sparse multislice with unequal spacing (Sec. S1.C, the variable
+        # variant): gaps[j] is the free-space distance from slice j to slice
+        # j+1 in metres.  slice_dz_m stays the thickness in the transmission.
+        # None: every gap equals slice_dz_m.
+        self.gaps = None if gaps is None else np.asarray(gaps, dtype=np.float64).reshape(-1)
+        if self.gaps is not None and self.gaps.size != max(self.n_slices - 1, 0):
+            raise ValueError("gaps needs n_slices - 1 entries")
+
+    def gap(self, j):
+        """Distance from slice j to slice j+1 (metres)."""
+        return self.slice_dz_m if self.gaps is None else float(self.gaps[j])
+
+    def gap_kernels(self):
+        """The S - 1 Fresnel transfer functions, one per gap."""
+        if self.gaps is None:
+            return [self.h] * (self.n_slices - 1)
+        return [fresnel_kernel(self.n, self.wavelength_m, self.pixel_m, d) for d in self.gaps]
 
     @property
     def kdz(self):
@@ -205,7 +222,7 @@ def exit_waves(geom, obj_a, obj_b, probe, positions, keep_slices=False):
     tb = take_chunks(obj_b, corners, n)
     t = transmission(ta, tb, geom.obj_repr, geom.kdz)          # [B][S][N][N]
     psi = fourier_shift(probe, shifts)                          # [B][N][N]
-    h = geom.h
+    hs = geom.gap_kernels()
     if keep_slices:
         psis = np.empty((len(corners), s, n, n), dtype=np.complex128)
         phis = np.empty_like(psis)
@@ -216,7 +233,7 @@ def exit_waves(geom, obj_a, obj_b, probe, positions, keep_slices=False):
             psis[:, j] = psi
             phis[:, j] = phi
         if j < s - 1:
-            psi = fresnel_propagate(phi, h)
+            psi = fresnel_propagate(phi, hs[j])
     return (phi, psis, phis) if keep_slices else phi
 
 
@@ -291,16 +308,27 @@ def loss_grad(geom, obj_a, obj_b, probe, positions, i_meas):
     return (value,) + reverse_sweep(geom, obj_a, obj_b, probe, positions, d_di)
 
 
-def reverse_sweep(geom, obj_a, obj_b, probe, positions, d_di):
+def reverse_sweep(geom, obj_a, obj_b, probe, positions, d_di, want_gaps=False):
     """Gradient of a loss whose derivative with respect to the predicted
     intensity I = |Psi|^2 of this probe is d_di [B][N][N]: the far-field
     residual g = 2 d_di Psi is pulled back through the Fraunhofer transform,
     each slice, the Fourier shift and the chunk gather.  Returns (g_a, g_b,
-    g_probe, g_shift) as in loss_grad."""
+    g_probe, g_shift) as in loss_grad; with ``want_gaps`` also g_gaps [S-1],
+    the derivative with respect to each inter-slice distance.
+
+    A gap d_j enters only through psi_{j+1} = F^-1[H_j F phi_j] with
+    H_j = exp(i pi lambda d_j |nu|^2), so dpsi_{j+1}/dd_j =
+    F^-1[i pi lambda |nu|^2 F psi_{j+1}], and with mu = dL/dpsi_{j+1}
+    dL/dd_j = Re sum conj(F mu) (i pi lambda |nu|^2) F psi_{j+1}
+    (the real inner product of a real parameter's derivative; F unitary).
+    """
     corners, shifts = split_position(positions)
     n, s = geom.n, geom.n_slices
     kdz = geom.kdz
-    h = geom.h
+    hs = geom.gap_kernels()
+    nu = np.fft.fftfreq(n, d=geom.pixel_m)
+    dh_dd = 1j * np.pi * geom.wavelength_m * (nu[:, None] ** 2 + nu[None, :] ** 2)
+    g_gaps = np.zeros(max(s - 1, 0))
     ta = take_chunks(obj_a, corners, n)
     tb = take_chunks(obj_b, corners, n)
     t = transmission(ta, tb, geom.obj_repr, kdz)
@@ -325,7 +353,9 @@ def reverse_sweep(geom, obj_a, obj_b, probe, positions, d_di):
             g_tb[:, j] = np.imag(z)
         mu = np.conj(t[:, j]) * lam                      # dL/dpsi_j
         if j > 0:
-            lam = fresnel_propagate_adjoint(mu, h)       # dL/dphi_{j-1}
+            if want_gaps:
+                g_gaps[j - 1] = np.sum(np.real(np.conj(fft2u(mu)) * dh_dd * fft2u(psis[:, j])))
+            lam = fresnel_propagate_adjoint(mu, hs[j - 1])   # dL/dphi_{j-1}
     g_pb = mu                                            # dL/d(shifted probe)
 
     # Fourier shift: p_b = F^-1[ P e_b ],  P = F[p],  e_b = exp(-2 pi i s_b.f)
@@ -340,7 +370,21 @@ def reverse_sweep(geom, obj_a, obj_b, probe, positions, d_di):
 
     g_a = scatter_chunks(g_ta, corners, obj_a.shape)
     g_b = scatter_chunks(g_tb, corners, obj_b.shape)
+    if want_gaps:
+        return g_a, g_b, g_probe, g_shift, g_gaps
     return g_a, g_b, g_probe, g_shift
+
+
+def loss_grad_gaps(geom, obj_a, obj_b, probe, positions, i_meas):
+    """loss_grad plus the gradient with respect to the inter-slice distances
+    (slice-position refinement of sparse multislice, Sec. S1.C and the list
+    of refinable parameters in Sec. S1.D).  Returns (loss, g_a, g_b, g_probe,
+    g_shift, g_gaps [S-1])."""
+    i_pred = forward(geom, obj_a, obj_b, probe, positions)
+    n_norm = i_pred.size
+    value = loss_value(geom.loss, i_pred, i_meas, geom.eps, n_norm)
+    d_di = loss_dI(geom.loss, i_pred, i_meas, geom.eps, n_norm)
+    return (value,) + reverse_sweep(geom, obj_a, obj_b, probe, positions, d_di, want_gaps=True)
 
 
 # ---------------------------------------------------------------------------
