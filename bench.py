@@ -96,7 +96,7 @@ def main():
                     help="workgroups per position (0 = the library's automatic choice)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters)")
-    ap.add_argument("--workload", default="multislice", choices=["multislice", "batching", "serving"],
+    ap.add_argument("--workload", default="multislice", choices=["multislice", "batching", "serving", "sparse"],
                     help="multislice: the 64-slice minibatch (default line); batching: 32 mixed scans, "
                          "batched vs per-job; serving: the request loop")
     ap.add_argument("--ckpt", type=int, default=16, help="slice checkpoint interval of the adjoint")
@@ -126,6 +126,8 @@ def main():
     if args.workload == "serving":
         from paper_2012_12686_amd.serve import bench_serving
         return bench_serving(args)
+    if args.workload == "sparse":
+        return bench_sparse(args)
 
     import synth
     from paper_2012_12686_amd import Context, Geometry, split_positions
@@ -241,6 +243,95 @@ def main():
     }
     if not args.no_cpu_baseline and n_modes == 1:
         line["cpu_baseline"] = cpu_baseline(sc, slice(0, mb), i_meas_np[:mb].astype(np.float64))
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def bench_sparse(args):
+    """Sparse multislice (two layers 10 um apart, N = 128, 12 keV): loss and
+    gradients including the gap gradient, one minibatch of 202 positions per
+    step (adorym_loss_grad_gaps)."""
+    import torch
+
+    import synth
+    from paper_2012_12686_amd import Context, Geometry, split_positions
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    sc = synth.sparse_multislice()
+    n, s, mb = sc.n, sc.n_slices, sc.minibatch
+    n_mb = len(sc.positions) // mb
+    ctx = Context(dev)
+    geom = Geometry.from_scan(sc, ckpt_every=args.ckpt)
+    to_t = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device=dev)
+    true_a, true_b = to_t(sc.obj_a, torch.float32), to_t(sc.obj_b, torch.float32)
+    probe = to_t(sc.probe, torch.complex64)
+    corner, shift = split_positions(to_t(sc.positions, torch.float64))
+    gaps_true, gaps = to_t(sc.gaps, torch.float64), to_t(sc.eval_gaps, torch.float64)
+    i_true = torch.cat([ctx.forward_gaps(geom, true_a, true_b, probe, corner[k * mb:(k + 1) * mb],
+                                         shift[k * mb:(k + 1) * mb], gaps_true) for k in range(n_mb)])
+    i_meas_np = np.random.default_rng(2).poisson(i_true.cpu().numpy().astype(np.float64)).astype(np.float32)
+    i_meas = to_t(i_meas_np, torch.float32)
+    a, b = torch.zeros_like(true_a), torch.zeros_like(true_b)
+    ws = torch.empty(ctx.gaps_workspace_size(geom, mb), dtype=torch.uint8, device=dev)
+    out = {"loss": torch.empty((), dtype=torch.float64, device=dev), "g_a": torch.empty_like(a),
+           "g_b": torch.empty_like(b), "g_probe": torch.empty_like(probe),
+           "g_shift": torch.empty((mb, 2), dtype=torch.float32, device=dev),
+           "g_gaps": torch.empty((s - 1,), dtype=torch.float64, device=dev)}
+
+    def step(k):
+        sl = slice((k % n_mb) * mb, (k % n_mb + 1) * mb)
+        ctx.loss_grad_gaps(geom, a, b, probe, corner[sl], shift[sl], gaps, i_meas[sl], out=out, workspace=ws)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    ctx.sync_error()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ctx.profile_start(args.steps + 8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record()
+        step(k)
+        ends[k].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms, kern_n = ctx.profile_stop()
+    ctx.sync_error()
+    elapsed = t1 - t0
+    lat = sorted(st.elapsed_time(en) for st, en in zip(starts, ends))
+    kern_avg_s = kern_ms / max(kern_n, 1) / 1e3
+    bytes_launch = algorithmic_bytes_per_position(n, s, args.ckpt) * mb
+    achieved_gbs = bytes_launch / kern_avg_s / 1e9
+    line = {
+        "metric": "sparse multislice fwd+adjoint (with gap gradient) positions/s, % HBM roofline",
+        "value": mb * args.steps / elapsed, "unit": "positions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "sparse multislice N=128, 2 layers 10 um apart, object 512x512x2 (7.3 nm, "
+                               "12 keV), minibatch 202 of 1414 positions, Poisson 1e5 photons, "
+                               "fwd+loss+adjoint+gap gradient", "global_batch": mb, "seq_len": s,
+                   "parallelism": "none"},
+        "p50_iter_ms": float(np.percentile(lat, 50)), "p99_iter_ms": float(np.percentile(lat, 99)),
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "multislice_kernel<N=128, delta/beta, Poisson, loss+adjoint, unequal gaps>",
+                     "kernel_avg_ms": kern_avg_s * 1e3, "kernel_launches": kern_n,
+                     "algorithmic_bytes_per_launch": bytes_launch},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import multislice as om
+        sample = 16
+        og = om.Geometry(n, s, sc.wavelength_m, sc.pixel_m, sc.slice_dz_m, sc.obj_repr, sc.loss, sc.eps,
+                         gaps=sc.eval_gaps)
+        z = np.zeros(sc.obj_a.shape)
+        t = time.perf_counter()
+        om.loss_grad_gaps(og, z, z, sc.probe, sc.positions[:sample], i_meas_np[:sample].astype(np.float64))
+        dt = time.perf_counter() - t
+        line["cpu_baseline"] = {"value": sample / dt, "unit": "positions/s", "cores": om._WORKERS, "kind": "oracle",
+                                "sample": f"FP64 oracle loss_grad_gaps on {sample} positions of the first minibatch"}
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -143,6 +143,35 @@ adorym_status adorym_loss_grad(adorym_ctx* ctx, const adorym_geom* g,
                                double* loss, float* g_a, float* g_b, float* g_probe,
                                float* g_shift, float* intensity);
 
+/* ---- Unequal slice spacing: sparse multislice (Sec. S1.C, the variable-
+ * spacing variant; slice positions are refinable parameters, Sec. S1.D) ---
+ * gaps: DEVICE float64 [S-1], gaps[j] = free-space distance (metres) from
+ * slice j to slice j+1, replacing slice_dz_m in the Fresnel kernel of that
+ * gap (H_j = exp(i pi lambda gaps[j] |nu|^2)); slice_dz_m keeps its role as
+ * the slice thickness in the transmission exp(i k dz delta - k dz beta).
+ * Any real value is accepted (zero: adjacent slices act as one thin
+ * object; negative: back-propagation).  May be NULL when S == 1.
+ * adorym_forward_gaps: as adorym_forward, workspace of
+ * adorym_forward_workspace_size bytes.
+ * adorym_loss_grad_gaps: as adorym_loss_grad, workspace of
+ * adorym_gaps_workspace_size bytes, and, if g_gaps (DEVICE float64 [S-1])
+ * is not NULL, dL/d(gaps[j]) in 1/m (overwritten, or added with
+ * ADORYM_ACCUMULATE_GRADS).  The gap gradient of each position is reduced
+ * in FP64 in a fixed order.  Both run with one fixed split per probe size
+ * (1 for N <= 96, 4 for N = 128, 6 for N = 192), whatever adorym_set_split
+ * chose. */
+size_t adorym_gaps_workspace_size(const adorym_geom* g, int32_t batch);
+adorym_status adorym_forward_gaps(adorym_ctx* ctx, const adorym_geom* g,
+                                  const float* obj_a, const float* obj_b, const float* probe,
+                                  const int32_t* corner, const float* shift, int32_t batch,
+                                  const double* gaps, float* intensity, void* workspace, size_t ws_bytes);
+adorym_status adorym_loss_grad_gaps(adorym_ctx* ctx, const adorym_geom* g,
+                                    const float* obj_a, const float* obj_b, const float* probe,
+                                    const int32_t* corner, const float* shift, int32_t batch,
+                                    const double* gaps, const float* i_meas, void* workspace, size_t ws_bytes,
+                                    double* loss, float* g_a, float* g_b, float* g_probe,
+                                    float* g_shift, double* g_gaps, float* intensity);
+
 /* ---- Several mutually incoherent probe modes (Eq. multimode) ----------
  * The detector records the sum over modes m of |Psi_m|^2, each mode
  * propagated through the same object at the same positions; the loss is the

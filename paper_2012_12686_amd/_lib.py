@@ -61,6 +61,11 @@ SIGNATURES = {
     "adorym_forward": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t]),
     "adorym_loss_grad": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t,
                                         _P, _P, _P, _P, _P, _P]),
+    "adorym_gaps_workspace_size": (ctypes.c_size_t, [_GP, ctypes.c_int32]),
+    "adorym_forward_gaps": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P,
+                                           ctypes.c_size_t]),
+    "adorym_loss_grad_gaps": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P,
+                                             ctypes.c_size_t, _P, _P, _P, _P, _P, _P, _P]),
     "adorym_modes_workspace_size": (ctypes.c_size_t, [_GP, ctypes.c_int32, ctypes.c_int32]),
     "adorym_loss_grad_modes": (ctypes.c_int, [_P, _GP, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P,
                                               ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),

@@ -174,6 +174,67 @@ class Context:
         check(st, self._ctx)
         return out
 
+    # ------------------------------------------- unequal slice spacing
+    def _check_gaps(self, geom, gaps):
+        if geom.n_slices == 1 and gaps is None:
+            return None
+        if (gaps is None or gaps.dtype != torch.float64 or tuple(gaps.shape) != (geom.n_slices - 1,)
+                or not gaps.is_contiguous() or gaps.device != self.device):
+            raise ValueError(f"gaps: expected contiguous float64 [{geom.n_slices - 1}] on {self.device}")
+        return gaps
+
+    def forward_gaps(self, geom, obj_a, obj_b, probe, corner, shift, gaps, out=None, workspace=None):
+        """Predicted intensities with unequal slice spacing: ``gaps`` float64
+        [S-1] (metres, device) are the distances from slice j to j+1."""
+        self._bind_stream()
+        b = self._check_inputs(geom, obj_a, obj_b, probe, corner, shift)
+        gaps = self._check_gaps(geom, gaps)
+        out = out if out is not None else torch.empty((b, geom.n, geom.n), dtype=torch.float32, device=self.device)
+        ws = workspace if workspace is not None else self.workspace(geom, b, forward=True)
+        st = load().adorym_forward_gaps(self._ctx, ctypes.byref(geom.to_c()), _ptr(obj_a), _ptr(obj_b),
+                                        _ptr(torch.view_as_real(probe)), _ptr(corner), _ptr(shift), b, _ptr(gaps),
+                                        _ptr(out), _ptr(ws), ws.numel())
+        check(st, self._ctx)
+        return out
+
+    def gaps_workspace_size(self, geom: Geometry, batch: int) -> int:
+        return int(load().adorym_gaps_workspace_size(ctypes.byref(geom.to_c()), batch))
+
+    def loss_grad_gaps(self, geom, obj_a, obj_b, probe, corner, shift, gaps, i_meas, grads=True, intensity=False,
+                       out=None, workspace=None):
+        """As :meth:`loss_grad` with unequal slice spacing ``gaps``; with
+        ``grads`` the outputs also hold ``g_gaps`` (float64 [S-1], dL/d gap in 1/m)."""
+        self._bind_stream()
+        b = self._check_inputs(geom, obj_a, obj_b, probe, corner, shift)
+        gaps = self._check_gaps(geom, gaps)
+        if tuple(i_meas.shape) != (b, geom.n, geom.n) or i_meas.dtype != torch.float32 or not i_meas.is_contiguous():
+            raise ValueError("i_meas: expected contiguous float32 [B][N][N]")
+        out = dict(out or {})
+        dev = self.device
+        if "loss" not in out:
+            out["loss"] = torch.empty((), dtype=torch.float64, device=dev)
+        if grads:
+            for name, shape, dt in (("g_a", obj_a.shape, torch.float32), ("g_b", obj_b.shape, torch.float32),
+                                    ("g_probe", probe.shape, torch.complex64), ("g_shift", (b, 2), torch.float32),
+                                    ("g_gaps", (max(geom.n_slices - 1, 0),), torch.float64)):
+                if name not in out:
+                    out[name] = (torch.zeros if geom.accumulate else torch.empty)(shape, dtype=dt, device=dev)
+        if intensity and "intensity" not in out:
+            out["intensity"] = torch.empty((b, geom.n, geom.n), dtype=torch.float32, device=dev)
+        ws = workspace if workspace is not None else torch.empty(self.gaps_workspace_size(geom, b),
+                                                                 dtype=torch.uint8, device=dev)
+        gp = out.get("g_probe")
+        gg = out.get("g_gaps")
+        st = load().adorym_loss_grad_gaps(
+            self._ctx, ctypes.byref(geom.to_c()), _ptr(obj_a), _ptr(obj_b), _ptr(torch.view_as_real(probe)),
+            _ptr(corner), _ptr(shift), b, _ptr(gaps), _ptr(i_meas), _ptr(ws), ws.numel(), _ptr(out["loss"]),
+            _ptr(out.get("g_a")), _ptr(out.get("g_b")), _ptr(torch.view_as_real(gp) if gp is not None else None),
+            _ptr(out.get("g_shift")), _ptr(gg if gg is not None and gg.numel() else None),
+            _ptr(out.get("intensity")))
+        check(st, self._ctx)
+        return out
+
+    # ------------------------------------------------- probe modes
     def modes_workspace_size(self, geom: Geometry, batch: int, n_modes: int) -> int:
         return int(load().adorym_modes_workspace_size(ctypes.byref(geom.to_c()), batch, n_modes))
 

@@ -35,6 +35,10 @@ extern template ADORYM_RUN_SIGNATURE(96, 8, 3);
 extern template ADORYM_BATCHED_SIGNATURE(96, 8, 3);
 extern template ADORYM_RUN_SIGNATURE(192, 8, 8);
 extern template ADORYM_BATCHED_SIGNATURE(192, 8, 8);
+extern template ADORYM_RUN_GAPS_SIGNATURE(64, 4, 1);
+extern template ADORYM_RUN_GAPS_SIGNATURE(96, 8, 1);
+extern template ADORYM_RUN_GAPS_SIGNATURE(128, 8, 4);
+extern template ADORYM_RUN_GAPS_SIGNATURE(192, 8, 6);
 extern template ADORYM_PARAMS_SIGNATURE(64, 4);
 extern template ADORYM_PROLOGUE_SIGNATURE(64, 4);
 extern template ADORYM_EPILOGUE_SIGNATURE(64, 4);
@@ -112,6 +116,27 @@ adorym_status dispatch(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
   }
 #undef ADORYM_RUN
   return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size / split");
+}
+
+// Unequal slice spacing: one fixed split per probe size (that of the
+// deterministic mode).
+adorym_status dispatch_gaps(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b,
+                            const float* probe, const int32_t* corner, const float* shift, int batch,
+                            const double* gaps, const float* i_meas, void* ws, double* loss, float* g_a, float* g_b,
+                            float* g_probe, float* g_shift, double* g_gaps, float* intensity, bool with_loss) {
+#define ADORYM_RUN_GAPS(N_, L_, K_)                                                                              \
+  return run_gaps<N_, L_, K_>(ctx, g, a, b, probe, corner, shift, batch, gaps, i_meas, ws, loss, g_a, g_b, g_probe, \
+                              g_shift, g_gaps, intensity, with_loss)
+  static_assert(det_split(64) == 1 && det_split(96) == 1 && det_split(128) == 4 && det_split(192) == 6,
+                "unequal-spacing kernels are instantiated for the deterministic splits");
+  switch (g->n) {
+    case 64: ADORYM_RUN_GAPS(64, 4, 1);
+    case 96: ADORYM_RUN_GAPS(96, 8, 1);
+    case 128: ADORYM_RUN_GAPS(128, 8, 4);
+    case 192: ADORYM_RUN_GAPS(192, 8, 6);
+  }
+#undef ADORYM_RUN_GAPS
+  return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size");
 }
 
 
@@ -275,6 +300,41 @@ adorym_status adorym_loss_grad(adorym_ctx* ctx, const adorym_geom* g, const floa
   if (ws_bytes < adorym_workspace_size(g, batch)) return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
   return dispatch(ctx, g, obj_a, obj_b, probe, corner, shift, batch, i_meas, workspace, loss, g_a, g_b, g_probe,
                   g_shift, intensity, true);
+}
+
+// ---- Unequal slice spacing (sparse multislice) -----------------------------
+size_t adorym_gaps_workspace_size(const adorym_geom* g, int32_t batch) {
+  if (!g || batch < 1 || g->n < 1 || g->n_slices < 1 || g->ckpt_every < 1) return 0;
+  return gaps_ws_size(g, batch, false);
+}
+
+adorym_status adorym_forward_gaps(adorym_ctx* ctx, const adorym_geom* g, const float* obj_a, const float* obj_b,
+                                  const float* probe, const int32_t* corner, const float* shift, int32_t batch,
+                                  const double* gaps, float* intensity, void* workspace, size_t ws_bytes) {
+  adorym_status st = check_geom(ctx, g, batch);
+  if (st != ADORYM_OK) return st;
+  if (!obj_a || !obj_b || !probe || !corner || !shift || !intensity || !workspace)
+    return set_err(ctx, ADORYM_EINVAL, "NULL array argument");
+  if (g->n_slices > 1 && !gaps) return set_err(ctx, ADORYM_EINVAL, "gaps is NULL");
+  if (ws_bytes < adorym_forward_workspace_size(g, batch)) return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
+  return dispatch_gaps(ctx, g, obj_a, obj_b, probe, corner, shift, batch, gaps, nullptr, workspace, nullptr, nullptr,
+                       nullptr, nullptr, nullptr, nullptr, intensity, false);
+}
+
+adorym_status adorym_loss_grad_gaps(adorym_ctx* ctx, const adorym_geom* g, const float* obj_a, const float* obj_b,
+                                    const float* probe, const int32_t* corner, const float* shift, int32_t batch,
+                                    const double* gaps, const float* i_meas, void* workspace, size_t ws_bytes,
+                                    double* loss, float* g_a, float* g_b, float* g_probe, float* g_shift,
+                                    double* g_gaps, float* intensity) {
+  adorym_status st = check_geom(ctx, g, batch);
+  if (st != ADORYM_OK) return st;
+  if (!obj_a || !obj_b || !probe || !corner || !shift || !i_meas || !workspace || !loss)
+    return set_err(ctx, ADORYM_EINVAL, "NULL array argument");
+  if (g->n_slices > 1 && !gaps) return set_err(ctx, ADORYM_EINVAL, "gaps is NULL");
+  if ((g_a == nullptr) != (g_b == nullptr)) return set_err(ctx, ADORYM_EINVAL, "g_a and g_b must both be given");
+  if (ws_bytes < adorym_gaps_workspace_size(g, batch)) return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
+  return dispatch_gaps(ctx, g, obj_a, obj_b, probe, corner, shift, batch, gaps, i_meas, workspace, loss, g_a, g_b,
+                       g_probe, g_shift, g_gaps, intensity, true);
 }
 
 // ---- Several incoherent probe modes --------------------------------------

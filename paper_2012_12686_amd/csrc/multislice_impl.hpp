@@ -63,6 +63,9 @@ struct MsParams {
   int* counters;           // [B] group barrier counters (K > 1)
   int* xcc;                // [B][K] XCD ids of each group's members (K > 1)
   int* err;
+  const double* gaps;      // [S-1] distance from slice j to j+1 (m): unequal spacing, or null
+  double* gd_part;         // [B][K][S-1] gap-gradient partials (unequal spacing)
+  double chirp_per_m;      // lambda / dx^2: the Fresnel phase / pi of gap d is chirp_per_m d f^2
   int B, S, Ly, Lx, ckpt_every, nslots;
   int loss;                // ADORYM_LOSS_*
   int ksplit;              // workgroups per position of the launch that fills the partials
@@ -177,6 +180,47 @@ template <class C, bool CONJ>
 __device__ __forceinline__ void prop(float2 (&v)[C::R], MsShared<C>& sh, const Lane<C>& ln) {
   if constexpr (C::K == 1) __syncthreads();
   propagate_line<C, CONJ>(v, sh.tb, ln, sh.buf + (ln.w * C::RPW + ln.g) * C::PITCH);
+}
+
+// Unequal slice spacing: the 1D Fresnel table of gap j, rebuilt in LDS
+// before the propagations across that gap (in FP64, as the uniform table).
+template <class C>
+__device__ __forceinline__ void gap_table(MsShared<C>& sh, const MsParams& P, const Lane<C>& ln, int j) {
+  __syncthreads();                           // every wave is done with the last table
+  build_fresnel<C>(sh.tb, ln.tid, P.chirp_per_m * P.gaps[j]);
+  __syncthreads();
+}
+
+// One axis of the gap gradient.  A gap d enters as psi' = F^-1[H F phi] with
+// H = exp(i pi lambda d |nu|^2), and |nu|^2 splits into the two axes, so
+// dL/dd = -(pi lambda / dx^2) Im sum conj(F lam') |f|^2 F psi' adds one
+// term per axis; along an axis only the 1D transforms along it are needed
+// (Parseval across the other axis), and the propagation along one axis
+// leaves the term of the other axis unchanged.  Returns this thread's
+// share of sum_k k^2 Im(conj(Lam_k) Psi_k) over its lines (unnormalised
+// DFTs; the host applies -(pi lambda / dx^2) / N^3).
+template <class C>
+__device__ __forceinline__ float gap_term(const float2 (&psi)[C::R], const float2 (&lam)[C::R], const Tables<C>& tb,
+                                          const Lane<C>& ln) {
+  float2 x[C::R], y[C::R];
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) { x[m] = psi[m]; y[m] = lam[m]; }
+  fft_line<C, -1>(x, tb, ln);
+  fft_line<C, -1>(y, tb, ln);
+  float acc = 0.f;
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    const int k = ln.pos_spec(m);
+    const int kk = k < (C::N + 1) / 2 ? k : k - C::N;
+    acc = fmaf(float(kk * kk), cmulc(x[m], y[m]).y, acc);   // k^2 Im(Psi conj(Lam))
+  }
+  return acc;
+}
+
+template <class C>
+__device__ __forceinline__ void gap_store(const MsParams& P, MsShared<C>& sh, const Work<C>& wk, int gap, float acc) {
+  const double t = block_sum<C::THREADS>((double)acc, sh.red);
+  if (threadIdx.x == 0) P.gd_part[((size_t)wk.b * C::K + wk.part) * (P.S - 1) + gap] = t;
 }
 
 // Split-phase transposes of one (NF = 1) or two fields: xfer_begin ...
@@ -312,7 +356,7 @@ __device__ __forceinline__ void place_probe(float2 (&v)[C::R], const MsParams& P
 
 // One forward slice step of tiles that do not prefetch: (store) load the
 // slice's object values, modulate, and propagate to slice j + 1.
-template <class C, int REPR, bool ROW, bool CKPT>
+template <class C, int REPR, bool ROW, bool CKPT, bool VAR = false>
 __device__ __forceinline__ void forward_slice(float2 (&v)[C::R], float (&ca)[C::R], float (&cb)[C::R],
                                               const MsParams& P, MsShared<C>& sh, Work<C>& wk,
                                               const ChunkOffsets& o, int j) {
@@ -320,6 +364,7 @@ __device__ __forceinline__ void forward_slice(float2 (&v)[C::R], float (&ca)[C::
   load_chunk<C, ROW>(ca, cb, P, o, j);
   modulate<C, REPR>(v, ca, cb, P.kdz);
   if (j < P.S - 1) {
+    if constexpr (VAR) gap_table<C>(sh, P, wk.ln, j);
     prop<C, false>(v, sh, wk.ln);
     xfer<C>(v, sh, wk, false, false);
     prop<C, false>(v, sh, wk.ln);
@@ -334,7 +379,7 @@ __device__ __forceinline__ void forward_slice(float2 (&v)[C::R], float (&ca)[C::
 //   out: psi = phi_{j-1} = P^H psi_j, lam = dL/dphi_{j-1} = P^H conj(t_j) lam
 // The slice gradient goes to this position's staging planes.  (Tiles that
 // do not prefetch; backward_slice_pf below is the prefetching form.)
-template <class C, int REPR, bool ROW>
+template <class C, int REPR, bool ROW, bool VAR = false>
 __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam)[C::R], float (&ca)[C::R],
                                                float (&cb)[C::R], const MsParams& P, MsShared<C>& sh, Work<C>& wk,
                                                const ChunkOffsets& o, int j) {
@@ -371,13 +416,21 @@ __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam
     psi[m] = in_wave;
   }
   if (j > 0) {
-    const bool need_psi = !is_ckpt(j - 1, P.S, P.ckpt_every);
+    // unequal spacing: the gap gradient needs psi across the gap every time
+    const bool need_psi = VAR || !is_ckpt(j - 1, P.S, P.ckpt_every);
     if (need_psi) {
+      float gacc = 0.f;
+      if constexpr (VAR) {
+        gap_table<C>(sh, P, ln, j - 1);
+        gacc = gap_term<C>(psi, lam, sh.tb, ln);
+      }
       prop<C, true>(psi, sh, ln);
       prop<C, true>(lam, sh, ln);
       xfer2<C>(psi, lam, sh, wk, false, false);
+      if constexpr (VAR) gacc += gap_term<C>(psi, lam, sh.tb, ln);
       prop<C, true>(psi, sh, ln);
       prop<C, true>(lam, sh, ln);
+      if constexpr (VAR) gap_store<C>(P, sh, wk, j - 1, gacc);
     } else {
       prop<C, true>(lam, sh, ln);
       xfer<C>(lam, sh, wk, false, false);
@@ -391,7 +444,7 @@ __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam
 // computed while the transpose's exchange is in flight (between the two
 // halves of the split barrier).  t/g2 carry the transmission of the current
 // slice from step to step.
-template <class C, int REPR, bool ROW, bool CKPT>
+template <class C, int REPR, bool ROW, bool CKPT, bool VAR = false>
 __device__ __forceinline__ void forward_slice_pf(float2 (&v)[C::R], float2 (&t)[C::R], float (&g2)[C::R],
                                                  const MsParams& P, MsShared<C>& sh, Work<C>& wk,
                                                  const ChunkOffsets& o, int j) {
@@ -399,6 +452,7 @@ __device__ __forceinline__ void forward_slice_pf(float2 (&v)[C::R], float2 (&t)[
 #pragma unroll
   for (int m = 0; m < C::R; ++m) v[m] = cmul(v[m], t[m]);
   if (j < P.S - 1) {
+    if constexpr (VAR) gap_table<C>(sh, P, wk.ln, j);
     float ca[C::R], cb[C::R];
     load_chunk<C, !ROW>(ca, cb, P, o, j + 1);   // in flight during the propagation
     prop<C, false>(v, sh, wk.ln);
@@ -409,7 +463,7 @@ __device__ __forceinline__ void forward_slice_pf(float2 (&v)[C::R], float2 (&t)[
   }
 }
 
-template <class C, int REPR, bool ROW>
+template <class C, int REPR, bool ROW, bool VAR = false>
 __device__ __forceinline__ void backward_slice_pf(float2 (&psi)[C::R], float2 (&lam)[C::R], float2 (&t)[C::R],
                                                   float (&g2)[C::R], const MsParams& P, MsShared<C>& sh,
                                                   Work<C>& wk, const ChunkOffsets& o, int j) {
@@ -444,17 +498,25 @@ __device__ __forceinline__ void backward_slice_pf(float2 (&psi)[C::R], float2 (&
     psi[m] = in_wave;
   }
   if (j > 0) {
+    float gacc = 0.f;
+    if constexpr (VAR) {
+      gap_table<C>(sh, P, ln, j - 1);
+      gacc = gap_term<C>(psi, lam, sh.tb, ln);
+    }
     float ca[C::R], cb[C::R];
     load_chunk<C, !ROW>(ca, cb, P, o, j - 1);   // in flight during the propagation
-    const bool need_psi = !is_ckpt(j - 1, P.S, P.ckpt_every);
+    // unequal spacing: the gap gradient needs psi across the gap every time
+    const bool need_psi = VAR || !is_ckpt(j - 1, P.S, P.ckpt_every);
     if (need_psi) {
       prop<C, true>(psi, sh, ln);
       prop<C, true>(lam, sh, ln);
       xfer_begin<C, 2>(psi, lam, sh, wk, false, false);
       make_trans<C, REPR, true>(t, g2, ca, cb, kdz);
       xfer_end<C, 2>(psi, lam, wk, false);
+      if constexpr (VAR) gacc += gap_term<C>(psi, lam, sh.tb, ln);
       prop<C, true>(psi, sh, ln);
       prop<C, true>(lam, sh, ln);
+      if constexpr (VAR) gap_store<C>(P, sh, wk, j - 1, gacc);
     } else {
       prop<C, true>(lam, sh, ln);
       xfer_begin<C, 1>(lam, lam, sh, wk, false, false);
@@ -478,7 +540,7 @@ __device__ __forceinline__ void group_of_block(int& b, int& part) {
 
 // Everything one workgroup does for its part of one position.  wk.b, wk.part
 // and the exchange state wk.x are set by the caller.
-template <class C, int REPR, bool LOSS>
+template <class C, int REPR, bool LOSS, bool VAR = false>
 __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>& sh, Work<C>& wk) {
   const int b = wk.b, part = wk.part;
   const Lane<C>& ln = wk.ln;
@@ -500,6 +562,9 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
       if (P.gacc)
         for (int i = part * C::THREADS + threadIdx.x; i < NN; i += C::K * C::THREADS)
           P.gacc[(size_t)b * NN + i] = make_float2(0.f, 0.f);
+      if (VAR)
+        for (int i = threadIdx.x; i < P.S - 1; i += C::THREADS)
+          P.gd_part[((size_t)b * C::K + part) * (P.S - 1) + i] = 0.0;
     }
     if (P.intensity)
       for (int i = part * C::THREADS + threadIdx.x; i < NN; i += C::K * C::THREADS)
@@ -527,11 +592,11 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
   // MultislicePropagate: even slices in ROW layout, odd slices in COL layout.
   for (int j = 0; j < P.S; j += 2) {
     if constexpr (C::PREFETCH) {
-      forward_slice_pf<C, REPR, true, LOSS>(v, tr, g2, P, sh, wk, o, j);
-      if (j + 1 < P.S) forward_slice_pf<C, REPR, false, LOSS>(v, tr, g2, P, sh, wk, o, j + 1);
+      forward_slice_pf<C, REPR, true, LOSS, VAR>(v, tr, g2, P, sh, wk, o, j);
+      if (j + 1 < P.S) forward_slice_pf<C, REPR, false, LOSS, VAR>(v, tr, g2, P, sh, wk, o, j + 1);
     } else {
-      forward_slice<C, REPR, true, LOSS>(v, ca, cb, P, sh, wk, o, j);
-      if (j + 1 < P.S) forward_slice<C, REPR, false, LOSS>(v, ca, cb, P, sh, wk, o, j + 1);
+      forward_slice<C, REPR, true, LOSS, VAR>(v, ca, cb, P, sh, wk, o, j);
+      if (j + 1 < P.S) forward_slice<C, REPR, false, LOSS, VAR>(v, ca, cb, P, sh, wk, o, j + 1);
     }
   }
   const bool last_row = ((P.S - 1) & 1) == 0;
@@ -598,25 +663,25 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
   // transmission in tr)
   if constexpr (C::PREFETCH) {
     if (!last_row) {
-      backward_slice_pf<C, REPR, false>(psi, v, tr, g2, P, sh, wk, o, j);
+      backward_slice_pf<C, REPR, false, VAR>(psi, v, tr, g2, P, sh, wk, o, j);
       --j;
     }
     for (; j >= 1; j -= 2) {
-      backward_slice_pf<C, REPR, true>(psi, v, tr, g2, P, sh, wk, o, j);
-      backward_slice_pf<C, REPR, false>(psi, v, tr, g2, P, sh, wk, o, j - 1);
+      backward_slice_pf<C, REPR, true, VAR>(psi, v, tr, g2, P, sh, wk, o, j);
+      backward_slice_pf<C, REPR, false, VAR>(psi, v, tr, g2, P, sh, wk, o, j - 1);
     }
-    if (j == 0) backward_slice_pf<C, REPR, true>(psi, v, tr, g2, P, sh, wk, o, 0);
+    if (j == 0) backward_slice_pf<C, REPR, true, VAR>(psi, v, tr, g2, P, sh, wk, o, 0);
   } else {
     if (!last_row) {
-      backward_slice<C, REPR, false>(psi, v, ca, cb, P, sh, wk, o, j);
+      backward_slice<C, REPR, false, VAR>(psi, v, ca, cb, P, sh, wk, o, j);
       --j;
     }
     // now slice j is even (ROW); pairs (j ROW, j-1 COL) down to slice 0
     for (; j >= 1; j -= 2) {
-      backward_slice<C, REPR, true>(psi, v, ca, cb, P, sh, wk, o, j);
-      backward_slice<C, REPR, false>(psi, v, ca, cb, P, sh, wk, o, j - 1);
+      backward_slice<C, REPR, true, VAR>(psi, v, ca, cb, P, sh, wk, o, j);
+      backward_slice<C, REPR, false, VAR>(psi, v, ca, cb, P, sh, wk, o, j - 1);
     }
-    if (j == 0) backward_slice<C, REPR, true>(psi, v, ca, cb, P, sh, wk, o, 0);
+    if (j == 0) backward_slice<C, REPR, true, VAR>(psi, v, ca, cb, P, sh, wk, o, 0);
   }
   // v = dL/d(shifted probe) in ROW layout, natural order.
 
@@ -651,7 +716,7 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
 }
 
 // One group of K workgroups per position of a single job.
-template <class C, int REPR, bool LOSS>
+template <class C, int REPR, bool LOSS, bool VAR = false>
 __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
   __shared__ MsShared<C> sh;
   int b, part;
@@ -666,7 +731,7 @@ __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
   const int cy = P.corner[2 * b], cx = P.corner[2 * b + 1];
   const bool inside = cy >= 0 && cx >= 0 && cy + C::N <= P.Ly && cx + C::N <= P.Lx;
   if (C::K > 1 && inside) exchange_init<C::K>(wk.x, P.xcc + b * C::K, part);
-  process_position<C, REPR, LOSS>(P, sh, wk);
+  process_position<C, REPR, LOSS, VAR>(P, sh, wk);
 }
 
 // Persistent multi-job kernel: groups of K workgroups take (job, position)
@@ -979,14 +1044,14 @@ inline adorym_status check_geom(adorym_ctx* ctx, const adorym_geom* g, int batch
 }
 
 
-template <class C, bool LOSS>
+template <class C, bool LOSS, bool VAR = false>
 void launch_ms(const MsParams& P, int repr, hipStream_t st) {
   // XCD-aware grid: ceil(B/8) groups per XCD, K slots per group
   const dim3 grid(((P.B + 7) / 8) * 8 * C::K), block(C::THREADS);
   if (repr == ADORYM_OBJ_DELTA_BETA)
-    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, LOSS>), grid, block, 0, st, P);
+    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, LOSS, VAR>), grid, block, 0, st, P);
   else
-    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, LOSS>), grid, block, 0, st, P);
+    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, LOSS, VAR>), grid, block, 0, st, P);
 }
 
 // Kernel parameters of one job; `ws` is its workspace (adorym_workspace_size).
@@ -1089,6 +1154,67 @@ adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const f
   return ADORYM_OK;
 }
 
+// Gap gradients dL/dd_j = scale * sum of the (position, part) partials of
+// gap j, one workgroup per gap: a fixed strided split over the threads and a
+// fixed-order tree, in FP64 (bitwise reproducible).
+static __global__ void __launch_bounds__(256) gap_reduce_kernel(const double* __restrict__ part, int nbk, int ngaps,
+                                                                double scale, double* __restrict__ g_gaps,
+                                                                int accumulate) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nbk; i += blockDim.x) s += part[(size_t)i * ngaps + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) g_gaps[j] = accumulate ? g_gaps[j] + scale * red[0] : scale * red[0];
+}
+
+// Workspace of the unequal-spacing calls: that of the uniform call plus the
+// gap-gradient partials.
+inline size_t gaps_ws_size(const adorym_geom* g, int batch, bool forward_only) {
+  const size_t base = ws_layout(g, batch, forward_only).total;
+  if (forward_only) return base;
+  return base + align256((size_t)batch * kMaxSplit * std::max(g->n_slices - 1, 1) * sizeof(double));
+}
+
+// Unequal slice spacing (sparse multislice): as run, with the Fresnel table
+// rebuilt for every gap and, with the loss, the gap gradients.
+template <int N, int L, int K>
+adorym_status run_gaps(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b, const float* probe,
+                       const int32_t* corner, const float* shift, int batch, const double* gaps, const float* i_meas,
+                       void* ws, double* loss, float* g_a, float* g_b, float* g_probe, float* g_shift,
+                       double* g_gaps, float* intensity, bool with_loss) {
+  using C = TileCfg<N, L, K>;
+  MsParams P = make_params<N, L>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
+                                    with_loss ? g_a : nullptr, with_loss ? g_b : nullptr, intensity);
+  P.ksplit = K;
+  P.gaps = gaps;
+  P.chirp_per_m = g->wavelength_m / (g->pixel_m * g->pixel_m);
+  P.gd_part = with_loss ? reinterpret_cast<double*>(static_cast<char*>(ws) + ws_layout(g, batch).total) : nullptr;
+  hipStream_t st = ctx->stream;
+  const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
+  launch_prologue<N, L>(P, probe, g, st);
+  if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
+  if (with_loss) launch_ms<C, true, true>(P, g->obj_repr, st);
+  else launch_ms<C, false, true>(P, g->obj_repr, st);
+  if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
+  if (with_loss) {
+    launch_epilogue<N, L>(P, ws, g, loss, g_probe, g_shift, st);
+    if (g_gaps && P.S > 1) {
+      const double scale = -M_PI * P.chirp_per_m / ((double)N * N * N);
+      hipLaunchKernelGGL(gap_reduce_kernel, dim3(P.S - 1), dim3(256), 0, st, P.gd_part, P.B * K, P.S - 1, scale,
+                         g_gaps, (g->flags & ADORYM_ACCUMULATE_GRADS) ? 1 : 0);
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
+  return ADORYM_OK;
+}
+
 // The persistent multi-job kernel of one probe-size class (device tables
 // prepared by the plan).
 template <int N, int L, int K>
@@ -1119,6 +1245,11 @@ void launch_batched(const MsParams* jobs, const int2* items, int n_items, int* t
   adorym_ms::MsParams adorym_ms::make_params<N_, L_>(adorym_ctx*, const adorym_geom*, const float*, \
                                                         const float*, int, const int32_t*, const float*, \
                                                         const float*, void*, bool, float*, float*, float*)
+#define ADORYM_RUN_GAPS_SIGNATURE(N_, L_, K_) \
+  adorym_status adorym_ms::run_gaps<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, const float*, \
+                                                const float*, const int32_t*, const float*, int, const double*, \
+                                                const float*, void*, double*, float*, float*, float*, float*, \
+                                                double*, float*, bool)
 #define ADORYM_RUN_SIGNATURE(N_, L_, K_) \
   adorym_status adorym_ms::run<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, const float*, const float*, \
                                            const int32_t*, const float*, int, const float*, void*, double*, float*, \

@@ -63,6 +63,10 @@ class Scan:
     eval_probe: Optional[np.ndarray] = None
     eval_positions: Optional[np.ndarray] = None
     photons: Optional[float] = None   # Poisson counting: expected photons / pattern
+    # Unequal slice spacing: distance from slice j to j+1 (metres), [S-1];
+    # None: every gap is slice_dz_m.  eval_gaps: where gradients are taken.
+    gaps: Optional[np.ndarray] = None
+    eval_gaps: Optional[np.ndarray] = None
 
     @property
     def n_slices(self) -> int:
@@ -270,6 +274,34 @@ def tilt_job(seed: int = 5, side: int = 256, n_angles: int = 90):
                 obj_repr="delta_beta", loss="poisson", minibatch=100, photons=1e4,
                 eval_obj_a=np.zeros_like(delta), eval_obj_b=np.zeros_like(beta))
     return scan, angles
+
+
+def sparse_multislice(seed: int = 6, n_pos: int = 1414) -> Scan:
+    """Sparse multislice ptychography: two thin layers 10 um apart.
+
+    The shape of the paper's sparse-multislice experiment (Sec. 3, two
+    layers of nanoflakes on either side of a window): 12 keV, 7.3 nm pixels,
+    N = 128, object 512 x 512 x 2 (the 501 x 500 x 2 field padded to a
+    multiple of 128), 1414 positions on a jittered 38 x 38 raster (step 9.9
+    px), Poisson data at 1e5 photons per pattern, minibatch 202 (7 per
+    epoch).  Each layer holds 40 random flakes (ellipses, 5-40 px, delta
+    1e-5..5e-5, beta 0.05-0.15 delta) of thickness slice_dz_m = 100 nm.
+    Evaluated at delta = beta = 0 and at gaps 5% longer than the truth.
+    """
+    rng = np.random.default_rng(seed)
+    side = 512
+    layers = [ellipsoid_volume(rng, (1, side, side), 40, lat=(5.0, 40.0), ax=(2.0, 2.0),
+                               delta_range=(1e-5, 5e-5), beta_ratio=(0.05, 0.15)) for _ in range(2)]
+    delta = np.concatenate([d for d, _ in layers])
+    beta = np.concatenate([b for _, b in layers])
+    probe = gaussian_probe(rng, 128, 16.0, 6.0, phase_std=2.0, total=1e5)
+    pos = raster(38, 38, 8.0, 9.9, jitter=2.0, rng=rng)[:n_pos]
+    z = np.zeros_like(delta)
+    gaps = np.array([10e-6])
+    return Scan(name="sparse_multislice_n128_s2", n=128, obj_a=delta, obj_b=beta, probe=probe, positions=pos,
+                wavelength_m=wavelength_from_energy(12000.0), pixel_m=7.3e-9, slice_dz_m=100e-9,
+                obj_repr="delta_beta", loss="poisson", minibatch=202, photons=1e5,
+                eval_obj_a=z, eval_obj_b=z, gaps=gaps, eval_gaps=gaps * 1.05)
 
 
 def split_positions(pos: np.ndarray):

@@ -31,7 +31,9 @@ def _forward(geom, a, b, p, pos):
     shift = (pos - corner).astype(F32)
     f = np.fft.fftfreq(n)
     nu2 = (f[:, None] ** 2 + f[None, :] ** 2) / geom.pixel_m ** 2
-    h = _c64(np.exp(1j * np.pi * geom.wavelength_m * geom.slice_dz_m * nu2))
+    gaps = getattr(geom, "gaps", None)
+    gaps = [geom.slice_dz_m] * (s - 1) if gaps is None else list(gaps)
+    hs = [_c64(np.exp(1j * np.pi * geom.wavelength_m * d * nu2)) for d in gaps]
     kdz = F32(2 * np.pi / geom.wavelength_m * geom.slice_dz_m)
     nb = len(corner)
     ta = np.stack([a[:, cy:cy + n, cx:cx + n] for cy, cx in corner]).astype(F32)
@@ -50,9 +52,10 @@ def _forward(geom, a, b, p, pos):
         phi = psi * t[:, j]
         phis[:, j] = phi
         if j < s - 1:
-            psi = sfft.ifft2(sfft.fft2(phi, norm="ortho") * h, norm="ortho")
+            psi = sfft.ifft2(sfft.fft2(phi, norm="ortho") * hs[j], norm="ortho")
     det = np.fft.fftshift(sfft.ifft2(phi, norm="ortho"), axes=(-2, -1))
-    return dict(corner=corner, f=f, h=h, kdz=kdz, t=t, e=e, pf=pf, psis=psis, phis=phis, det=det)
+    dh = _c64(1j * np.pi * geom.wavelength_m * nu2)
+    return dict(corner=corner, f=f, hs=hs, dh=dh, kdz=kdz, t=t, e=e, pf=pf, psis=psis, phis=phis, det=det)
 
 
 def _loss(geom, ip, i_meas):
@@ -71,7 +74,7 @@ def _loss(geom, ip, i_meas):
 
 def _reverse(geom, st, a, b, dldi):
     n, s = geom.n, geom.n_slices
-    corner, f, h, kdz, t, e, pf = (st[k] for k in ("corner", "f", "h", "kdz", "t", "e", "pf"))
+    corner, f, hs, kdz, t, e, pf = (st[k] for k in ("corner", "f", "hs", "kdz", "t", "e", "pf"))
     psis, phis, det = st["psis"], st["phis"], st["det"]
     lam = sfft.fft2(np.fft.ifftshift((F32(2) * dldi * det).astype(C64), axes=(-2, -1)), norm="ortho")
     ga = np.zeros(a.shape, F32)
@@ -88,7 +91,10 @@ def _reverse(geom, st, a, b, dldi):
             gb[j, cy:cy + n, cx:cx + n] += db[k]
         mu = np.conj(t[:, j]) * lam
         if j > 0:
-            lam = sfft.ifft2(sfft.fft2(mu, norm="ortho") * np.conj(h), norm="ortho")
+            mu_f = sfft.fft2(mu, norm="ortho")
+            st.setdefault("g_gaps", np.zeros(s - 1))[j - 1] = float(
+                np.sum(np.real(np.conj(mu_f) * st["dh"] * sfft.fft2(psis[:, j], norm="ortho")).astype(np.float64)))
+            lam = sfft.ifft2(mu_f * np.conj(hs[j - 1]), norm="ortho")
     big_g = sfft.fft2(mu, norm="ortho")
     gp = sfft.ifft2(np.sum(big_g * np.conj(e), axis=0), norm="ortho")
     z = np.conj(big_g) * pf[None] * e
@@ -105,6 +111,14 @@ def loss_grad_fp32(geom, a, b, p, pos, i_meas):
     st = _forward(geom, a, b, p, pos)
     value, dldi = _loss(geom, _intensity(st["det"]), i_meas)
     return (value,) + _reverse(geom, st, a, b, dldi)
+
+
+def loss_grad_fp32_gaps(geom, a, b, p, pos, i_meas):
+    """As loss_grad_fp32 with the geometry's unequal gaps; adds g_gaps."""
+    st = _forward(geom, a, b, p, pos)
+    value, dldi = _loss(geom, _intensity(st["det"]), i_meas)
+    out = _reverse(geom, st, a, b, dldi)
+    return (value,) + out + (st.get("g_gaps", np.zeros(max(geom.n_slices - 1, 0))),)
 
 
 def loss_grad_fp32_modes(geom, a, b, probes, pos, i_meas):
