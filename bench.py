@@ -96,7 +96,7 @@ def main():
                     help="workgroups per position (0 = the library's automatic choice)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters)")
-    ap.add_argument("--workload", default="multislice", choices=["multislice", "batching", "serving", "sparse"],
+    ap.add_argument("--workload", default="multislice", choices=["multislice", "batching", "serving", "sparse", "priors"],
                     help="multislice: the 64-slice minibatch (default line); batching: 32 mixed scans, "
                          "batched vs per-job; serving: the request loop")
     ap.add_argument("--ckpt", type=int, default=16, help="slice checkpoint interval of the adjoint")
@@ -128,6 +128,8 @@ def main():
         return bench_serving(args)
     if args.workload == "sparse":
         return bench_sparse(args)
+    if args.workload == "priors":
+        return bench_priors(args)
 
     import synth
     from paper_2012_12686_amd import Context, Geometry, split_positions
@@ -332,6 +334,69 @@ def bench_sparse(args):
         dt = time.perf_counter() - t
         line["cpu_baseline"] = {"value": sample / dt, "unit": "positions/s", "cores": om._WORKERS, "kind": "oracle",
                                 "sample": f"FP64 oracle loss_grad_gaps on {sample} positions of the first minibatch"}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def bench_priors(args):
+    """Object priors (l1 + TV, value and gradient added onto a data gradient)
+    on the 512 x 512 x 128 delta/beta object of the 128-slice workload."""
+    import torch
+
+    import synth
+    from paper_2012_12686_amd import Context
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    sc = synth.config3()
+    ctx = Context(dev)
+    a = torch.as_tensor(sc.obj_a, dtype=torch.float32, device=dev).contiguous()
+    b = torch.as_tensor(sc.obj_b, dtype=torch.float32, device=dev).contiguous()
+    out = {"g_a": torch.zeros_like(a), "g_b": torch.zeros_like(b)}
+    n_vox = a.numel()
+
+    def step():
+        ctx.prior_grad("delta_beta", a, b, l1_a=0.05, l1_b=0.5, tv=0.02, out=out, accumulate=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.sync_error()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for k in range(args.steps):
+        step()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lat = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    avg_s = sum(lat) / len(lat) / 1e3
+    bytes_call = 24 * n_vox          # read delta, beta, g_a, g_b; write g_a, g_b
+    achieved = bytes_call / avg_s / 1e9
+    line = {
+        "metric": "object prior (l1 + TV) value+gradient voxels/s, % HBM roofline",
+        "value": n_vox * args.steps / elapsed, "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "l1 (delta, beta) + total variation on the 512x512x128 delta/beta object, "
+                               "gradient added onto the data gradient", "voxels": n_vox},
+        "p50_iter_ms": float(np.percentile(lat, 50)), "p99_iter_ms": float(np.percentile(lat, 99)),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "prior_grad_kernel<delta/beta> + its FP64 partial sum",
+                     "algorithmic_bytes_per_launch": bytes_call, "call_avg_ms": avg_s * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import regularizers as orr
+        sub = (16, 512, 512)
+        aa, bb = sc.obj_a[:sub[0]], sc.obj_b[:sub[0]]
+        t = time.perf_counter()
+        orr.value(aa, bb, "delta_beta", 0.05, 0.5, 0.02)
+        orr.grad(aa, bb, "delta_beta", 0.05, 0.5, 0.02)
+        dt = time.perf_counter() - t
+        line["cpu_baseline"] = {"value": aa.size / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
+                                "sample": f"FP64 NumPy oracle value + gradient on 16 of the 128 slices, {dt:.1f} s"}
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -201,6 +201,39 @@ adorym_status adorym_loss_grad_modes(adorym_ctx* ctx, const adorym_geom* g,
 adorym_status adorym_rotate(adorym_ctx* ctx, const float* in, float* out, int32_t lz, int32_t ly, int32_t lx,
                             double theta, int transpose);
 
+/* ---- Object priors (Eq. tikhonov, Table tab:regularizers) -------------
+ * Regularizers added to the data loss, on the object [S][Ly][Lx] (DEVICE
+ * float32 obj_a/obj_b as in adorym_loss_grad).  With N_o = S Ly Lx voxels
+ * and the per-voxel quantities q1, q2 = (delta, beta) for
+ * ADORYM_OBJ_DELTA_BETA or (|O| - mean|O|, arg O) for ADORYM_OBJ_REAL_IMAG:
+ *   R = (1/N_o) sum [l1_a W1 |q1| + l1_b W2 |q2|]                (l1)
+ *     + (tv/N_o) sum over neighbouring voxel pairs along z, y, x
+ *       of |q1' - q1| + |q2' - q2|                                (TV)
+ * W1, W2 = 1, or the reweighted-l1 weights w_a, w_b (DEVICE float32, same
+ * shape, both or neither).  The derivative of |t| at 0 is taken as 0;
+ * mean|O| is differentiated through.
+ * adorym_prior_grad: writes R to *value (DEVICE float64) and adds dR/da,
+ * dR/db onto g_a, g_b (accumulate != 0, the usual case after
+ * adorym_loss_grad) or overwrites them (accumulate == 0).  Coefficients
+ * must be >= 0.  Workspace of adorym_prior_workspace_size bytes.  All sums
+ * are in FP64 in a fixed order.
+ * adorym_prior_weights: W = max|q| / (|q| + eps) per voxel from a snapshot
+ * of the object (the adaptive weights of the reweighted l1, held constant
+ * between updates), eps > 0.
+ * adorym_support_project: the finite-support constraint: voxels whose mask
+ * byte (DEVICE uint8 [n]) is 0 are set to vacuum (delta = beta = 0, or
+ * O = 1 + 0i), in place. */
+size_t adorym_prior_workspace_size(int32_t s, int32_t ly, int32_t lx);
+adorym_status adorym_prior_grad(adorym_ctx* ctx, int32_t obj_repr, const float* obj_a, const float* obj_b,
+                                int32_t s, int32_t ly, int32_t lx, double l1_a, double l1_b, double tv,
+                                const float* w_a, const float* w_b, void* workspace, size_t ws_bytes,
+                                double* value, float* g_a, float* g_b, int32_t accumulate);
+adorym_status adorym_prior_weights(adorym_ctx* ctx, int32_t obj_repr, const float* snap_a, const float* snap_b,
+                                   int32_t s, int32_t ly, int32_t lx, double eps, void* workspace,
+                                   size_t ws_bytes, float* w_a, float* w_b);
+adorym_status adorym_support_project(adorym_ctx* ctx, int32_t obj_repr, const uint8_t* mask, float* obj_a,
+                                     float* obj_b, size_t n);
+
 /* One Adam step (Sec. S1.F) on n float32 values, in place on x, m, v:
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
  * x -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), t >= 1.

@@ -79,6 +79,24 @@ def fresnel_kernel(n, wavelength_m, pixel_m, dist_m):
     return np.exp(1j * np.pi * wavelength_m * dist_m * nu2)
 
 
+def sommerfeld_kernel(n, wavelength_m, pixel_m, dist_m):
+    """Sommerfeld-Rayleigh transfer function, Eq. sommerfeld_kernel:
+    H2 = exp(-i k d sqrt(1 - lambda^2 |nu|^2)) where 1 - lambda^2 |nu|^2 > 0,
+    0 elsewhere (evanescent).  Evaluated as the global phase exp(-i k d)
+    times exp(-i k d (sqrt(1 - x) - 1)), x = lambda^2 |nu|^2, with
+    sqrt(1 - x) - 1 = -x / (sqrt(1 - x) + 1): the same function, without
+    the cancellation of a ~1e10 rad phase."""
+    nu = np.fft.fftfreq(n, d=pixel_m)
+    x = wavelength_m ** 2 * (nu[:, None] ** 2 + nu[None, :] ** 2)
+    k = 2.0 * np.pi / wavelength_m
+    inside = x < 1.0
+    xs = np.where(inside, x, 0.0)
+    rel = -xs / (np.sqrt(1.0 - xs) + 1.0)
+    kd = k * dist_m
+    glob = np.exp(-1j * np.fmod(kd, 2.0 * np.pi))
+    return np.where(inside, glob * np.exp(-1j * kd * rel), 0.0)
+
+
 def fresnel_propagate(psi, h):
     """Fresnel propagation F^-1{ F[psi] H }, Eq. fresnel_prop."""
     return ifft2u(fft2u(psi) * h)
@@ -308,7 +326,7 @@ def loss_grad(geom, obj_a, obj_b, probe, positions, i_meas):
     return (value,) + reverse_sweep(geom, obj_a, obj_b, probe, positions, d_di)
 
 
-def reverse_sweep(geom, obj_a, obj_b, probe, positions, d_di, want_gaps=False):
+def reverse_sweep(geom, obj_a, obj_b, probe, positions, d_di, want_gaps=False, lam_exit=None):
     """Gradient of a loss whose derivative with respect to the predicted
     intensity I = |Psi|^2 of this probe is d_di [B][N][N]: the far-field
     residual g = 2 d_di Psi is pulled back through the Fraunhofer transform,
@@ -321,6 +339,8 @@ def reverse_sweep(geom, obj_a, obj_b, probe, positions, d_di, want_gaps=False):
     F^-1[i pi lambda |nu|^2 F psi_{j+1}], and with mu = dL/dpsi_{j+1}
     dL/dd_j = Re sum conj(F mu) (i pi lambda |nu|^2) F psi_{j+1}
     (the real inner product of a real parameter's derivative; F unitary).
+    ``lam_exit``, if given, is dL/dphi_{S-1} (another detector model than
+    the far field); d_di is then unused.
     """
     corners, shifts = split_position(positions)
     n, s = geom.n, geom.n_slices
@@ -333,10 +353,11 @@ def reverse_sweep(geom, obj_a, obj_b, probe, positions, d_di, want_gaps=False):
     tb = take_chunks(obj_b, corners, n)
     t = transmission(ta, tb, geom.obj_repr, kdz)
     exit_phi, psis, phis = exit_waves(geom, obj_a, obj_b, probe, positions, keep_slices=True)
-    psi_det = far_field(exit_phi)
-
-    g_det = 2.0 * d_di * psi_det
-    lam = far_field_adjoint(g_det)                       # dL/dphi_{S-1}
+    if lam_exit is None:
+        g_det = 2.0 * d_di * far_field(exit_phi)
+        lam = far_field_adjoint(g_det)                   # dL/dphi_{S-1}
+    else:
+        lam = lam_exit
     g_ta = np.empty_like(ta)
     g_tb = np.empty_like(tb)
     for j in range(s - 1, -1, -1):
@@ -385,6 +406,70 @@ def loss_grad_gaps(geom, obj_a, obj_b, probe, positions, i_meas):
     value = loss_value(geom.loss, i_pred, i_meas, geom.eps, n_norm)
     d_di = loss_dI(geom.loss, i_pred, i_meas, geom.eps, n_norm)
     return (value,) + reverse_sweep(geom, obj_a, obj_b, probe, positions, d_di, want_gaps=True)
+
+
+# ---------------------------------------------------------------------------
+# Near field (holography, near-field ptychography): Fresnel propagation to
+# the detector instead of the Fraunhofer transform (Eq. fresnel_prop with
+# the paraxial or the Sommerfeld kernel; Sec. S1.D, free propagation
+# distance refinement)
+# ---------------------------------------------------------------------------
+
+def nearfield_kernels(geom, dists, kind):
+    """Transfer functions to the detector for each distance (metres)."""
+    make = {"paraxial": fresnel_kernel, "sommerfeld": sommerfeld_kernel}[kind]
+    return [make(geom.n, geom.wavelength_m, geom.pixel_m, d) for d in np.asarray(dists, dtype=np.float64)]
+
+
+def nearfield_kernel_ddist(geom, kind):
+    """d log H / d d: i pi lambda |nu|^2 (paraxial) or -i k sqrt(1 - lambda^2 |nu|^2)
+    inside the propagating band (Sommerfeld; H = 0 outside)."""
+    nu = np.fft.fftfreq(geom.n, d=geom.pixel_m)
+    nu2 = nu[:, None] ** 2 + nu[None, :] ** 2
+    if kind == "paraxial":
+        return 1j * np.pi * geom.wavelength_m * nu2
+    x = geom.wavelength_m ** 2 * nu2
+    k = 2.0 * np.pi / geom.wavelength_m
+    return np.where(x < 1.0, -1j * k * np.sqrt(np.clip(1.0 - x, 0.0, None)), 0.0)
+
+
+def forward_nearfield(geom, obj_a, obj_b, probe, positions, dists, dist_idx, kind="paraxial"):
+    """Detector intensities |F^-1[H_b F phi_exit]|^2 [B][N][N] (natural order),
+    H_b the transfer function of position b's distance dists[dist_idx[b]]."""
+    hs = nearfield_kernels(geom, dists, kind)
+    exit_phi = exit_waves(geom, obj_a, obj_b, probe, positions)
+    hb = np.stack([hs[i] for i in np.asarray(dist_idx)])
+    return np.abs(fresnel_propagate(exit_phi, hb)) ** 2
+
+
+def loss_nearfield(geom, obj_a, obj_b, probe, positions, i_meas, dists, dist_idx, kind="paraxial"):
+    i_pred = forward_nearfield(geom, obj_a, obj_b, probe, positions, dists, dist_idx, kind)
+    return loss_value(geom.loss, i_pred, i_meas, geom.eps)
+
+
+def loss_grad_nearfield(geom, obj_a, obj_b, probe, positions, i_meas, dists, dist_idx, kind="paraxial"):
+    """Loss and gradients of the near-field model: (loss, g_a, g_b, g_probe,
+    g_shift, g_dist [n_dist]).  With g = 2 dL/dI psi_det the residual at the
+    detector, the exit-wave gradient is F^-1[conj(H_b) F g] and
+    dL/dd_b = Re sum conj(F g) (dH_b/dd) F phi_exit, summed over the
+    positions that share a distance."""
+    hs = nearfield_kernels(geom, dists, kind)
+    dlog = nearfield_kernel_ddist(geom, kind)
+    idx = np.asarray(dist_idx)
+    hb = np.stack([hs[i] for i in idx])
+    exit_phi = exit_waves(geom, obj_a, obj_b, probe, positions)
+    exit_f = fft2u(exit_phi)
+    psi_det = ifft2u(exit_f * hb)
+    i_pred = np.abs(psi_det) ** 2
+    n_norm = i_pred.size
+    value = loss_value(geom.loss, i_pred, i_meas, geom.eps, n_norm)
+    g_det = 2.0 * loss_dI(geom.loss, i_pred, i_meas, geom.eps, n_norm) * psi_det
+    g_f = fft2u(g_det)
+    per_pos = np.sum(np.real(np.conj(g_f) * dlog * hb * exit_f), axis=(1, 2))
+    g_dist = np.zeros(len(np.atleast_1d(dists)))
+    np.add.at(g_dist, idx, per_pos)
+    lam_exit = ifft2u(g_f * np.conj(hb))
+    return (value,) + reverse_sweep(geom, obj_a, obj_b, probe, positions, None, lam_exit=lam_exit) + (g_dist,)
 
 
 # ---------------------------------------------------------------------------

@@ -66,6 +66,13 @@ SIGNATURES = {
                                            ctypes.c_size_t]),
     "adorym_loss_grad_gaps": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P,
                                              ctypes.c_size_t, _P, _P, _P, _P, _P, _P, _P]),
+    "adorym_prior_workspace_size": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "adorym_prior_grad": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _P,
+                                         _P, ctypes.c_size_t, _P, _P, _P, ctypes.c_int32]),
+    "adorym_prior_weights": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_double, _P, ctypes.c_size_t, _P, _P]),
+    "adorym_support_project": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t]),
     "adorym_modes_workspace_size": (ctypes.c_size_t, [_GP, ctypes.c_int32, ctypes.c_int32]),
     "adorym_loss_grad_modes": (ctypes.c_int, [_P, _GP, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P,
                                               ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),

@@ -234,6 +234,62 @@ class Context:
         check(st, self._ctx)
         return out
 
+    # ------------------------------------------------- object priors
+    def _check_obj(self, *ts):
+        shape = tuple(ts[0].shape)
+        for t in ts:
+            if t is None:
+                continue
+            if t.dtype != torch.float32 or t.dim() != 3 or tuple(t.shape) != shape or not t.is_contiguous() \
+                    or t.device != self.device:
+                raise ValueError(f"expected contiguous float32 [S][Ly][Lx] tensors of one shape on {self.device}")
+        return shape
+
+    def prior_grad(self, obj_repr, obj_a, obj_b, l1_a=0.0, l1_b=0.0, tv=0.0, weights=None, out=None,
+                   accumulate=True, workspace=None):
+        """Object priors (Eq. tikhonov): l1 / reweighted l1 (``weights`` = (w_a, w_b)) and TV.
+        Returns ``{"value", "g_a", "g_b"}``; with ``accumulate`` the gradients are added onto
+        ``out["g_a"], out["g_b"]`` (e.g. the data gradient)."""
+        self._bind_stream()
+        w_a, w_b = weights if weights is not None else (None, None)
+        s, ly, lx = self._check_obj(obj_a, obj_b, w_a, w_b)
+        out = dict(out or {})
+        dev = self.device
+        out.setdefault("value", torch.empty((), dtype=torch.float64, device=dev))
+        for k, ref in (("g_a", obj_a), ("g_b", obj_b)):
+            if k not in out:
+                out[k] = torch.zeros_like(ref)
+        self._check_obj(obj_a, out["g_a"], out["g_b"])
+        ws = workspace if workspace is not None else torch.empty(
+            int(load().adorym_prior_workspace_size(s, ly, lx)), dtype=torch.uint8, device=dev)
+        check(load().adorym_prior_grad(self._ctx, REPRS[obj_repr], _ptr(obj_a), _ptr(obj_b), s, ly, lx,
+                                       float(l1_a), float(l1_b), float(tv), _ptr(w_a), _ptr(w_b), _ptr(ws),
+                                       ws.numel(), _ptr(out["value"]), _ptr(out["g_a"]), _ptr(out["g_b"]),
+                                       int(bool(accumulate))), self._ctx)
+        return out
+
+    def prior_weights(self, obj_repr, snap_a, snap_b, eps, workspace=None):
+        """Reweighted-l1 weights W = max|q| / (|q| + eps) of a snapshot."""
+        self._bind_stream()
+        s, ly, lx = self._check_obj(snap_a, snap_b)
+        w_a, w_b = torch.empty_like(snap_a), torch.empty_like(snap_b)
+        ws = workspace if workspace is not None else torch.empty(
+            int(load().adorym_prior_workspace_size(s, ly, lx)), dtype=torch.uint8, device=self.device)
+        check(load().adorym_prior_weights(self._ctx, REPRS[obj_repr], _ptr(snap_a), _ptr(snap_b), s, ly, lx,
+                                          float(eps), _ptr(ws), ws.numel(), _ptr(w_a), _ptr(w_b)), self._ctx)
+        return w_a, w_b
+
+    def support_project(self, obj_repr, mask, obj_a, obj_b):
+        """Finite support, in place: voxels with mask == 0 become vacuum."""
+        self._bind_stream()
+        self._check_obj(obj_a, obj_b)
+        if mask.dtype != torch.uint8 or mask.numel() != obj_a.numel() or not mask.is_contiguous() \
+                or mask.device != self.device:
+            raise ValueError("mask: expected contiguous uint8 of the object's size")
+        check(load().adorym_support_project(self._ctx, REPRS[obj_repr], _ptr(mask), _ptr(obj_a), _ptr(obj_b),
+                                            obj_a.numel()), self._ctx)
+        return obj_a, obj_b
+
     # ------------------------------------------------- probe modes
     def modes_workspace_size(self, geom: Geometry, batch: int, n_modes: int) -> int:
         return int(load().adorym_modes_workspace_size(ctypes.byref(geom.to_c()), batch, n_modes))

@@ -625,3 +625,122 @@ def test_gap_gradients_match_central_finite_differences(loss):
             args_m = (am, b) if arr is a else (a, am)
             fd = (om.loss(geom, *args_p, p, pos, i_meas) - om.loss(geom, *args_m, p, pos, i_meas)) / (2 * hu)
             assert g[zz, y, x] == pytest.approx(fd, rel=1e-5, abs=1e-7 * np.max(np.abs(g)))
+
+
+# ---------------------------------------------------------------- near field (Eqs. fresnel_prop, sommerfeld_kernel)
+
+def test_sommerfeld_kernel_on_plane_waves():
+    """A plane wave of grid frequency nu0 is an eigenfunction of free space:
+    it picks up exp(-i k d sqrt(1 - lambda^2 |nu0|^2)) if it propagates and is
+    removed if it is evanescent (lambda |nu0| > 1)."""
+    n, dx, lam, d = 32, 1e-10, 1.5e-10, 2e-9           # lambda / (2 dx) = 0.75: some frequencies evanescent
+    yy, xx = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    k = 2 * np.pi / lam
+    h = om.sommerfeld_kernel(n, lam, dx, d)
+    for ky, kx in ((0, 0), (3, -2), (5, 7), (-9, 4), (12, 12), (16, 0)):
+        psi = np.exp(2j * np.pi * (ky * yy + kx * xx) / n)
+        nu2 = (ky ** 2 + kx ** 2) / (n * dx) ** 2
+        out = om.fresnel_propagate(psi, h)
+        if lam ** 2 * nu2 < 1:
+            assert rel(out, psi * np.exp(-1j * k * d * np.sqrt(1 - lam ** 2 * nu2))) < 1e-12, (ky, kx)
+        else:
+            assert np.max(np.abs(out)) < 1e-13, (ky, kx)
+
+
+def test_sommerfeld_reduces_to_paraxial_at_small_angles():
+    """H2 exp(+i k d) - H1 = O(k d lambda^4 |nu|^4 / 8): at 1 um pixels and
+    hard X-rays the two near-field models agree to that order, and they
+    part where the angle is large."""
+    sc = synth.config3_fd_subcase()
+    lam = sc.wavelength_m
+    for dx, d, close in ((1e-6, 0.4, True), (2e-10, 3e-8, False)):
+        geom = om.Geometry(sc.n, sc.n_slices, lam, dx, sc.slice_dz_m)
+        i1 = om.forward_nearfield(geom, sc.obj_a, sc.obj_b, sc.probe, sc.positions, [d], np.zeros(9, int), "paraxial")
+        i2 = om.forward_nearfield(geom, sc.obj_a, sc.obj_b, sc.probe, sc.positions, [d], np.zeros(9, int), "sommerfeld")
+        bound = 2 * np.pi / lam * d * lam ** 4 * (0.5 / dx) ** 4 * 2 / 8 * 4
+        if close:
+            assert rel(i2, i1) < max(bound, 1e-12)
+        else:
+            assert rel(i2, i1) > 1e-3
+
+
+def test_nearfield_of_a_gaussian_beam_through_vacuum():
+    """Vacuum slices: the detector sees the Gaussian beam's closed form at the
+    total distance (S-1) dz + d."""
+    n, dx, lam, dz, s = 64, 10e-9, 1.2398419843320002e-10, 10e-9, 3
+    w0 = 5 * dx
+    zr = math.pi * w0 ** 2 / lam
+    c = (np.arange(n) - n / 2) * dx
+    r2 = c[:, None] ** 2 + c[None, :] ** 2
+    probe = np.exp(-r2 / w0 ** 2)
+    geom = om.Geometry(n, s, lam, dx, dz)
+    z = np.zeros((s, n, n))
+    for d in (0.5 * zr, 1.5 * zr):
+        q = 1.0 - 1j * ((s - 1) * dz + d) / zr
+        ref = np.abs(np.exp(-r2 / (w0 ** 2 * q)) / q) ** 2
+        got = om.forward_nearfield(geom, z, z, probe, np.zeros((1, 2)), [d], [0], "paraxial")[0]
+        assert rel(got, ref) < 1e-9      # the periodic window's aliasing of the tails is ~3e-11
+
+
+def test_nearfield_distance_is_an_empty_last_slice():
+    """Detector distance dz behind S slices = S + 1 slices (the last empty) at distance 0."""
+    geom, a, b, p, pos, _ = _fd_case("gaussian")
+    i_d = om.forward_nearfield(geom, a, b, p, pos, [geom.slice_dz_m], np.zeros(len(pos), int))
+    a1 = np.concatenate([a, np.zeros_like(a[:1])])
+    b1 = np.concatenate([b, np.zeros_like(b[:1])])
+    g1 = om.Geometry(geom.n, geom.n_slices + 1, geom.wavelength_m, geom.pixel_m, geom.slice_dz_m)
+    i_0 = om.forward_nearfield(g1, a1, b1, p, pos, [0.0], np.zeros(len(pos), int))
+    assert rel(i_d, i_0) < 1e-13
+
+
+def _nf_case(loss, kind):
+    geom, a, b, p, pos, _ = _fd_case(loss)
+    sc = synth.config3_fd_subcase()
+    dists = np.array([0.6e-6, 1.4e-6])
+    idx = np.arange(len(pos)) % 2
+    i_true = om.forward_nearfield(geom, sc.obj_a, sc.obj_b, sc.probe, sc.positions, dists, idx, kind)
+    i_meas = i_true if loss == "gaussian" else np.random.default_rng(3).poisson(i_true).astype(float)
+    return geom, a, b, p, pos, i_meas, dists * np.array([1.07, 0.95]), idx
+
+
+@pytest.mark.parametrize("kind", ["paraxial", "sommerfeld"])
+@pytest.mark.parametrize("loss", ["gaussian", "poisson"])
+def test_nearfield_gradients_match_central_finite_differences(loss, kind):
+    geom, a, b, p, pos, i_meas, dists, idx = _nf_case(loss, kind)
+    L, ga, gb, gp, gs, gd = om.loss_grad_nearfield(geom, a, b, p, pos, i_meas, dists, idx, kind)
+
+    def f(a_=a, p_=p, pos_=pos, d_=dists):
+        return om.loss_nearfield(geom, a_, b, p_, pos_, i_meas, d_, idx, kind)
+
+    assert L == pytest.approx(f(), rel=1e-14)
+    h = 3e-11
+    for j in range(len(dists)):
+        dp, dm = dists.copy(), dists.copy()
+        dp[j] += h
+        dm[j] -= h
+        assert gd[j] == pytest.approx((f(d_=dp) - f(d_=dm)) / (2 * h), rel=1e-6, abs=1e-9 * np.max(np.abs(gd))), j
+    rng = np.random.default_rng(17)
+    corners, _ = om.split_position(pos)
+    hu = 1e-5 / geom.kdz
+    for _ in range(4):
+        k = rng.integers(len(corners))
+        zz, y, x = rng.integers(geom.n_slices), corners[k, 0] + rng.integers(geom.n), corners[k, 1] + rng.integers(geom.n)
+        ap, am = a.copy(), a.copy()
+        ap[zz, y, x] += hu
+        am[zz, y, x] -= hu
+        assert ga[zz, y, x] == pytest.approx((f(a_=ap) - f(a_=am)) / (2 * hu), rel=1e-5, abs=1e-7 * np.max(np.abs(ga)))
+    hp = 1e-6 * np.max(np.abs(p))
+    for _ in range(3):
+        iy, ix = rng.integers(geom.n, size=2)
+        for unit, comp in ((1.0, np.real), (1j, np.imag)):
+            pp, pm = p.copy(), p.copy()
+            pp[iy, ix] += unit * hp
+            pm[iy, ix] -= unit * hp
+            assert comp(gp[iy, ix]) == pytest.approx((f(p_=pp) - f(p_=pm)) / (2 * hp), rel=1e-5,
+                                                     abs=1e-7 * np.max(np.abs(gp)))
+    for k in range(2):
+        for c in range(2):
+            pp, pm = pos.copy(), pos.copy()
+            pp[k, c] += 1e-6
+            pm[k, c] -= 1e-6
+            assert gs[k, c] == pytest.approx((f(pos_=pp) - f(pos_=pm)) / 2e-6, rel=1e-5, abs=1e-7 * np.max(np.abs(gs)))
