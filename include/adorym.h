@@ -69,6 +69,7 @@ typedef enum {
 
 enum { ADORYM_LOSS_GAUSSIAN = 0, ADORYM_LOSS_POISSON = 1 };
 enum { ADORYM_OBJ_DELTA_BETA = 0, ADORYM_OBJ_REAL_IMAG = 1 };
+enum { ADORYM_PROP_PARAXIAL = 0, ADORYM_PROP_SOMMERFELD = 1 };   /* near-field detector kernels */
 enum {
   ADORYM_ACCUMULATE_GRADS = 1u, /* add into the gradient arrays instead of overwriting */
   ADORYM_DETERMINISTIC = 2u     /* bitwise-reproducible object gradients (see below)  */
@@ -171,6 +172,41 @@ adorym_status adorym_loss_grad_gaps(adorym_ctx* ctx, const adorym_geom* g,
                                     const double* gaps, const float* i_meas, void* workspace, size_t ws_bytes,
                                     double* loss, float* g_a, float* g_b, float* g_probe,
                                     float* g_shift, double* g_gaps, float* intensity);
+
+/* ---- Near field: Fresnel propagation to the detector (holography,
+ * near-field ptychography; Eq. fresnel_prop with Eq. paraxial_kernel or
+ * Eq. sommerfeld_kernel; free propagation distance refinement, Sec. S1.D)
+ * In place of the Fraunhofer transform the exit wave is propagated over the
+ * distance dist[dist_idx[b]] to the detector: I = |F^-1[H F phi_exit]|^2,
+ * natural (not centred) order, float32 [B][N][N].
+ * kind: ADORYM_PROP_PARAXIAL, H = exp(i pi lambda d |nu|^2), or
+ * ADORYM_PROP_SOMMERFELD, H = exp(-i k d sqrt(1 - lambda^2 |nu|^2)) with the
+ * evanescent frequencies (lambda |nu| >= 1) removed; its global phase
+ * exp(-i k d) is left out (no effect on intensities or their gradients).
+ * dist: DEVICE float64 [n_dist] metres (any sign); dist_idx: DEVICE int32
+ * [B], each in [0, n_dist) (a position with another index contributes
+ * nothing and adorym_sync_error reports ADORYM_EINVAL).
+ * adorym_loss_grad_nearfield also writes, if g_dist (DEVICE float64
+ * [n_dist]) is not NULL, dL/d(dist[d]) summed over the positions with that
+ * index (overwritten, or added with ADORYM_ACCUMULATE_GRADS), reduced in
+ * FP64 in a fixed order.  Workspace of adorym_nearfield_workspace_size
+ * bytes for both calls.  Both run with the fixed split of
+ * ADORYM_DETERMINISTIC (1 for N <= 96, 4 for N = 128, 6 for N = 192). */
+size_t adorym_nearfield_workspace_size(const adorym_geom* g, int32_t batch, int32_t n_dist);
+adorym_status adorym_forward_nearfield(adorym_ctx* ctx, const adorym_geom* g,
+                                       const float* obj_a, const float* obj_b, const float* probe,
+                                       const int32_t* corner, const float* shift, int32_t batch,
+                                       int32_t kind, const double* dist, int32_t n_dist,
+                                       const int32_t* dist_idx, float* intensity,
+                                       void* workspace, size_t ws_bytes);
+adorym_status adorym_loss_grad_nearfield(adorym_ctx* ctx, const adorym_geom* g,
+                                         const float* obj_a, const float* obj_b, const float* probe,
+                                         const int32_t* corner, const float* shift, int32_t batch,
+                                         int32_t kind, const double* dist, int32_t n_dist,
+                                         const int32_t* dist_idx, const float* i_meas,
+                                         void* workspace, size_t ws_bytes, double* loss, float* g_a,
+                                         float* g_b, float* g_probe, float* g_shift, double* g_dist,
+                                         float* intensity);
 
 /* ---- Several mutually incoherent probe modes (Eq. multimode) ----------
  * The detector records the sum over modes m of |Psi_m|^2, each mode

@@ -20,6 +20,8 @@ LOSS_GAUSSIAN, LOSS_POISSON = 0, 1
 OBJ_DELTA_BETA, OBJ_REAL_IMAG = 0, 1
 ACCUMULATE_GRADS = 1
 DETERMINISTIC = 2
+PROP_PARAXIAL = 0
+PROP_SOMMERFELD = 1
 
 
 class Geom(ctypes.Structure):
@@ -61,6 +63,12 @@ SIGNATURES = {
     "adorym_forward": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t]),
     "adorym_loss_grad": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t,
                                         _P, _P, _P, _P, _P, _P]),
+    "adorym_nearfield_workspace_size": (ctypes.c_size_t, [_GP, ctypes.c_int32, ctypes.c_int32]),
+    "adorym_forward_nearfield": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P,
+                                                ctypes.c_int32, _P, _P, _P, ctypes.c_size_t]),
+    "adorym_loss_grad_nearfield": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P,
+                                                  ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P, _P, _P, _P, _P,
+                                                  _P, _P]),
     "adorym_gaps_workspace_size": (ctypes.c_size_t, [_GP, ctypes.c_int32]),
     "adorym_forward_gaps": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P,
                                            ctypes.c_size_t]),

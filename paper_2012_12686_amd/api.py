@@ -234,6 +234,70 @@ class Context:
         check(st, self._ctx)
         return out
 
+    # ------------------------------------------------- near field
+    _KINDS = {"paraxial": _lib.PROP_PARAXIAL, "sommerfeld": _lib.PROP_SOMMERFELD}
+
+    def _check_nf(self, b, dists, dist_idx):
+        if dists.dtype != torch.float64 or dists.dim() != 1 or not dists.is_contiguous() or dists.device != self.device:
+            raise ValueError("dists: expected contiguous float64 [n_dist] on the device")
+        if dist_idx.dtype != torch.int32 or tuple(dist_idx.shape) != (b,) or not dist_idx.is_contiguous() \
+                or dist_idx.device != self.device:
+            raise ValueError("dist_idx: expected contiguous int32 [B] on the device")
+        return dists.numel()
+
+    def nearfield_workspace_size(self, geom: Geometry, batch: int, n_dist: int) -> int:
+        return int(load().adorym_nearfield_workspace_size(ctypes.byref(geom.to_c()), batch, n_dist))
+
+    def forward_nearfield(self, geom, obj_a, obj_b, probe, corner, shift, dists, dist_idx, kind="paraxial",
+                          out=None, workspace=None):
+        """Near-field detector intensities [B][N][N] (natural order): the exit
+        wave Fresnel-propagated over dists[dist_idx[b]] (paraxial or Sommerfeld kernel)."""
+        self._bind_stream()
+        b = self._check_inputs(geom, obj_a, obj_b, probe, corner, shift)
+        nd = self._check_nf(b, dists, dist_idx)
+        out = out if out is not None else torch.empty((b, geom.n, geom.n), dtype=torch.float32, device=self.device)
+        ws = workspace if workspace is not None else torch.empty(self.nearfield_workspace_size(geom, b, nd),
+                                                                 dtype=torch.uint8, device=self.device)
+        st = load().adorym_forward_nearfield(self._ctx, ctypes.byref(geom.to_c()), _ptr(obj_a), _ptr(obj_b),
+                                             _ptr(torch.view_as_real(probe)), _ptr(corner), _ptr(shift), b,
+                                             self._KINDS[kind], _ptr(dists), nd, _ptr(dist_idx), _ptr(out), _ptr(ws),
+                                             ws.numel())
+        check(st, self._ctx)
+        return out
+
+    def loss_grad_nearfield(self, geom, obj_a, obj_b, probe, corner, shift, dists, dist_idx, i_meas,
+                            kind="paraxial", grads=True, intensity=False, out=None, workspace=None):
+        """As :meth:`loss_grad` for the near-field detector; with ``grads`` also
+        ``g_dist`` (float64 [n_dist], dL/d distance in 1/m)."""
+        self._bind_stream()
+        b = self._check_inputs(geom, obj_a, obj_b, probe, corner, shift)
+        nd = self._check_nf(b, dists, dist_idx)
+        if tuple(i_meas.shape) != (b, geom.n, geom.n) or i_meas.dtype != torch.float32 or not i_meas.is_contiguous():
+            raise ValueError("i_meas: expected contiguous float32 [B][N][N]")
+        out = dict(out or {})
+        dev = self.device
+        if "loss" not in out:
+            out["loss"] = torch.empty((), dtype=torch.float64, device=dev)
+        if grads:
+            for name, shape, dt in (("g_a", obj_a.shape, torch.float32), ("g_b", obj_b.shape, torch.float32),
+                                    ("g_probe", probe.shape, torch.complex64), ("g_shift", (b, 2), torch.float32),
+                                    ("g_dist", (nd,), torch.float64)):
+                if name not in out:
+                    out[name] = (torch.zeros if geom.accumulate else torch.empty)(shape, dtype=dt, device=dev)
+        if intensity and "intensity" not in out:
+            out["intensity"] = torch.empty((b, geom.n, geom.n), dtype=torch.float32, device=dev)
+        ws = workspace if workspace is not None else torch.empty(self.nearfield_workspace_size(geom, b, nd),
+                                                                 dtype=torch.uint8, device=dev)
+        gp = out.get("g_probe")
+        st = load().adorym_loss_grad_nearfield(
+            self._ctx, ctypes.byref(geom.to_c()), _ptr(obj_a), _ptr(obj_b), _ptr(torch.view_as_real(probe)),
+            _ptr(corner), _ptr(shift), b, self._KINDS[kind], _ptr(dists), nd, _ptr(dist_idx), _ptr(i_meas), _ptr(ws),
+            ws.numel(), _ptr(out["loss"]), _ptr(out.get("g_a")), _ptr(out.get("g_b")),
+            _ptr(torch.view_as_real(gp) if gp is not None else None), _ptr(out.get("g_shift")),
+            _ptr(out.get("g_dist")), _ptr(out.get("intensity")))
+        check(st, self._ctx)
+        return out
+
     # ------------------------------------------------- object priors
     def _check_obj(self, *ts):
         shape = tuple(ts[0].shape)

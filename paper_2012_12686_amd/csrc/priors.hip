@@ -11,7 +11,9 @@
 // (W = 1 unless weights are given).  d|t|/dt at t = 0 is taken as 0.
 //
 // The gradient kernel is one pass over the object, HBM-bound: every
-// workgroup owns a 64 x 4 column tile and a run of kZc slices and marches
+// workgroup owns a 64 x 4 column tile and a run of kZc = 32 slices (a
+// sweep of tile heights and run lengths on the 512 x 512 x 128 object:
+// taller tiles lose more to fewer workgroups than they save in halo reads) and marches
 // along z; each slice's tile with a one-voxel halo is staged in LDS as the
 // two quantities, so x/y neighbours come from LDS and z neighbours from the
 // previous step's registers.  The derivative of a voxel is final once the
@@ -33,8 +35,16 @@
 
 namespace {
 
-constexpr int kTx = 64, kTy = 4, kHx = kTx + 2, kHy = kTy + 2;
-constexpr int kZc = 16;                    // slices per workgroup
+#ifndef ADORYM_PRIOR_ROWS
+#define ADORYM_PRIOR_ROWS 1
+#endif
+#ifndef ADORYM_PRIOR_ZRUN
+#define ADORYM_PRIOR_ZRUN 32
+#endif
+constexpr int kRows = ADORYM_PRIOR_ROWS;   // rows per thread (256 threads = 64 x 4)
+constexpr int kTx = 64, kTy = 4 * kRows, kHx = kTx + 2, kHy = kTy + 2;
+constexpr int kHalo = kHx * kHy, kHaloPer = (kHalo + 255) / 256;
+constexpr int kZc = ADORYM_PRIOR_ZRUN;     // slices per workgroup
 constexpr int kRedBlocks = 1024;           // fixed grid of the reductions
 
 // scalars in the workspace (doubles): [0] mean|O|, [1] mean-term correction
@@ -96,98 +106,129 @@ template <int REPR>
 __global__ void __launch_bounds__(256) prior_grad_kernel(PriorArgs p) {
   __shared__ float s1[kHy][kHx], s2[kHy][kHx];
   __shared__ double red[256];
-  const int tx = threadIdx.x % kTx, ty = threadIdx.x / kTx;
+  const int tx = threadIdx.x % kTx, ty = threadIdx.x / kTx;    // rows ty + 4 r of the tile
   const int x0 = blockIdx.x * kTx, y0 = blockIdx.y * kTy;
-  const int x = x0 + tx, y = y0 + ty;
-  const bool mine = x < p.Lx && y < p.Ly;
+  const int x = x0 + tx;
   const size_t plane = (size_t)p.Ly * p.Lx;
   const float mean_mod = (REPR == ADORYM_OBJ_DELTA_BETA) ? 0.f : (float)p.scal[0];
   const float corr = (REPR == ADORYM_OBJ_DELTA_BETA) ? 0.f : (float)p.scal[1];
-  double val = 0.0;
-  float q1p = 0.f, q2p = 0.f, d1p = 0.f, d2p = 0.f, ap = 0.f, bp = 0.f;
+  const float ct = p.ctv;
   const int z0 = blockIdx.z * kZc, z1 = min(p.S, z0 + kZc);
-  if (mine && z0 > 0) {        // the slice below the run, for the pair (z0-1, z0)
-    const size_t i0 = (size_t)(z0 - 1) * plane + (size_t)y * p.Lx + x;
-    quantities<REPR>(p.a[i0], p.b[i0], mean_mod, q1p, q2p);
+  // this thread's halo elements: in-plane offset, -1 outside the object,
+  // -2 past the end of the halo
+  int hoff[kHaloPer];
+#pragma unroll
+  for (int u = 0; u < kHaloPer; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    const int gy = y0 + i / kHx - 1, gx = x0 + i % kHx - 1;
+    hoff[u] = i >= kHalo ? -2 : ((gy >= 0 && gy < p.Ly && gx >= 0 && gx < p.Lx) ? gy * p.Lx + gx : -1);
   }
+  float na[kHaloPer], nb[kHaloPer];      // the next slice's halo values, loaded a slice ahead
+  auto fetch = [&](int z) {
+#pragma unroll
+    for (int u = 0; u < kHaloPer; ++u) {
+      const bool in = hoff[u] >= 0;
+      na[u] = in ? p.a[(size_t)z * plane + hoff[u]] : 0.f;
+      nb[u] = in ? p.b[(size_t)z * plane + hoff[u]] : 0.f;
+    }
+  };
+  bool mine[kRows];
+  float q1p[kRows], q2p[kRows], d1p[kRows], d2p[kRows], ap[kRows], bp[kRows], gpa[kRows], gpb[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int y = y0 + ty + 4 * r;
+    mine[r] = x < p.Lx && y < p.Ly;
+    q1p[r] = q2p[r] = d1p[r] = d2p[r] = ap[r] = bp[r] = gpa[r] = gpb[r] = 0.f;
+    if (mine[r] && z0 > 0) {             // the slice below the run, for the pair (z0-1, z0)
+      const size_t i0 = (size_t)(z0 - 1) * plane + (size_t)y * p.Lx + x;
+      quantities<REPR>(p.a[i0], p.b[i0], mean_mod, q1p[r], q2p[r]);
+    }
+  }
+  double val = 0.0;
+  if (z0 < z1) fetch(z0);
   for (int z = z0; z < z1; ++z) {
-    // stage slice z's quantities with a one-voxel halo
-    __syncthreads();
-    for (int i = threadIdx.x; i < kHx * kHy; i += 256) {
-      const int hy = i / kHx, hx = i % kHx;
-      const int gy = y0 + hy - 1, gx = x0 + hx - 1;
+    __syncthreads();                     // the last slice's LDS reads are done
+#pragma unroll
+    for (int u = 0; u < kHaloPer; ++u) {
+      const int i = threadIdx.x + 256 * u;
+      if (hoff[u] == -2) continue;
       float q1 = 0.f, q2 = 0.f;
-      if (gy >= 0 && gy < p.Ly && gx >= 0 && gx < p.Lx) {
-        const size_t idx = z * plane + (size_t)gy * p.Lx + gx;
-        quantities<REPR>(p.a[idx], p.b[idx], mean_mod, q1, q2);
-      }
-      s1[hy][hx] = q1;
-      s2[hy][hx] = q2;
+      if (hoff[u] >= 0) quantities<REPR>(na[u], nb[u], mean_mod, q1, q2);
+      s1[i / kHx][i % kHx] = q1;
+      s2[i / kHx][i % kHx] = q2;
     }
     __syncthreads();
-    if (!mine) continue;
-    const size_t idx = z * plane + (size_t)y * p.Lx + x;
-    const float q1 = s1[ty + 1][tx + 1], q2 = s2[ty + 1][tx + 1];
-    const float w1 = p.wa ? p.wa[idx] : 1.f, w2 = p.wb ? p.wb[idx] : 1.f;
-    // l1 (the mean term's own derivative enters through corr)
-    float d1 = p.c1 * w1 * sgn(q1) - corr, d2 = p.c2 * w2 * sgn(q2);
-    val += (double)(p.c1 * w1 * fabsf(q1) + p.c2 * w2 * fabsf(q2));
-    if (p.ctv != 0.f) {
-      const float ct = p.ctv;
-      float tv = 0.f;
-      if (x + 1 < p.Lx) {
-        const float e1 = s1[ty + 1][tx + 2] - q1, e2 = s2[ty + 1][tx + 2] - q2;
-        tv += fabsf(e1) + fabsf(e2);
-        d1 -= ct * sgn(e1);
-        d2 -= ct * sgn(e2);
+    if (z + 1 < z1) fetch(z + 1);        // in flight while this slice is processed
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      if (!mine[r]) continue;
+      const int ly = ty + 4 * r, y = y0 + ly;
+      const size_t idx = (size_t)z * plane + (size_t)y * p.Lx + x;
+      const float q1 = s1[ly + 1][tx + 1], q2 = s2[ly + 1][tx + 1];
+      const float w1 = p.wa ? p.wa[idx] : 1.f, w2 = p.wb ? p.wb[idx] : 1.f;
+      // l1 (the mean term's own derivative enters through corr)
+      float d1 = p.c1 * w1 * sgn(q1) - corr, d2 = p.c2 * w2 * sgn(q2);
+      val += (double)(p.c1 * w1 * fabsf(q1) + p.c2 * w2 * fabsf(q2));
+      if (ct != 0.f) {
+        float tv = 0.f;
+        if (x + 1 < p.Lx) {
+          const float e1 = s1[ly + 1][tx + 2] - q1, e2 = s2[ly + 1][tx + 2] - q2;
+          tv += fabsf(e1) + fabsf(e2);
+          d1 -= ct * sgn(e1);
+          d2 -= ct * sgn(e2);
+        }
+        if (x > 0) {
+          d1 += ct * sgn(q1 - s1[ly + 1][tx]);
+          d2 += ct * sgn(q2 - s2[ly + 1][tx]);
+        }
+        if (y + 1 < p.Ly) {
+          const float e1 = s1[ly + 2][tx + 1] - q1, e2 = s2[ly + 2][tx + 1] - q2;
+          tv += fabsf(e1) + fabsf(e2);
+          d1 -= ct * sgn(e1);
+          d2 -= ct * sgn(e2);
+        }
+        if (y > 0) {
+          d1 += ct * sgn(q1 - s1[ly][tx + 1]);
+          d2 += ct * sgn(q2 - s2[ly][tx + 1]);
+        }
+        if (z > 0) {
+          const float e1 = q1 - q1p[r], e2 = q2 - q2p[r];
+          tv += fabsf(e1) + fabsf(e2);
+          d1 += ct * sgn(e1);
+          d2 += ct * sgn(e2);
+          d1p[r] -= ct * sgn(e1);
+          d2p[r] -= ct * sgn(e2);
+        }
+        val += (double)(ct * tv);
       }
-      if (x > 0) {
-        d1 += ct * sgn(q1 - s1[ty + 1][tx]);
-        d2 += ct * sgn(q2 - s2[ty + 1][tx]);
+      if (z > z0) {                      // voxel z-1 is complete
+        const size_t ip = idx - plane;
+        float ga, gb;
+        chain<REPR>(ap[r], bp[r], d1p[r], d2p[r], ga, gb);
+        p.ga[ip] = gpa[r] + ga;
+        p.gb[ip] = gpb[r] + gb;
       }
-      if (y + 1 < p.Ly) {
-        const float e1 = s1[ty + 2][tx + 1] - q1, e2 = s2[ty + 2][tx + 1] - q2;
-        tv += fabsf(e1) + fabsf(e2);
-        d1 -= ct * sgn(e1);
-        d2 -= ct * sgn(e2);
-      }
-      if (y > 0) {
-        d1 += ct * sgn(q1 - s1[ty][tx + 1]);
-        d2 += ct * sgn(q2 - s2[ty][tx + 1]);
-      }
-      if (z > 0) {
-        const float e1 = q1 - q1p, e2 = q2 - q2p;
-        tv += fabsf(e1) + fabsf(e2);
-        d1 += ct * sgn(e1);
-        d2 += ct * sgn(e2);
-        d1p -= ct * sgn(e1);
-        d2p -= ct * sgn(e2);
-      }
-      val += (double)(ct * tv);
+      q1p[r] = q1; q2p[r] = q2; d1p[r] = d1; d2p[r] = d2;
+      if constexpr (REPR != ADORYM_OBJ_DELTA_BETA) { ap[r] = p.a[idx]; bp[r] = p.b[idx]; }
+      // the data gradient this voxel's derivative is added onto, loaded a slice ahead
+      gpa[r] = p.accumulate ? p.ga[idx] : 0.f;
+      gpb[r] = p.accumulate ? p.gb[idx] : 0.f;
     }
-    if (z > z0) {
-      // voxel z-1 is complete
-      const size_t ip = idx - plane;
-      float ga, gb;
-      chain<REPR>(ap, bp, d1p, d2p, ga, gb);
-      p.ga[ip] = p.accumulate ? p.ga[ip] + ga : ga;
-      p.gb[ip] = p.accumulate ? p.gb[ip] + gb : gb;
-    }
-    q1p = q1; q2p = q2; d1p = d1; d2p = d2;
-    if constexpr (REPR != ADORYM_OBJ_DELTA_BETA) { ap = p.a[idx]; bp = p.b[idx]; }
   }
-  if (mine && z1 > z0) {
-    const size_t ip = (size_t)(z1 - 1) * plane + (size_t)y * p.Lx + x;
-    if (z1 < p.S && p.ctv != 0.f) {   // the pair (z1-1, z1) with the slice above the run
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    if (!mine[r] || z1 <= z0) continue;
+    const size_t ip = (size_t)(z1 - 1) * plane + (size_t)(y0 + ty + 4 * r) * p.Lx + x;
+    if (z1 < p.S && ct != 0.f) {         // the pair (z1-1, z1) with the slice above the run
       float q1n, q2n;
       quantities<REPR>(p.a[ip + plane], p.b[ip + plane], mean_mod, q1n, q2n);
-      d1p -= p.ctv * sgn(q1n - q1p);
-      d2p -= p.ctv * sgn(q2n - q2p);
+      d1p[r] -= ct * sgn(q1n - q1p[r]);
+      d2p[r] -= ct * sgn(q2n - q2p[r]);
     }
     float ga, gb;
-    chain<REPR>(ap, bp, d1p, d2p, ga, gb);
-    p.ga[ip] = p.accumulate ? p.ga[ip] + ga : ga;
-    p.gb[ip] = p.accumulate ? p.gb[ip] + gb : gb;
+    chain<REPR>(ap[r], bp[r], d1p[r], d2p[r], ga, gb);
+    p.ga[ip] = gpa[r] + ga;
+    p.gb[ip] = gpb[r] + gb;
   }
   const double tot = block_sum256(val, red);
   if (threadIdx.x == 0) p.part[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
