@@ -422,15 +422,21 @@ def nearfield_kernels(geom, dists, kind):
 
 
 def nearfield_kernel_ddist(geom, kind):
-    """d log H / d d: i pi lambda |nu|^2 (paraxial) or -i k sqrt(1 - lambda^2 |nu|^2)
-    inside the propagating band (Sommerfeld; H = 0 outside)."""
+    """d log H / d d: i pi lambda |nu|^2 (paraxial), and for the Sommerfeld
+    kernel -i k (sqrt(1 - lambda^2 |nu|^2) - 1) inside the propagating band
+    (0 outside).  The Sommerfeld kernel's own derivative is
+    -i k sqrt(1 - lambda^2 |nu|^2); the two differ by -i k, the derivative of
+    the global phase exp(-i k d), whose term -k Im<g, psi_det> vanishes for
+    any loss of the intensity (g = 2 dL/dI psi_det makes <g, psi_det> real).
+    Leaving it out avoids a ~1e11 rad/m factor times a rounding residual."""
     nu = np.fft.fftfreq(geom.n, d=geom.pixel_m)
     nu2 = nu[:, None] ** 2 + nu[None, :] ** 2
     if kind == "paraxial":
         return 1j * np.pi * geom.wavelength_m * nu2
     x = geom.wavelength_m ** 2 * nu2
     k = 2.0 * np.pi / geom.wavelength_m
-    return np.where(x < 1.0, -1j * k * np.sqrt(np.clip(1.0 - x, 0.0, None)), 0.0)
+    xs = np.where(x < 1.0, x, 0.0)
+    return np.where(x < 1.0, 1j * k * xs / (np.sqrt(1.0 - xs) + 1.0), 0.0)
 
 
 def forward_nearfield(geom, obj_a, obj_b, probe, positions, dists, dist_idx, kind="paraxial"):

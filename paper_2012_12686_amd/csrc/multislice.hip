@@ -35,6 +35,10 @@ extern template ADORYM_RUN_SIGNATURE(96, 8, 3);
 extern template ADORYM_BATCHED_SIGNATURE(96, 8, 3);
 extern template ADORYM_RUN_SIGNATURE(192, 8, 8);
 extern template ADORYM_BATCHED_SIGNATURE(192, 8, 8);
+extern template ADORYM_RUN_NF_SIGNATURE(64, 4, 1);
+extern template ADORYM_RUN_NF_SIGNATURE(96, 8, 1);
+extern template ADORYM_RUN_NF_SIGNATURE(128, 8, 4);
+extern template ADORYM_RUN_NF_SIGNATURE(192, 8, 6);
 extern template ADORYM_RUN_GAPS_SIGNATURE(64, 4, 1);
 extern template ADORYM_RUN_GAPS_SIGNATURE(96, 8, 1);
 extern template ADORYM_RUN_GAPS_SIGNATURE(128, 8, 4);
@@ -136,6 +140,25 @@ adorym_status dispatch_gaps(adorym_ctx* ctx, const adorym_geom* g, const float* 
     case 192: ADORYM_RUN_GAPS(192, 8, 6);
   }
 #undef ADORYM_RUN_GAPS
+  return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size");
+}
+
+// Near field: the same fixed splits.
+adorym_status dispatch_nf(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b, const float* probe,
+                          const int32_t* corner, const float* shift, int batch, int kind, const double* dist,
+                          int n_dist, const int32_t* idx, const float* i_meas, void* ws, double* loss, float* g_a,
+                          float* g_b, float* g_probe, float* g_shift, double* g_dist, float* intensity,
+                          bool with_loss) {
+#define ADORYM_RUN_NF(N_, L_, K_)                                                                                    \
+  return run_nf<N_, L_, K_>(ctx, g, a, b, probe, corner, shift, batch, kind, dist, n_dist, idx, i_meas, ws, loss, g_a, \
+                            g_b, g_probe, g_shift, g_dist, intensity, with_loss)
+  switch (g->n) {
+    case 64: ADORYM_RUN_NF(64, 4, 1);
+    case 96: ADORYM_RUN_NF(96, 8, 1);
+    case 128: ADORYM_RUN_NF(128, 8, 4);
+    case 192: ADORYM_RUN_NF(192, 8, 6);
+  }
+#undef ADORYM_RUN_NF
   return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size");
 }
 
@@ -337,6 +360,53 @@ adorym_status adorym_loss_grad_gaps(adorym_ctx* ctx, const adorym_geom* g, const
                        g_probe, g_shift, g_gaps, intensity, true);
 }
 
+// ---- Near field --------------------------------------------------------------
+size_t adorym_nearfield_workspace_size(const adorym_geom* g, int32_t batch, int32_t n_dist) {
+  if (!g || batch < 1 || g->n < 1 || g->n_slices < 1 || g->ckpt_every < 1 || n_dist < 1) return 0;
+  return nf_layout(g, batch, n_dist).total;
+}
+
+static adorym_status check_nf(adorym_ctx* ctx, const adorym_geom* g, int batch, int kind, const double* dist,
+                              int n_dist, const int32_t* idx, size_t ws_bytes) {
+  if (kind != ADORYM_PROP_PARAXIAL && kind != ADORYM_PROP_SOMMERFELD)
+    return set_err(ctx, ADORYM_EINVAL, "unknown near-field kernel");
+  if (n_dist < 1 || !dist || !idx) return set_err(ctx, ADORYM_EINVAL, "distances and their indices are required");
+  if (ws_bytes < adorym_nearfield_workspace_size(g, batch, n_dist))
+    return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
+  return ADORYM_OK;
+}
+
+adorym_status adorym_forward_nearfield(adorym_ctx* ctx, const adorym_geom* g, const float* obj_a, const float* obj_b,
+                                       const float* probe, const int32_t* corner, const float* shift, int32_t batch,
+                                       int32_t kind, const double* dist, int32_t n_dist, const int32_t* dist_idx,
+                                       float* intensity, void* workspace, size_t ws_bytes) {
+  adorym_status st = check_geom(ctx, g, batch);
+  if (st != ADORYM_OK) return st;
+  if (!obj_a || !obj_b || !probe || !corner || !shift || !intensity || !workspace)
+    return set_err(ctx, ADORYM_EINVAL, "NULL array argument");
+  st = check_nf(ctx, g, batch, kind, dist, n_dist, dist_idx, ws_bytes);
+  if (st != ADORYM_OK) return st;
+  return dispatch_nf(ctx, g, obj_a, obj_b, probe, corner, shift, batch, kind, dist, n_dist, dist_idx, nullptr,
+                     workspace, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, intensity, false);
+}
+
+adorym_status adorym_loss_grad_nearfield(adorym_ctx* ctx, const adorym_geom* g, const float* obj_a,
+                                         const float* obj_b, const float* probe, const int32_t* corner,
+                                         const float* shift, int32_t batch, int32_t kind, const double* dist,
+                                         int32_t n_dist, const int32_t* dist_idx, const float* i_meas,
+                                         void* workspace, size_t ws_bytes, double* loss, float* g_a, float* g_b,
+                                         float* g_probe, float* g_shift, double* g_dist, float* intensity) {
+  adorym_status st = check_geom(ctx, g, batch);
+  if (st != ADORYM_OK) return st;
+  if (!obj_a || !obj_b || !probe || !corner || !shift || !i_meas || !workspace || !loss)
+    return set_err(ctx, ADORYM_EINVAL, "NULL array argument");
+  if ((g_a == nullptr) != (g_b == nullptr)) return set_err(ctx, ADORYM_EINVAL, "g_a and g_b must both be given");
+  st = check_nf(ctx, g, batch, kind, dist, n_dist, dist_idx, ws_bytes);
+  if (st != ADORYM_OK) return st;
+  return dispatch_nf(ctx, g, obj_a, obj_b, probe, corner, shift, batch, kind, dist, n_dist, dist_idx, i_meas,
+                     workspace, loss, g_a, g_b, g_probe, g_shift, g_dist, intensity, true);
+}
+
 // ---- Several incoherent probe modes --------------------------------------
 size_t adorym_modes_workspace_size(const adorym_geom* g, int32_t batch, int32_t n_modes) {
   const size_t one = adorym_workspace_size(g, batch);
@@ -402,6 +472,7 @@ adorym_status adorym_sync_error(adorym_ctx* ctx) {
     return set_err(ctx, ADORYM_EDEVICE, "reading the error flag failed");
   if (hipMemset(ctx->d_err, 0, sizeof(int)) != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, "clearing failed");
   if (flag & 2) return set_err(ctx, ADORYM_EDEVICE, "a workgroup group barrier timed out (groups not co-resident)");
+  if (flag & 4) return set_err(ctx, ADORYM_EINVAL, "a distance index was outside the distance list; those positions contributed nothing");
   if (flag & 1) return set_err(ctx, ADORYM_ERANGE, "a chunk left the object; those positions contributed nothing");
   return ADORYM_OK;
 }

@@ -64,6 +64,12 @@ struct MsParams {
   int* xcc;                // [B][K] XCD ids of each group's members (K > 1)
   int* err;
   const double* gaps;      // [S-1] distance from slice j to j+1 (m): unequal spacing, or null
+  const float2* nf_h;      // near field: [n_dist][N][N] transfer functions to the detector
+  const float* nf_dph;     // near field: [N][N] d(phase of H)/d(distance), rad/m
+  const int32_t* nf_idx;   // near field: [B] distance index of each position
+  float2* nf_spec;         // near field: [B][K][R*THREADS] the detector spectrum H F phi (loss)
+  double* nd_part;         // near field: [B][K] distance-gradient partials
+  int n_dist;
   double* gd_part;         // [B][K][S-1] gap-gradient partials (unequal spacing)
   double chirp_per_m;      // lambda / dx^2: the Fresnel phase / pi of gap d is chirp_per_m d f^2
   int B, S, Ly, Lx, ckpt_every, nslots;
@@ -76,6 +82,7 @@ struct MsParams {
 };
 
 constexpr int kErrChunkRange = 1;   // error bit: a chunk left the object
+constexpr int kErrDistIndex = 4;    // error bit: a distance index outside [0, n_dist)
 
 __device__ __forceinline__ bool is_ckpt(int j, int S, int C) { return (j % C == 0) || (j == S - 1); }
 __device__ __forceinline__ int ckpt_slot(int j, int S, int C) {
@@ -540,7 +547,46 @@ __device__ __forceinline__ void group_of_block(int& b, int& part) {
 
 // Everything one workgroup does for its part of one position.  wk.b, wk.part
 // and the exchange state wk.x are set by the caller.
-template <class C, int REPR, bool LOSS, bool VAR = false>
+// Near field: the 2D transfer function to the detector between a DFT and
+// an inverse DFT over both axes.  In : the wave in the layout of slice S-1,
+// natural order.  Out: the propagated wave in the same layout, natural
+// order, times N^2 (unnormalised transforms).  CONJ applies conj(H) (the
+// adjoint); `stash`, if given, receives H F v (thread-native order) and,
+// with `dz`, the distance-gradient term sum dph Im((F v) conj(stash)) is
+// accumulated into *dz.
+template <class C, bool CONJ>
+__device__ __forceinline__ void nearfield_prop(float2 (&v)[C::R], const float2* __restrict__ h,
+                                               const float* __restrict__ dph, MsShared<C>& sh, Work<C>& wk,
+                                               float2* stash_out, const float2* stash_in, float* dz) {
+  const Lane<C>& ln = wk.ln;
+  constexpr int N = C::N;
+  fft_line<C, -1>(v, sh.tb, ln);
+  xfer<C>(v, sh, wk, true, false);
+  fft_line<C, -1>(v, sh.tb, ln);
+  // element m: line = one axis's frequency (natural index), pos_spec(m) = the other's;
+  // H depends on |nu|^2 only, so its table is symmetric
+  float acc = 0.f;
+  float2 st[C::R];
+  if (stash_in) {
+    const rsrc_t r = make_rsrc(stash_in, C::R * C::THREADS * 8);
+#pragma unroll
+    for (int m = 0; m < C::R; ++m) st[m] = bload2(r, ln.tid * 8, m * C::THREADS * 8);
+  }
+#pragma unroll
+  for (int m = 0; m < C::R; ++m) {
+    const int idx = ln.line * N + ln.pos_spec(m);
+    if (stash_in) acc = fmaf(dph[idx], cmulc(v[m], st[m]).y, acc);
+    const float2 hv = h[idx];
+    v[m] = CONJ ? cmulc(v[m], hv) : cmul(v[m], hv);
+  }
+  if (dz) *dz = acc;
+  if (stash_out) field_store<C>(v, stash_out, ln);
+  ifft_line<C, +1>(v, sh.tb, ln);
+  xfer<C>(v, sh, wk, false, true);
+  ifft_line<C, +1>(v, sh.tb, ln);
+}
+
+template <class C, int REPR, bool LOSS, bool VAR = false, bool NF = false>
 __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>& sh, Work<C>& wk) {
   const int b = wk.b, part = wk.part;
   const Lane<C>& ln = wk.ln;
@@ -550,9 +596,12 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
   wk.cx = P.corner[2 * b + 1];
   const float sy = P.shift[2 * b], sx = P.shift[2 * b + 1];
 
-  // TakeObjectChunk: the chunk must lie inside the object.
-  if (wk.cy < 0 || wk.cx < 0 || wk.cy + N > P.Ly || wk.cx + N > P.Lx) {
-    if (threadIdx.x == 0 && part == 0) atomicOr(P.err, kErrChunkRange);
+  // TakeObjectChunk: the chunk must lie inside the object (and a near-field
+  // position's distance index inside the distance list).
+  const int didx = NF ? P.nf_idx[b] : 0;
+  const bool bad_dist = NF && (didx < 0 || didx >= P.n_dist);
+  if (wk.cy < 0 || wk.cx < 0 || wk.cy + N > P.Ly || wk.cx + N > P.Lx || bad_dist) {
+    if (threadIdx.x == 0 && part == 0) atomicOr(P.err, bad_dist ? kErrDistIndex : kErrChunkRange);
     if (LOSS) {
       if (threadIdx.x == 0) {
         P.loss_part[b * C::K + part] = 0.0;
@@ -565,6 +614,7 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
       if (VAR)
         for (int i = threadIdx.x; i < P.S - 1; i += C::THREADS)
           P.gd_part[((size_t)b * C::K + part) * (P.S - 1) + i] = 0.0;
+      if (NF && threadIdx.x == 0) P.nd_part[b * C::K + part] = 0.0;
     }
     if (P.intensity)
       for (int i = part * C::THREADS + threadIdx.x; i < NN; i += C::K * C::THREADS)
@@ -601,12 +651,20 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
   }
   const bool last_row = ((P.S - 1) & 1) == 0;
 
-  // FarFieldPropagate: inverse DFT along the current lines, transpose, along
-  // the other axis.  Result: spectral along the lines of the final layout.
-  fft_line<C, +1>(v, sh.tb, ln);
-  xfer<C>(v, sh, wk, true, false);
-  fft_line<C, +1>(v, sh.tb, ln);
-  const float inv_nf = 1.0f / float(N);
+  float2* nf_slot = nullptr;
+  if constexpr (NF) {
+    // Fresnel propagation to the detector: natural order in the layout of slice S-1
+    nf_slot = P.nf_spec + ((size_t)b * C::K + part) * (C::R * C::THREADS);
+    nearfield_prop<C, false>(v, P.nf_h + (size_t)didx * NN, P.nf_dph, sh, wk, LOSS ? nf_slot : nullptr, nullptr,
+                             nullptr);
+  } else {
+    // FarFieldPropagate: inverse DFT along the current lines, transpose, along
+    // the other axis.  Result: spectral along the lines of the final layout.
+    fft_line<C, +1>(v, sh.tb, ln);
+    xfer<C>(v, sh, wk, true, false);
+    fft_line<C, +1>(v, sh.tb, ln);
+  }
+  const float inv_nf = NF ? 1.0f / float(NN) : 1.0f / float(N);
 
   // Per-pixel loss terms in FP32; the sum over pixels is accumulated in FP64.
   double lsum = 0.0;
@@ -618,9 +676,17 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
     int ky, kx;
-    if (last_row) { ky = ln.pos_spec(m); kx = ln.line; }    // final layout COL
-    else          { ky = ln.line; kx = ln.pos_spec(m); }    // final layout ROW
-    const uint32_t det = (uint32_t)(((ky + N / 2) % N) * N + (kx + N / 2) % N) * 4;
+    uint32_t det;
+    if constexpr (NF) {
+      // natural order in the layout of slice S-1: ROW when S-1 is even
+      if (last_row) { ky = ln.line; kx = ln.pos_nat(m); }
+      else          { ky = ln.pos_nat(m); kx = ln.line; }
+      det = (uint32_t)(ky * N + kx) * 4;
+    } else {
+      if (last_row) { ky = ln.pos_spec(m); kx = ln.line; }    // final layout COL
+      else          { ky = ln.line; kx = ln.pos_spec(m); }    // final layout ROW
+      det = (uint32_t)(((ky + N / 2) % N) * N + (kx + N / 2) % N) * 4;
+    }
     const float2 psi_det = cscale(v[m], inv_nf);
     const float ip = psi_det.x * psi_det.x + psi_det.y * psi_det.y;
     if (P.intensity) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, ip), rint, det, 0, 0);
@@ -651,10 +717,19 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
     if (threadIdx.x == 0) P.loss_part[b * C::K + part] = tot * P.inv_n;   // mean over the B N^2 pixels
   }
 
-  // Adjoint of the far field: DFT back along the two axes.
-  ifft_line<C, -1>(v, sh.tb, ln);
-  xfer<C>(v, sh, wk, false, true);
-  ifft_line<C, -1>(v, sh.tb, ln);
+  if constexpr (NF) {
+    // Adjoint of the detector propagation (conj(H)), and the distance
+    // gradient from the stashed spectrum
+    float dz = 0.f;
+    nearfield_prop<C, true>(v, P.nf_h + (size_t)didx * NN, P.nf_dph, sh, wk, nullptr, nf_slot, &dz);
+    const double tz = block_sum<C::THREADS>((double)dz, sh.red);
+    if (threadIdx.x == 0) P.nd_part[b * C::K + part] = tz;
+  } else {
+    // Adjoint of the far field: DFT back along the two axes.
+    ifft_line<C, -1>(v, sh.tb, ln);
+    xfer<C>(v, sh, wk, false, true);
+    ifft_line<C, -1>(v, sh.tb, ln);
+  }
   // v = lambda_{S-1} in the layout of slice S-1
 
   float2 psi[C::R];
@@ -716,7 +791,7 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
 }
 
 // One group of K workgroups per position of a single job.
-template <class C, int REPR, bool LOSS, bool VAR = false>
+template <class C, int REPR, bool LOSS, bool VAR = false, bool NF = false>
 __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
   __shared__ MsShared<C> sh;
   int b, part;
@@ -731,7 +806,7 @@ __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
   const int cy = P.corner[2 * b], cx = P.corner[2 * b + 1];
   const bool inside = cy >= 0 && cx >= 0 && cy + C::N <= P.Ly && cx + C::N <= P.Lx;
   if (C::K > 1 && inside) exchange_init<C::K>(wk.x, P.xcc + b * C::K, part);
-  process_position<C, REPR, LOSS, VAR>(P, sh, wk);
+  process_position<C, REPR, LOSS, VAR, NF>(P, sh, wk);
 }
 
 // Persistent multi-job kernel: groups of K workgroups take (job, position)
@@ -1044,14 +1119,14 @@ inline adorym_status check_geom(adorym_ctx* ctx, const adorym_geom* g, int batch
 }
 
 
-template <class C, bool LOSS, bool VAR = false>
+template <class C, bool LOSS, bool VAR = false, bool NF = false>
 void launch_ms(const MsParams& P, int repr, hipStream_t st) {
   // XCD-aware grid: ceil(B/8) groups per XCD, K slots per group
   const dim3 grid(((P.B + 7) / 8) * 8 * C::K), block(C::THREADS);
   if (repr == ADORYM_OBJ_DELTA_BETA)
-    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, LOSS, VAR>), grid, block, 0, st, P);
+    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, LOSS, VAR, NF>), grid, block, 0, st, P);
   else
-    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, LOSS, VAR>), grid, block, 0, st, P);
+    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, LOSS, VAR, NF>), grid, block, 0, st, P);
 }
 
 // Kernel parameters of one job; `ws` is its workspace (adorym_workspace_size).
@@ -1215,6 +1290,110 @@ adorym_status run_gaps(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
   return ADORYM_OK;
 }
 
+// ---- Near field (Fresnel propagation to the detector) ----------------------
+// Transfer functions to the detector and d(phase)/d(distance), in FP64:
+// paraxial H1 = exp(i pi lambda d |nu|^2); Sommerfeld H2 without its global
+// phase exp(-i k d) (it does not change an intensity), i.e.
+// exp(i k d x / (sqrt(1 - x) + 1)), x = lambda^2 |nu|^2 < 1, and 0 for the
+// evanescent x >= 1.  The phase is reduced modulo 2 pi in FP64.
+static __global__ void nf_table_kernel(int n, double lambda, double dx, int kind, const double* __restrict__ dist,
+                                       int n_dist, float2* __restrict__ h, float* __restrict__ dph) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * n) return;
+  const int ka = i / n, kb = i % n;
+  const double fa = double(ka < (n + 1) / 2 ? ka : ka - n) / (n * dx);
+  const double fb = double(kb < (n + 1) / 2 ? kb : kb - n) / (n * dx);
+  const double nu2 = fa * fa + fb * fb;
+  double g = 0.0;                 // phase per metre of distance
+  bool pass = true;
+  if (kind == ADORYM_PROP_PARAXIAL) {
+    g = M_PI * lambda * nu2;
+  } else {
+    const double x = lambda * lambda * nu2;
+    if (x >= 1.0) pass = false;
+    else g = (2.0 * M_PI / lambda) * x / (sqrt(1.0 - x) + 1.0);
+  }
+  dph[i] = (float)g;
+  for (int d = 0; d < n_dist; ++d) {
+    double sn, cs;
+    sincos(fmod(g * dist[d], 2.0 * M_PI), &sn, &cs);
+    h[(size_t)d * n * n + i] = pass ? make_float2((float)cs, (float)sn) : make_float2(0.f, 0.f);
+  }
+}
+
+// dL/d(distance d) = sum of the partials of the positions with index d, in
+// position order (one workgroup per distance).
+static __global__ void __launch_bounds__(256) dist_reduce_kernel(const double* __restrict__ part,
+                                                                 const int32_t* __restrict__ idx, int nb, int k,
+                                                                 double* __restrict__ g_dist, int accumulate) {
+  __shared__ double red[256];
+  const int d = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256)
+    if (idx[b] == d)
+      for (int p = 0; p < k; ++p) s += part[b * k + p];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) g_dist[d] = accumulate ? g_dist[d] + red[0] : red[0];
+}
+
+// Workspace of the near-field calls: that of the far-field call, then the
+// distance partials, the detector spectra, the transfer functions and the
+// phase derivative.
+struct NfLayout { size_t part, spec, h, dph, total; };
+inline NfLayout nf_layout(const adorym_geom* g, int batch, int n_dist) {
+  NfLayout l{};
+  const size_t nn = (size_t)g->n * g->n;
+  size_t off = ws_layout(g, batch).total;
+  l.part = off; off += align256((size_t)batch * kMaxSplit * sizeof(double));
+  l.spec = off; off += align256((size_t)batch * nn * sizeof(float2));
+  l.h = off; off += align256((size_t)n_dist * nn * sizeof(float2));
+  l.dph = off; off += align256(nn * sizeof(float));
+  l.total = off;
+  return l;
+}
+
+template <int N, int L, int K>
+adorym_status run_nf(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b, const float* probe,
+                     const int32_t* corner, const float* shift, int batch, int kind, const double* dist, int n_dist,
+                     const int32_t* dist_idx, const float* i_meas, void* ws, double* loss, float* g_a, float* g_b,
+                     float* g_probe, float* g_shift, double* g_dist, float* intensity, bool with_loss) {
+  using C = TileCfg<N, L, K>;
+  MsParams P = make_params<N, L>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
+                                    with_loss ? g_a : nullptr, with_loss ? g_b : nullptr, intensity);
+  P.ksplit = K;
+  const NfLayout l = nf_layout(g, batch, n_dist);
+  char* base = static_cast<char*>(ws);
+  P.nd_part = reinterpret_cast<double*>(base + l.part);
+  P.nf_spec = reinterpret_cast<float2*>(base + l.spec);
+  P.nf_h = reinterpret_cast<const float2*>(base + l.h);
+  P.nf_dph = reinterpret_cast<const float*>(base + l.dph);
+  P.nf_idx = dist_idx;
+  P.n_dist = n_dist;
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(nf_table_kernel, dim3((N * N + 255) / 256), dim3(256), 0, st, N, g->wavelength_m, g->pixel_m,
+                     kind, dist, n_dist, reinterpret_cast<float2*>(base + l.h), reinterpret_cast<float*>(base + l.dph));
+  const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
+  launch_prologue<N, L>(P, probe, g, st);
+  if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
+  if (with_loss) launch_ms<C, true, false, true>(P, g->obj_repr, st);
+  else launch_ms<C, false, false, true>(P, g->obj_repr, st);
+  if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
+  if (with_loss) {
+    launch_epilogue<N, L>(P, ws, g, loss, g_probe, g_shift, st);
+    if (g_dist)
+      hipLaunchKernelGGL(dist_reduce_kernel, dim3(n_dist), dim3(256), 0, st, P.nd_part, dist_idx, P.B, K, g_dist,
+                         (g->flags & ADORYM_ACCUMULATE_GRADS) ? 1 : 0);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
+  return ADORYM_OK;
+}
+
 // The persistent multi-job kernel of one probe-size class (device tables
 // prepared by the plan).
 template <int N, int L, int K>
@@ -1245,6 +1424,11 @@ void launch_batched(const MsParams* jobs, const int2* items, int n_items, int* t
   adorym_ms::MsParams adorym_ms::make_params<N_, L_>(adorym_ctx*, const adorym_geom*, const float*, \
                                                         const float*, int, const int32_t*, const float*, \
                                                         const float*, void*, bool, float*, float*, float*)
+#define ADORYM_RUN_NF_SIGNATURE(N_, L_, K_) \
+  adorym_status adorym_ms::run_nf<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, const float*, \
+                                              const float*, const int32_t*, const float*, int, int, const double*, \
+                                              int, const int32_t*, const float*, void*, double*, float*, float*, \
+                                              float*, float*, double*, float*, bool)
 #define ADORYM_RUN_GAPS_SIGNATURE(N_, L_, K_) \
   adorym_status adorym_ms::run_gaps<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, const float*, \
                                                 const float*, const int32_t*, const float*, int, const double*, \

@@ -304,6 +304,35 @@ def sparse_multislice(seed: int = 6, n_pos: int = 1414) -> Scan:
                 eval_obj_a=z, eval_obj_b=z, gaps=gaps, eval_gaps=gaps * 1.05)
 
 
+def mdh_tiles(seed: int = 7, side: int = 512, n: int = 128, step: int = 96):
+    """Multi-distance holography as tiles: a 512 x 512 complex object, 1 um
+    pixels, 17.5 keV, holograms at 40, 60, 80 and 100 cm (the paper's
+    simulated MDH case, Sec. 3), cut into 25 overlapping 128 x 128 tiles
+    (step 96) under plane-wave illumination, each tile at every distance:
+    100 (tile, distance) positions per iteration.  Magnitude 0.6 - 1.0 and
+    phase -0.5 - 0.5 rad are independent smooth random fields (they stand in
+    for the paper's two test images); Poisson data at 100 photons per pixel.
+    Evaluated at the mean of the truth and a vacuum object.
+    Returns (scan, dists [4] metres, dist_idx [100] int32)."""
+    rng = np.random.default_rng(seed)
+    mag = smooth_random_field(rng, (1, side, side), 4.0, 0.0, 1.0)
+    mag = 0.6 + 0.4 * (mag - mag.min()) / (mag.max() - mag.min())
+    ph = smooth_random_field(rng, (1, side, side), 4.0, 0.0, 1.0)
+    ph = -0.5 + (ph - ph.min()) / (ph.max() - ph.min())
+    o = mag * np.exp(1j * ph)
+    dists = np.array([0.4, 0.6, 0.8, 1.0])
+    corners = raster(5, 5, 0.0, float(step))
+    pos = np.repeat(corners, len(dists), axis=0)
+    idx = np.tile(np.arange(len(dists), dtype=np.int32), len(corners))
+    probe = np.full((n, n), 10.0 + 0j)
+    ev = 0.5 * (o + 1.0)
+    sc = Scan(name="mdh_tiles_n128", n=n, obj_a=o.real.copy(), obj_b=o.imag.copy(), probe=probe, positions=pos,
+              wavelength_m=wavelength_from_energy(17500.0), pixel_m=1e-6, slice_dz_m=1e-6, obj_repr="real_imag",
+              loss="poisson", minibatch=len(pos), photons=100.0 * n * n,
+              eval_obj_a=ev.real.copy(), eval_obj_b=ev.imag.copy())
+    return sc, dists, idx
+
+
 def split_positions(pos: np.ndarray):
     """Integer corner floor(r + 0.5) and the residual subpixel shift r - c."""
     corner = np.floor(pos + 0.5)

@@ -72,11 +72,14 @@ def _loss(geom, ip, i_meas):
     return value, dldi
 
 
-def _reverse(geom, st, a, b, dldi):
+def _reverse(geom, st, a, b, dldi, lam0=None):
     n, s = geom.n, geom.n_slices
     corner, f, hs, kdz, t, e, pf = (st[k] for k in ("corner", "f", "hs", "kdz", "t", "e", "pf"))
     psis, phis, det = st["psis"], st["phis"], st["det"]
-    lam = sfft.fft2(np.fft.ifftshift((F32(2) * dldi * det).astype(C64), axes=(-2, -1)), norm="ortho")
+    if lam0 is None:
+        lam = sfft.fft2(np.fft.ifftshift((F32(2) * dldi * det).astype(C64), axes=(-2, -1)), norm="ortho")
+    else:
+        lam = lam0
     ga = np.zeros(a.shape, F32)
     gb = np.zeros(b.shape, F32)
     for j in range(s - 1, -1, -1):
@@ -136,3 +139,20 @@ def loss_grad_fp32_modes(geom, a, b, probes, pos, i_meas):
         ga, gb, gs = ga + a_, gb + b_, gs + s_
         gps.append(p_)
     return value, ga, gb, np.stack(gps), gs
+
+
+def loss_grad_fp32_nearfield(geom, a, b, p, pos, i_meas, dists, dist_idx, kind, hs_det, dlog):
+    """Near-field detector in float32: hs_det [n_dist] transfer functions
+    and dlog = d log H / d d from the FP64 oracle, rounded to complex64."""
+    st = _forward(geom, a, b, p, pos)
+    hb = np.stack([_c64(hs_det[i]) for i in np.asarray(dist_idx)])
+    exit_f = sfft.fft2(st["phis"][:, -1], norm="ortho")
+    psi = sfft.ifft2(exit_f * hb, norm="ortho")
+    value, dldi = _loss(geom, _intensity(psi), i_meas)
+    g = (F32(2) * dldi * psi).astype(C64)
+    g_f = sfft.fft2(g, norm="ortho")
+    per = np.sum(np.real(np.conj(g_f) * _c64(dlog) * hb * exit_f).astype(np.float64), axis=(1, 2))
+    g_dist = np.zeros(len(dists))
+    np.add.at(g_dist, np.asarray(dist_idx), per)
+    lam0 = sfft.ifft2(g_f * np.conj(hb), norm="ortho")
+    return (value,) + _reverse(geom, st, a, b, dldi, lam0=lam0) + (g_dist,)
