@@ -96,7 +96,7 @@ def main():
                     help="workgroups per position (0 = the library's automatic choice)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters)")
-    ap.add_argument("--workload", default="multislice", choices=["multislice", "batching", "serving", "sparse", "priors"],
+    ap.add_argument("--workload", default="multislice", choices=["multislice", "batching", "serving", "sparse", "priors", "mdh"],
                     help="multislice: the 64-slice minibatch (default line); batching: 32 mixed scans, "
                          "batched vs per-job; serving: the request loop")
     ap.add_argument("--ckpt", type=int, default=16, help="slice checkpoint interval of the adjoint")
@@ -130,6 +130,8 @@ def main():
         return bench_sparse(args)
     if args.workload == "priors":
         return bench_priors(args)
+    if args.workload == "mdh":
+        return bench_mdh(args)
 
     import synth
     from paper_2012_12686_amd import Context, Geometry, split_positions
@@ -334,6 +336,91 @@ def bench_sparse(args):
         dt = time.perf_counter() - t
         line["cpu_baseline"] = {"value": sample / dt, "unit": "positions/s", "cores": om._WORKERS, "kind": "oracle",
                                 "sample": f"FP64 oracle loss_grad_gaps on {sample} positions of the first minibatch"}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def bench_mdh(args):
+    """Multi-distance holography as near-field tiles: 25 tiles x 4 distances
+    of a 512 x 512 complex object per step (adorym_loss_grad_nearfield with
+    the distance gradient)."""
+    import torch
+
+    import synth
+    from paper_2012_12686_amd import Context, Geometry, split_positions
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    sc, dists, idx = synth.mdh_tiles()
+    n, s, b = sc.n, sc.n_slices, len(sc.positions)
+    ctx = Context(dev)
+    geom = Geometry.from_scan(sc, ckpt_every=args.ckpt)
+    to_t = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device=dev)
+    probe = to_t(sc.probe, torch.complex64)
+    corner, shift = split_positions(to_t(sc.positions, torch.float64))
+    td, ti = to_t(dists, torch.float64), to_t(idx, torch.int32)
+    i_true = ctx.forward_nearfield(geom, to_t(sc.obj_a, torch.float32), to_t(sc.obj_b, torch.float32), probe,
+                                   corner, shift, td, ti)
+    i_meas_np = np.random.default_rng(2).poisson(i_true.cpu().numpy().astype(np.float64)).astype(np.float32)
+    i_meas = to_t(i_meas_np, torch.float32)
+    a, b_ = to_t(sc.eval_obj_a, torch.float32), to_t(sc.eval_obj_b, torch.float32)
+    ev = td * 1.02
+    ws = torch.empty(ctx.nearfield_workspace_size(geom, b, len(dists)), dtype=torch.uint8, device=dev)
+    out = {"loss": torch.empty((), dtype=torch.float64, device=dev), "g_a": torch.empty_like(a),
+           "g_b": torch.empty_like(b_), "g_probe": torch.empty_like(probe),
+           "g_shift": torch.empty((b, 2), dtype=torch.float32, device=dev),
+           "g_dist": torch.empty((len(dists),), dtype=torch.float64, device=dev)}
+
+    def step():
+        ctx.loss_grad_nearfield(geom, a, b_, probe, corner, shift, ev, ti, i_meas, out=out, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.sync_error()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ctx.profile_start(args.steps + 8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record()
+        step()
+        ends[k].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_ms, kern_n = ctx.profile_stop()
+    ctx.sync_error()
+    lat = sorted(st.elapsed_time(en) for st, en in zip(starts, ends))
+    kern_avg_s = kern_ms / max(kern_n, 1) / 1e3
+    # per position: the far-field model's bytes plus the detector spectrum stashed and reread
+    bytes_launch = (algorithmic_bytes_per_position(n, s, args.ckpt) + 16 * n * n) * b
+    achieved = bytes_launch / kern_avg_s / 1e9
+    line = {
+        "metric": "near-field (multi-distance holography tiles) fwd+adjoint positions/s, % HBM roofline",
+        "value": b * args.steps / elapsed, "unit": "positions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "multi-distance holography: 512x512 complex object, 1 um, 17.5 keV, 25 tiles of "
+                               "128x128 at 4 distances (0.4-1.0 m), plane wave, Poisson, paraxial near field, "
+                               "fwd+loss+adjoint+distance gradient", "global_batch": b, "seq_len": s,
+                   "parallelism": "none"},
+        "p50_iter_ms": float(np.percentile(lat, 50)), "p99_iter_ms": float(np.percentile(lat, 99)),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "multislice_kernel<N=128, real/imag, Poisson, loss+adjoint, near field>",
+                     "kernel_avg_ms": kern_avg_s * 1e3, "kernel_launches": kern_n,
+                     "algorithmic_bytes_per_launch": bytes_launch},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import multislice as om
+        og = om.Geometry.from_scan(sc)
+        t = time.perf_counter()
+        om.loss_grad_nearfield(og, sc.eval_obj_a, sc.eval_obj_b, sc.probe, sc.positions,
+                               i_meas_np.astype(np.float64), dists * 1.02, idx)
+        dt = time.perf_counter() - t
+        line["cpu_baseline"] = {"value": b / dt, "unit": "positions/s", "cores": om._WORKERS, "kind": "oracle",
+                                "sample": f"FP64 oracle loss_grad_nearfield on the whole 100-position step, {dt:.1f} s"}
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -11,12 +11,12 @@
 // (W = 1 unless weights are given).  d|t|/dt at t = 0 is taken as 0.
 //
 // The gradient kernel is one pass over the object, HBM-bound: every
-// workgroup owns a 64 x 4 column tile and a run of kZc = 32 slices (a
-// sweep of tile heights and run lengths on the 512 x 512 x 128 object:
-// taller tiles lose more to fewer workgroups than they save in halo reads) and marches
-// along z; each slice's tile with a one-voxel halo is staged in LDS as the
-// two quantities, so x/y neighbours come from LDS and z neighbours from the
-// previous step's registers.  The derivative of a voxel is final once the
+// workgroup owns a 64 x 4 column tile and a run of kZc = 32 slices and
+// marches along z (on the 512 x 512 x 128 object, taller tiles lost more to
+// the smaller grid than they saved in halo reads); each slice's tile with a
+// one-voxel halo is staged in LDS as the two quantities, so x/y neighbours
+// come from LDS and z neighbours from the previous step's registers, and
+// the next slice's halo is loaded while the current one is processed.  The derivative of a voxel is final once the
 // pair with the next slice is known, so each thread writes voxel z-1 while
 // it handles slice z; the slices just outside a run are read for the pairs
 // that cross its ends (each pair's value is counted by the run holding its
