@@ -209,10 +209,11 @@ def main():
     kern_avg_s = kern_ms / max(kern_n, 1) / 1e3
     bytes_launch = algorithmic_bytes_per_position(n, s, args.ckpt) * mb
     if n_modes > 1:
-        # M forward launches (object read, intensity written) and M
-        # loss+adjoint launches (which also read the summed intensity)
-        fwd = 8 * n * n * s + 4 * n * n
-        bytes_launch = (fwd + algorithmic_bytes_per_position(n, s, args.ckpt) + 4 * n * n) * mb / 2
+        # per mode a forward launch (object read, checkpoints and exit wave
+        # written, intensity written) and a loss launch resuming from them
+        # (exit wave and summed intensity read besides the one-launch bytes)
+        per_mode = algorithmic_bytes_per_position(n, s, args.ckpt) + 24 * n * n
+        bytes_launch = per_mode * mb / 2
     achieved_gbs = bytes_launch / kern_avg_s / 1e9
     flops_launch = algorithmic_flops_per_position(n, s) * mb
     achieved_tflops = flops_launch / kern_avg_s / 1e12

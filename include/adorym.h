@@ -215,11 +215,15 @@ adorym_status adorym_loss_grad_nearfield(adorym_ctx* ctx, const adorym_geom* g,
  * probes: complex [M][N][N].  Outputs as adorym_loss_grad, except g_probe
  * complex [M][N][N] (one gradient per mode) and `intensity`, if given, the
  * summed intensity.  g_a, g_b and g_shift are sums over the modes.
- * Runs M forward passes (the summed intensity), then M loss-and-gradient
- * passes, all on the context's stream.  Workspace of
- * adorym_modes_workspace_size(g, batch, M) bytes: two intensity planes
- * [B][N][N] and one adorym_loss_grad workspace.  With M = 1 the results
- * equal those of adorym_loss_grad. */
+ * Runs M forward passes, each keeping its slice checkpoints and exit waves
+ * and adding its intensity into the sum, then M loss-and-gradient passes
+ * that resume from what their forward pass kept (no second forward sweep),
+ * all on the context's stream, with the fixed split of ADORYM_DETERMINISTIC
+ * (1 for N <= 96, 4 for N = 128, 6 for N = 192).  Workspace of
+ * adorym_modes_workspace_size(g, batch, M) bytes: one adorym_loss_grad
+ * workspace, two intensity planes [B][N][N] and per mode the checkpoints
+ * and exit waves.  With M = 1 the results equal, bit for bit, those of
+ * adorym_loss_grad with ADORYM_DETERMINISTIC. */
 size_t adorym_modes_workspace_size(const adorym_geom* g, int32_t batch, int32_t n_modes);
 adorym_status adorym_loss_grad_modes(adorym_ctx* ctx, const adorym_geom* g,
                                      const float* obj_a, const float* obj_b, const float* probes,

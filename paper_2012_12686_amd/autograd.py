@@ -56,3 +56,111 @@ def multislice_loss(obj_a: torch.Tensor, obj_b: torch.Tensor, probe: torch.Tenso
                     i_meas: torch.Tensor, geom: Geometry, ctx: Optional[Context] = None) -> torch.Tensor:
     """Differentiable loss of one minibatch; see the module docstring."""
     return MultisliceLoss.apply(obj_a, obj_b, probe, positions, i_meas, geom, ctx)
+
+
+def _scaled(fctx, grads, grad_out, needs):
+    s = grad_out.to(torch.float64)
+    out = []
+    for g, need in zip(grads, needs):
+        if g is None or not need:
+            out.append(None)
+        elif g.is_complex():
+            out.append(g * s.to(torch.float32).to(g.dtype))
+        else:
+            out.append((g * s.to(g.dtype)) if g.dtype == torch.float64 else g * s.to(torch.float32))
+    return out
+
+
+class MultisliceLossModes(torch.autograd.Function):
+    """Loss of several incoherent probe modes (Eq. multimode); gradients for
+    the object, the modes [M][N][N] and the positions."""
+
+    @staticmethod
+    def forward(fctx, obj_a, obj_b, probes, positions, i_meas, geom: Geometry, lib: Optional[Context]):
+        lib = lib or _context(obj_a.device)
+        corner, shift = split_positions(positions.detach())
+        out = lib.loss_grad_modes(geom, obj_a.detach().contiguous(), obj_b.detach().contiguous(),
+                                  probes.detach().contiguous(), corner, shift, i_meas.contiguous())
+        fctx.save_for_backward(out["g_a"], out["g_b"], out["g_probe"], out["g_shift"])
+        fctx.pos_dtype = positions.dtype
+        return out["loss"]
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        ga, gb, gp, gs = _scaled(fctx, fctx.saved_tensors, grad_out, fctx.needs_input_grad[:4])
+        return ga, gb, gp, (gs.to(fctx.pos_dtype) if gs is not None else None), None, None, None
+
+
+class MultisliceLossGaps(torch.autograd.Function):
+    """Sparse multislice loss; also differentiable in the S-1 gaps (float64)."""
+
+    @staticmethod
+    def forward(fctx, obj_a, obj_b, probe, positions, gaps, i_meas, geom: Geometry, lib: Optional[Context]):
+        lib = lib or _context(obj_a.device)
+        corner, shift = split_positions(positions.detach())
+        out = lib.loss_grad_gaps(geom, obj_a.detach().contiguous(), obj_b.detach().contiguous(),
+                                 probe.detach().contiguous(), corner, shift,
+                                 None if gaps is None else gaps.detach().contiguous(), i_meas.contiguous())
+        fctx.save_for_backward(out["g_a"], out["g_b"], out["g_probe"], out["g_shift"], out["g_gaps"])
+        fctx.pos_dtype = positions.dtype
+        return out["loss"]
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        ga, gb, gp, gs, gg = _scaled(fctx, fctx.saved_tensors, grad_out, fctx.needs_input_grad[:5])
+        return ga, gb, gp, (gs.to(fctx.pos_dtype) if gs is not None else None), gg, None, None, None
+
+
+class MultisliceLossNearfield(torch.autograd.Function):
+    """Near-field loss; also differentiable in the detector distances (float64)."""
+
+    @staticmethod
+    def forward(fctx, obj_a, obj_b, probe, positions, dists, dist_idx, i_meas, geom: Geometry, kind: str,
+                lib: Optional[Context]):
+        lib = lib or _context(obj_a.device)
+        corner, shift = split_positions(positions.detach())
+        out = lib.loss_grad_nearfield(geom, obj_a.detach().contiguous(), obj_b.detach().contiguous(),
+                                      probe.detach().contiguous(), corner, shift, dists.detach().contiguous(),
+                                      dist_idx.contiguous(), i_meas.contiguous(), kind=kind)
+        fctx.save_for_backward(out["g_a"], out["g_b"], out["g_probe"], out["g_shift"], out["g_dist"])
+        fctx.pos_dtype = positions.dtype
+        return out["loss"]
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        ga, gb, gp, gs, gd = _scaled(fctx, fctx.saved_tensors, grad_out, fctx.needs_input_grad[:5])
+        return ga, gb, gp, (gs.to(fctx.pos_dtype) if gs is not None else None), gd, None, None, None, None, None
+
+
+class ObjectPrior(torch.autograd.Function):
+    """l1 / reweighted l1 / total-variation prior of the object (Eq. tikhonov)."""
+
+    @staticmethod
+    def forward(fctx, obj_a, obj_b, obj_repr: str, l1_a: float, l1_b: float, tv: float, weights, lib):
+        lib = lib or _context(obj_a.device)
+        out = lib.prior_grad(obj_repr, obj_a.detach().contiguous(), obj_b.detach().contiguous(), l1_a=l1_a,
+                             l1_b=l1_b, tv=tv, weights=weights, accumulate=False)
+        fctx.save_for_backward(out["g_a"], out["g_b"])
+        return out["value"]
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        ga, gb = _scaled(fctx, fctx.saved_tensors, grad_out, fctx.needs_input_grad[:2])
+        return ga, gb, None, None, None, None, None, None
+
+
+def multislice_loss_modes(obj_a, obj_b, probes, positions, i_meas, geom, ctx=None):
+    return MultisliceLossModes.apply(obj_a, obj_b, probes, positions, i_meas, geom, ctx)
+
+
+def multislice_loss_gaps(obj_a, obj_b, probe, positions, gaps, i_meas, geom, ctx=None):
+    return MultisliceLossGaps.apply(obj_a, obj_b, probe, positions, gaps, i_meas, geom, ctx)
+
+
+def multislice_loss_nearfield(obj_a, obj_b, probe, positions, dists, dist_idx, i_meas, geom, kind="paraxial",
+                              ctx=None):
+    return MultisliceLossNearfield.apply(obj_a, obj_b, probe, positions, dists, dist_idx, i_meas, geom, kind, ctx)
+
+
+def object_prior(obj_a, obj_b, obj_repr="delta_beta", l1_a=0.0, l1_b=0.0, tv=0.0, weights=None, ctx=None):
+    return ObjectPrior.apply(obj_a, obj_b, obj_repr, l1_a, l1_b, tv, weights, ctx)

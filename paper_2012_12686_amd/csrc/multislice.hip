@@ -35,6 +35,10 @@ extern template ADORYM_RUN_SIGNATURE(96, 8, 3);
 extern template ADORYM_BATCHED_SIGNATURE(96, 8, 3);
 extern template ADORYM_RUN_SIGNATURE(192, 8, 8);
 extern template ADORYM_BATCHED_SIGNATURE(192, 8, 8);
+extern template ADORYM_RUN_SPLIT_SIGNATURE(64, 4, 1);
+extern template ADORYM_RUN_SPLIT_SIGNATURE(96, 8, 1);
+extern template ADORYM_RUN_SPLIT_SIGNATURE(128, 8, 4);
+extern template ADORYM_RUN_SPLIT_SIGNATURE(192, 8, 6);
 extern template ADORYM_RUN_NF_SIGNATURE(64, 4, 1);
 extern template ADORYM_RUN_NF_SIGNATURE(96, 8, 1);
 extern template ADORYM_RUN_NF_SIGNATURE(128, 8, 4);
@@ -408,11 +412,14 @@ adorym_status adorym_loss_grad_nearfield(adorym_ctx* ctx, const adorym_geom* g, 
 }
 
 // ---- Several incoherent probe modes --------------------------------------
+// Workspace: a loss-and-gradient workspace, the summed and one mode's
+// intensity, and per mode the checkpoints and the exit wave kept between
+// the forward pass and the loss pass.
 size_t adorym_modes_workspace_size(const adorym_geom* g, int32_t batch, int32_t n_modes) {
   const size_t one = adorym_workspace_size(g, batch);
   if (one == 0 || n_modes < 1) return 0;
   const size_t plane = align256((size_t)batch * g->n * g->n * sizeof(float));
-  return 2 * plane + one;
+  return one + 2 * plane + (size_t)n_modes * (split_ckpt_bytes(g, batch) + split_exit_bytes(g, batch));
 }
 
 adorym_status adorym_loss_grad_modes(adorym_ctx* ctx, const adorym_geom* g, const float* obj_a, const float* obj_b,
@@ -430,21 +437,41 @@ adorym_status adorym_loss_grad_modes(adorym_ctx* ctx, const adorym_geom* g, cons
     return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
   const size_t nn = (size_t)g->n * g->n, nb = (size_t)batch * nn;
   const size_t plane = align256(nb * sizeof(float));
-  float* i_tot = static_cast<float*>(workspace);
-  float* i_mode = reinterpret_cast<float*>(static_cast<char*>(workspace) + plane);
-  void* ws = static_cast<char*>(workspace) + 2 * plane;
+  char* base = static_cast<char*>(workspace);
+  void* ws = base;                                     // the loss-and-gradient workspace
+  char* rest = base + adorym_workspace_size(g, batch);
+  float* i_tot = reinterpret_cast<float*>(rest);
+  float* i_mode = reinterpret_cast<float*>(rest + plane);
+  char* per_mode = rest + 2 * plane;
+  const size_t ck = split_ckpt_bytes(g, batch), ex = split_exit_bytes(g, batch);
+  auto ckpt_of = [&](int m) { return reinterpret_cast<float2*>(per_mode + (size_t)m * (ck + ex)); };
+  auto exit_of = [&](int m) { return reinterpret_cast<float2*>(per_mode + (size_t)m * (ck + ex) + ck); };
   hipStream_t s = ctx->stream;
   const int blocks = (int)std::min<size_t>((nb + 255) / 256, 4096);
-  // 1. every mode's intensity, summed
+  // one fixed split per probe size, as the deterministic mode
+  auto pass = [&](const adorym_geom* gm, int m, bool with_loss, float* gp, float* inten) -> adorym_status {
+    const float* pm = probes + (size_t)m * 2 * nn;
+#define ADORYM_RUN_SPLIT(N_, L_, K_)                                                                               \
+  return run_split<N_, L_, K_>(ctx, gm, obj_a, obj_b, pm, corner, shift, batch, with_loss ? i_meas : nullptr, ws, \
+                               ckpt_of(m), exit_of(m), with_loss ? loss : nullptr, with_loss ? g_a : nullptr,      \
+                               with_loss ? g_b : nullptr, gp, with_loss ? g_shift : nullptr, inten, with_loss)
+    switch (g->n) {
+      case 64: ADORYM_RUN_SPLIT(64, 4, 1);
+      case 96: ADORYM_RUN_SPLIT(96, 8, 1);
+      case 128: ADORYM_RUN_SPLIT(128, 8, 4);
+      case 192: ADORYM_RUN_SPLIT(192, 8, 6);
+    }
+#undef ADORYM_RUN_SPLIT
+    return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size");
+  };
+  // 1. every mode's forward pass: intensities summed, checkpoints and exit waves kept
   for (int m = 0; m < n_modes; ++m) {
-    st = dispatch(ctx, g, obj_a, obj_b, probes + (size_t)m * 2 * nn, corner, shift, batch, nullptr, ws, nullptr,
-                  nullptr, nullptr, nullptr, nullptr, m == 0 ? i_tot : i_mode, false);
+    st = pass(g, m, false, nullptr, m == 0 ? i_tot : i_mode);
     if (st != ADORYM_OK) return st;
     if (m > 0) hipLaunchKernelGGL(add_into_kernel, dim3(blocks), dim3(256), 0, s, i_tot, i_mode, nb);
   }
-  // 2. every mode's reverse sweep from the loss at the summed intensity;
-  //    object and shift gradients add up over the modes, the probe gradient
-  //    is per mode
+  // 2. every mode's loss pass at the summed intensity; object and shift
+  //    gradients add up over the modes, the probe gradient is per mode
   adorym_geom gm = *g;
   ctx->i_total = i_tot;
   for (int m = 0; m < n_modes && st == ADORYM_OK; ++m) {
@@ -453,8 +480,7 @@ adorym_status adorym_loss_grad_modes(adorym_ctx* ctx, const adorym_geom* g, cons
     if (gp && m > 0 && !(g->flags & ADORYM_ACCUMULATE_GRADS))
       hipLaunchKernelGGL(zero_kernel, dim3((int)std::min<size_t>((2 * nn + 255) / 256, 4096)), dim3(256), 0, s,
                          gp, 2 * nn);
-    st = dispatch(ctx, &gm, obj_a, obj_b, probes + (size_t)m * 2 * nn, corner, shift, batch, i_meas, ws, loss, g_a,
-                  g_b, gp, g_shift, nullptr, true);
+    st = pass(&gm, m, true, gp, nullptr);
   }
   ctx->i_total = nullptr;
   if (st != ADORYM_OK) return st;

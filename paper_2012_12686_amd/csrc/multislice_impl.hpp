@@ -56,6 +56,7 @@ struct MsParams {
   float* gstage;           // [B][S][2][N][N] per-position object-gradient contributions,
                            // null when no object gradient is wanted
   float2* ckpt;            // [B][nslots][K][R*THREADS]
+  float2* exit_wave;       // [B][K][R*THREADS] phi_{S-1} between the passes of a split evaluation
   float2* gacc;            // [B][N][N] natural, or null (probe-gradient partials)
   double* loss_part;       // [B][K]
   double* gs_part;         // [B][K][2] shift-gradient partials
@@ -586,7 +587,11 @@ __device__ __forceinline__ void nearfield_prop(float2 (&v)[C::R], const float2* 
   ifft_line<C, +1>(v, sh.tb, ln);
 }
 
-template <class C, int REPR, bool LOSS, bool VAR = false, bool NF = false>
+// SPLIT: the evaluation in two launches (several probe modes, whose loss
+// needs every mode's intensity first).  The forward launch (LOSS false)
+// stores the checkpoints and the exit wave; the loss launch resumes from
+// them instead of repeating the forward sweep.
+template <class C, int REPR, bool LOSS, bool VAR = false, bool NF = false, bool SPLIT = false>
 __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>& sh, Work<C>& wk) {
   const int b = wk.b, part = wk.part;
   const Lane<C>& ln = wk.ln;
@@ -631,25 +636,40 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
   float ca[C::R], cb[C::R];
   float2 tr[C::R];
   float g2[C::R];
-  if constexpr (C::PREFETCH) {
-    load_chunk<C, true>(ca, cb, P, o, 0);
-#pragma unroll
-    for (int m = 0; m < C::R; ++m) g2[m] = 1.0f;   // slice S-1 is always anchored: no inverse needed
-    make_trans<C, REPR, false>(tr, g2, ca, cb, P.kdz);
-  }
-  place_probe<C>(v, P, sh, wk);
-
-  // MultislicePropagate: even slices in ROW layout, odd slices in COL layout.
-  for (int j = 0; j < P.S; j += 2) {
-    if constexpr (C::PREFETCH) {
-      forward_slice_pf<C, REPR, true, LOSS, VAR>(v, tr, g2, P, sh, wk, o, j);
-      if (j + 1 < P.S) forward_slice_pf<C, REPR, false, LOSS, VAR>(v, tr, g2, P, sh, wk, o, j + 1);
-    } else {
-      forward_slice<C, REPR, true, LOSS, VAR>(v, ca, cb, P, sh, wk, o, j);
-      if (j + 1 < P.S) forward_slice<C, REPR, false, LOSS, VAR>(v, ca, cb, P, sh, wk, o, j + 1);
-    }
-  }
   const bool last_row = ((P.S - 1) & 1) == 0;
+  float2* const exit_slot = SPLIT ? P.exit_wave + ((size_t)b * C::K + part) * (C::R * C::THREADS) : nullptr;
+  constexpr bool CKPT = LOSS || SPLIT;
+  if constexpr (SPLIT && LOSS) {
+    // resume: the exit wave and the checkpoints of this position are stored
+    field_load<C>(v, exit_slot, ln);
+    if constexpr (C::PREFETCH) {
+#pragma unroll
+      for (int m = 0; m < C::R; ++m) g2[m] = 1.0f;
+      if (last_row) load_chunk<C, true>(ca, cb, P, o, P.S - 1);
+      else load_chunk<C, false>(ca, cb, P, o, P.S - 1);
+      make_trans<C, REPR, false>(tr, g2, ca, cb, P.kdz);
+    }
+  } else {
+    if constexpr (C::PREFETCH) {
+      load_chunk<C, true>(ca, cb, P, o, 0);
+#pragma unroll
+      for (int m = 0; m < C::R; ++m) g2[m] = 1.0f;   // slice S-1 is always anchored: no inverse needed
+      make_trans<C, REPR, false>(tr, g2, ca, cb, P.kdz);
+    }
+    place_probe<C>(v, P, sh, wk);
+
+    // MultislicePropagate: even slices in ROW layout, odd slices in COL layout.
+    for (int j = 0; j < P.S; j += 2) {
+      if constexpr (C::PREFETCH) {
+        forward_slice_pf<C, REPR, true, CKPT, VAR>(v, tr, g2, P, sh, wk, o, j);
+        if (j + 1 < P.S) forward_slice_pf<C, REPR, false, CKPT, VAR>(v, tr, g2, P, sh, wk, o, j + 1);
+      } else {
+        forward_slice<C, REPR, true, CKPT, VAR>(v, ca, cb, P, sh, wk, o, j);
+        if (j + 1 < P.S) forward_slice<C, REPR, false, CKPT, VAR>(v, ca, cb, P, sh, wk, o, j + 1);
+      }
+    }
+    if constexpr (SPLIT) field_store<C>(v, exit_slot, ln);
+  }
 
   float2* nf_slot = nullptr;
   if constexpr (NF) {
@@ -791,7 +811,7 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
 }
 
 // One group of K workgroups per position of a single job.
-template <class C, int REPR, bool LOSS, bool VAR = false, bool NF = false>
+template <class C, int REPR, bool LOSS, bool VAR = false, bool NF = false, bool SPLIT = false>
 __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
   __shared__ MsShared<C> sh;
   int b, part;
@@ -806,7 +826,7 @@ __global__ void __launch_bounds__(C::THREADS) multislice_kernel(MsParams P) {
   const int cy = P.corner[2 * b], cx = P.corner[2 * b + 1];
   const bool inside = cy >= 0 && cx >= 0 && cy + C::N <= P.Ly && cx + C::N <= P.Lx;
   if (C::K > 1 && inside) exchange_init<C::K>(wk.x, P.xcc + b * C::K, part);
-  process_position<C, REPR, LOSS, VAR, NF>(P, sh, wk);
+  process_position<C, REPR, LOSS, VAR, NF, SPLIT>(P, sh, wk);
 }
 
 // Persistent multi-job kernel: groups of K workgroups take (job, position)
@@ -1119,14 +1139,14 @@ inline adorym_status check_geom(adorym_ctx* ctx, const adorym_geom* g, int batch
 }
 
 
-template <class C, bool LOSS, bool VAR = false, bool NF = false>
+template <class C, bool LOSS, bool VAR = false, bool NF = false, bool SPLIT = false>
 void launch_ms(const MsParams& P, int repr, hipStream_t st) {
   // XCD-aware grid: ceil(B/8) groups per XCD, K slots per group
   const dim3 grid(((P.B + 7) / 8) * 8 * C::K), block(C::THREADS);
   if (repr == ADORYM_OBJ_DELTA_BETA)
-    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, LOSS, VAR, NF>), grid, block, 0, st, P);
+    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_DELTA_BETA, LOSS, VAR, NF, SPLIT>), grid, block, 0, st, P);
   else
-    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, LOSS, VAR, NF>), grid, block, 0, st, P);
+    hipLaunchKernelGGL((multislice_kernel<C, ADORYM_OBJ_REAL_IMAG, LOSS, VAR, NF, SPLIT>), grid, block, 0, st, P);
 }
 
 // Kernel parameters of one job; `ws` is its workspace (adorym_workspace_size).
@@ -1394,6 +1414,43 @@ adorym_status run_nf(adorym_ctx* ctx, const adorym_geom* g, const float* a, cons
   return ADORYM_OK;
 }
 
+// ---- Split evaluation (several probe modes) ------------------------------
+// Per-mode storage between the passes: the checkpoints and the exit wave.
+inline size_t split_ckpt_bytes(const adorym_geom* g, int batch) {
+  const WsLayout w = ws_layout(g, batch);
+  return align256((size_t)batch * w.nslots * g->n * g->n * sizeof(float2));
+}
+inline size_t split_exit_bytes(const adorym_geom* g, int batch) {
+  return align256((size_t)batch * g->n * g->n * sizeof(float2));
+}
+
+// One pass of a split evaluation: the forward pass (with_loss false: stores
+// checkpoints and the exit wave, writes the intensity) or the loss pass
+// (resumes from them).  `ws` is a loss-and-gradient workspace.
+template <int N, int L, int K>
+adorym_status run_split(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b, const float* probe,
+                        const int32_t* corner, const float* shift, int batch, const float* i_meas, void* ws,
+                        float2* ckpt, float2* exit_wave, double* loss, float* g_a, float* g_b, float* g_probe,
+                        float* g_shift, float* intensity, bool with_loss) {
+  using C = TileCfg<N, L, K>;
+  MsParams P = make_params<N, L>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
+                                    with_loss ? g_a : nullptr, with_loss ? g_b : nullptr, intensity);
+  P.ksplit = K;
+  P.ckpt = ckpt;
+  P.exit_wave = exit_wave;
+  hipStream_t st = ctx->stream;
+  const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
+  launch_prologue<N, L>(P, probe, g, st);
+  if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
+  if (with_loss) launch_ms<C, true, false, false, true>(P, g->obj_repr, st);
+  else launch_ms<C, false, false, false, true>(P, g->obj_repr, st);
+  if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
+  if (with_loss) launch_epilogue<N, L>(P, ws, g, loss, g_probe, g_shift, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
+  return ADORYM_OK;
+}
+
 // The persistent multi-job kernel of one probe-size class (device tables
 // prepared by the plan).
 template <int N, int L, int K>
@@ -1424,6 +1481,11 @@ void launch_batched(const MsParams* jobs, const int2* items, int n_items, int* t
   adorym_ms::MsParams adorym_ms::make_params<N_, L_>(adorym_ctx*, const adorym_geom*, const float*, \
                                                         const float*, int, const int32_t*, const float*, \
                                                         const float*, void*, bool, float*, float*, float*)
+#define ADORYM_RUN_SPLIT_SIGNATURE(N_, L_, K_) \
+  adorym_status adorym_ms::run_split<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, const float*, \
+                                                 const float*, const int32_t*, const float*, int, const float*, \
+                                                 void*, float2*, float2*, double*, float*, float*, float*, float*, \
+                                                 float*, bool)
 #define ADORYM_RUN_NF_SIGNATURE(N_, L_, K_) \
   adorym_status adorym_ms::run_nf<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, const float*, \
                                               const float*, const int32_t*, const float*, int, int, const double*, \

@@ -98,7 +98,7 @@ def test_one_mode_equals_the_single_probe_call(ctx):
     sc = synth.small_case(seed=731, n=128, n_slices=9, lateral=150, n_pos=3, strength=30.0, loss="poisson")
     case = Case(sc, poisson_seed=3)
     inp, i_meas = case.torch_inputs()
-    g = Geometry.from_scan(sc)
+    g = Geometry.from_scan(sc, deterministic=True)      # the split the modes entry always uses
     one = ctx.loss_grad(g, **inp, i_meas=i_meas, intensity=True)
     probe = inp.pop("probe")
     many = ctx.loss_grad_modes(g, probes=probe[None].contiguous(), i_meas=i_meas, intensity=True, **inp)
@@ -106,7 +106,7 @@ def test_one_mode_equals_the_single_probe_call(ctx):
     for k in ("loss", "g_a", "g_b", "g_shift", "intensity"):
         a, b = one[k].cpu().numpy(), many[k].cpu().numpy()
         print(k, "bitwise" if np.array_equal(a, b) else f"rel-L2 {rel_l2(a, b):.2e}")
-        # same kernels, same split, same order of operations: the same bits
+        # the forward sweep stored and resumed, same split, same order of operations: the same bits
         assert np.array_equal(a, b), k
     assert np.array_equal(one["g_probe"].cpu().numpy(), many["g_probe"][0].cpu().numpy())
 
@@ -136,3 +136,47 @@ def test_modes_accumulate_and_deterministic(ctx):
         want = (base[k] + r1[k]).cpu().numpy()
         assert rel_l2(acc[k].cpu().numpy(), want) <= 1e-6, k
     assert float(acc["loss"]) == float(r1["loss"])
+
+
+def test_modes_full_minibatch_sampled_positions(ctx):
+    """The benchmarked configuration with two modes (256x256x64 object, 128
+    probe, a full minibatch of 50 positions, C = 16), at half the true object.  The oracle evaluates
+    three sampled positions one by one (their summed intensities and shift
+    gradients depend on no other position; the gradient is rescaled from
+    3 to 50 positions, the loss being a mean over all B N^2 pixels)."""
+    import torch
+    from oracle import multislice as om
+    from paper_2012_12686_amd import Geometry
+    from tests.fp32_model import loss_grad_fp32_modes
+    sc = synth.config2()
+    bsz, sample = 50, np.array([0, 25, 49])
+    geom = om.Geometry.from_scan(sc)
+    probes = f32(synth.probe_modes(sc.probe, 2, seed=11))
+    # half the true object: at the benchmark's vacuum start the intensity does
+    # not depend on the probe position and the shift gradients vanish
+    a, b = f32(0.5 * sc.obj_a), f32(0.5 * sc.obj_b)
+    pos_all = np.asarray(sc.positions, dtype=np.float64)[:bsz]
+    corner, shift = synth.split_positions(pos_all)
+    shift = f32(shift)
+    pos = corner + shift
+    i_s = np.random.default_rng(3).poisson(
+        om.forward_modes(geom, sc.obj_a, sc.obj_b, synth.probe_modes(sc.probe, 2, seed=11), pos[sample]))
+    i_meas = np.repeat(f32(i_s)[:1], bsz, axis=0)
+    i_meas[sample] = f32(i_s)
+    t = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+    out = ctx.loss_grad_modes(Geometry.from_scan(sc), t(a, torch.float32), t(b, torch.float32),
+                              t(probes, torch.complex64), t(corner, torch.int32), t(shift, torch.float32),
+                              t(i_meas, torch.float32), intensity=True)
+    torch.cuda.synchronize()
+    ctx.sync_error()
+    i_ref = om.forward_modes(geom, a, b, probes, pos[sample])
+    e_i = rel_l2(out["intensity"].cpu().numpy()[sample], i_ref)
+    print(f"sampled summed intensity rel-L2 {e_i:.3e}")
+    assert e_i <= TOL_I
+    scale = len(sample) / bsz
+    ref = om.loss_grad_modes(geom, a, b, probes, pos[sample], i_meas[sample])[4] * scale
+    f32m = loss_grad_fp32_modes(geom, a, b, probes, pos[sample], i_meas[sample])[4] * scale
+    got = out["g_shift"].cpu().numpy()[sample]
+    e_gpu, e_f32 = rel_l2(got, ref), rel_l2(f32m, ref)
+    print(f"sampled shift gradients: GPU rel-L2 {e_gpu:.3e}, float32-model floor {e_f32:.3e}")
+    assert e_gpu <= max(TOL_G, 3.0 * e_f32)
