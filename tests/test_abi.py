@@ -109,3 +109,49 @@ def test_null_context_rejected_without_touching_the_device():
     assert st == _lib.EINVAL
     assert lib.adorym_sync_error(None) == _lib.EINVAL
     assert lib.adorym_destroy(None) == _lib.EINVAL
+
+
+def test_extension_workspace_sizes():
+    """Unequal spacing, probe modes, near field and priors: the documented
+    sizes on top of the loss-and-gradient workspace; 0 on bad input."""
+    lib = _lib.load()
+    g = _geom()
+    base = lib.adorym_workspace_size(ctypes.byref(g), 50)
+    nn8 = 128 * 128 * 8
+    # gap-gradient partials: 50 positions x up to 8 parts x 63 gaps, FP64
+    gaps = lib.adorym_gaps_workspace_size(ctypes.byref(g), 50)
+    assert base + 50 * 8 * 63 * 8 <= gaps < base + 50 * 8 * 63 * 8 + 256
+    # probe modes: two intensity planes, per mode the checkpoints and the exit wave
+    slots = 63 // 16 + 1 + 1
+    for m in (1, 3):
+        got = lib.adorym_modes_workspace_size(ctypes.byref(g), 50, m)
+        expect = base + 2 * 50 * 128 * 128 * 4 + m * (50 * slots * nn8 + 50 * nn8)
+        assert expect <= got < expect + (2 + 2 * m) * 256
+    assert lib.adorym_modes_workspace_size(ctypes.byref(g), 50, 0) == 0
+    # near field: distance partials, detector spectra, one transfer function per distance, phase slope
+    nf = lib.adorym_nearfield_workspace_size(ctypes.byref(g), 50, 4)
+    expect = base + 50 * 8 * 8 + 50 * nn8 + 4 * nn8 + 128 * 128 * 4
+    assert expect <= nf < expect + 4 * 256
+    assert lib.adorym_nearfield_workspace_size(ctypes.byref(g), 50, 0) == 0
+    # priors: a few scalars and one FP64 partial per (64 x 4 tile, 32-slice run), at least 2048
+    assert lib.adorym_prior_workspace_size(128, 512, 512) == (8 + 8 * 128 * 4) * 8
+    assert lib.adorym_prior_workspace_size(1, 5, 7) == (8 + 2048) * 8
+    assert lib.adorym_prior_workspace_size(0, 5, 7) == 0
+
+
+def test_extension_entry_points_reject_bad_arguments_without_a_device():
+    lib = _lib.load()
+    g = _geom()
+    P = None
+    assert lib.adorym_loss_grad_gaps(None, ctypes.byref(g), P, P, P, P, P, 1, P, P, P, 0, P, P, P, P, P, P,
+                                     P) == _lib.EINVAL
+    assert lib.adorym_forward_gaps(None, ctypes.byref(g), P, P, P, P, P, 1, P, P, P, 0) == _lib.EINVAL
+    assert lib.adorym_loss_grad_modes(None, ctypes.byref(g), P, P, P, 2, P, P, 1, P, P, 0, P, P, P, P, P,
+                                      P) == _lib.EINVAL
+    assert lib.adorym_forward_nearfield(None, ctypes.byref(g), P, P, P, P, P, 1, 0, P, 1, P, P, P,
+                                        0) == _lib.EINVAL
+    assert lib.adorym_loss_grad_nearfield(None, ctypes.byref(g), P, P, P, P, P, 1, 0, P, 1, P, P, P, 0, P, P, P,
+                                          P, P, P, P) == _lib.EINVAL
+    assert lib.adorym_prior_grad(None, 0, P, P, 1, 1, 1, 0.0, 0.0, 0.0, P, P, P, 0, P, P, P, 1) == _lib.EINVAL
+    assert lib.adorym_prior_weights(None, 0, P, P, 1, 1, 1, 1e-3, P, 0, P, P) == _lib.EINVAL
+    assert lib.adorym_support_project(None, 0, P, P, P, 4) == _lib.EINVAL
