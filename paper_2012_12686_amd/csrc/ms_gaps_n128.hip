@@ -1,4 +1,4 @@
 // Kernel instantiations with unequal slice spacing: N=128 K=4.
 #include "multislice_impl.hpp"
 
-template ADORYM_RUN_GAPS_SIGNATURE(128, 8, 4);
+template ADORYM_RUN_GAPS_SIGNATURE(128, 16, 4);

@@ -21,8 +21,8 @@ extern template ADORYM_RUN_SIGNATURE(128, 8, 1);
 extern template ADORYM_BATCHED_SIGNATURE(128, 8, 1);
 extern template ADORYM_RUN_SIGNATURE(128, 8, 2);
 extern template ADORYM_BATCHED_SIGNATURE(128, 8, 2);
-extern template ADORYM_RUN_SIGNATURE(128, 8, 4);
-extern template ADORYM_BATCHED_SIGNATURE(128, 8, 4);
+extern template ADORYM_RUN_SIGNATURE(128, 16, 4);
+extern template ADORYM_BATCHED_SIGNATURE(128, 16, 4);
 extern template ADORYM_RUN_SIGNATURE(128, 8, 8);
 extern template ADORYM_BATCHED_SIGNATURE(128, 8, 8);
 extern template ADORYM_RUN_SIGNATURE(192, 8, 2);
@@ -37,15 +37,15 @@ extern template ADORYM_RUN_SIGNATURE(192, 8, 8);
 extern template ADORYM_BATCHED_SIGNATURE(192, 8, 8);
 extern template ADORYM_RUN_SPLIT_SIGNATURE(64, 4, 1);
 extern template ADORYM_RUN_SPLIT_SIGNATURE(96, 8, 1);
-extern template ADORYM_RUN_SPLIT_SIGNATURE(128, 8, 4);
+extern template ADORYM_RUN_SPLIT_SIGNATURE(128, 16, 4);
 extern template ADORYM_RUN_SPLIT_SIGNATURE(192, 8, 6);
 extern template ADORYM_RUN_NF_SIGNATURE(64, 4, 1);
 extern template ADORYM_RUN_NF_SIGNATURE(96, 8, 1);
-extern template ADORYM_RUN_NF_SIGNATURE(128, 8, 4);
+extern template ADORYM_RUN_NF_SIGNATURE(128, 16, 4);
 extern template ADORYM_RUN_NF_SIGNATURE(192, 8, 6);
 extern template ADORYM_RUN_GAPS_SIGNATURE(64, 4, 1);
 extern template ADORYM_RUN_GAPS_SIGNATURE(96, 8, 1);
-extern template ADORYM_RUN_GAPS_SIGNATURE(128, 8, 4);
+extern template ADORYM_RUN_GAPS_SIGNATURE(128, 16, 4);
 extern template ADORYM_RUN_GAPS_SIGNATURE(192, 8, 6);
 extern template ADORYM_PARAMS_SIGNATURE(64, 4);
 extern template ADORYM_PROLOGUE_SIGNATURE(64, 4);
@@ -111,7 +111,7 @@ adorym_status dispatch(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
     switch (k) {
       case 1: ADORYM_RUN(128, 8, 1);
       case 2: ADORYM_RUN(128, 8, 2);
-      case 4: ADORYM_RUN(128, 8, 4);
+      case 4: ADORYM_RUN(128, 16, 4);
       case 8: ADORYM_RUN(128, 8, 8);
     }
   } else if (g->n == 192) {
@@ -140,7 +140,7 @@ adorym_status dispatch_gaps(adorym_ctx* ctx, const adorym_geom* g, const float* 
   switch (g->n) {
     case 64: ADORYM_RUN_GAPS(64, 4, 1);
     case 96: ADORYM_RUN_GAPS(96, 8, 1);
-    case 128: ADORYM_RUN_GAPS(128, 8, 4);
+    case 128: ADORYM_RUN_GAPS(128, 16, 4);
     case 192: ADORYM_RUN_GAPS(192, 8, 6);
   }
 #undef ADORYM_RUN_GAPS
@@ -159,7 +159,7 @@ adorym_status dispatch_nf(adorym_ctx* ctx, const adorym_geom* g, const float* a,
   switch (g->n) {
     case 64: ADORYM_RUN_NF(64, 4, 1);
     case 96: ADORYM_RUN_NF(96, 8, 1);
-    case 128: ADORYM_RUN_NF(128, 8, 4);
+    case 128: ADORYM_RUN_NF(128, 16, 4);
     case 192: ADORYM_RUN_NF(192, 8, 6);
   }
 #undef ADORYM_RUN_NF
@@ -237,7 +237,7 @@ void class_launch(const PlanClass& c, const MsParams* d_params, int* err, hipStr
   } else if (c.n == 128) {
     if (c.k == 1) ADORYM_BATCH(128, 8, 1);
     else if (c.k == 2) ADORYM_BATCH(128, 8, 2);
-    else if (c.k == 4) ADORYM_BATCH(128, 8, 4);
+    else if (c.k == 4) ADORYM_BATCH(128, 16, 4);
     else ADORYM_BATCH(128, 8, 8);
   } else {
     if (c.k == 2) ADORYM_BATCH(192, 8, 2);
@@ -458,7 +458,7 @@ adorym_status adorym_loss_grad_modes(adorym_ctx* ctx, const adorym_geom* g, cons
     switch (g->n) {
       case 64: ADORYM_RUN_SPLIT(64, 4, 1);
       case 96: ADORYM_RUN_SPLIT(96, 8, 1);
-      case 128: ADORYM_RUN_SPLIT(128, 8, 4);
+      case 128: ADORYM_RUN_SPLIT(128, 16, 4);
       case 192: ADORYM_RUN_SPLIT(192, 8, 6);
     }
 #undef ADORYM_RUN_SPLIT

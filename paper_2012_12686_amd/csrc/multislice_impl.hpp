@@ -1222,6 +1222,12 @@ void launch_epilogue(const MsParams& P, void* ws, const adorym_geom* g, double* 
   }
 }
 
+// Lanes per line of the one-group probe kernels and the job parameters: one
+// value per probe size, whatever tile the multislice kernel of a call uses,
+// so that every path computes the probe spectrum and gradient identically.
+template <int N>
+constexpr int probe_lanes() { return N == 64 ? 4 : 8; }
+
 // Deterministic mode runs with one fixed split per probe size, so that a
 // job's results do not depend on the split chosen for other calls.
 constexpr int det_split(int n) { return n == 192 ? 6 : (n == 128 ? 4 : 1); }
@@ -1233,17 +1239,17 @@ adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const f
                   double* loss, float* g_a, float* g_b, float* g_probe, float* g_shift, float* intensity,
                   bool with_loss) {
   using C = TileCfg<N, L, K>;
-  MsParams P = make_params<N, L>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
+  MsParams P = make_params<N, probe_lanes<N>()>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
                                     with_loss ? g_a : nullptr, with_loss ? g_b : nullptr, intensity);
   P.ksplit = K;
   hipStream_t st = ctx->stream;
   const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
-  launch_prologue<N, L>(P, probe, g, st);
+  launch_prologue<N, probe_lanes<N>()>(P, probe, g, st);
   if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
   if (with_loss) launch_ms<C, true>(P, g->obj_repr, st);
   else launch_ms<C, false>(P, g->obj_repr, st);
   if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
-  if (with_loss) launch_epilogue<N, L>(P, ws, g, loss, g_probe, g_shift, st);
+  if (with_loss) launch_epilogue<N, probe_lanes<N>()>(P, ws, g, loss, g_probe, g_shift, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
   return ADORYM_OK;
@@ -1284,7 +1290,7 @@ adorym_status run_gaps(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
                        void* ws, double* loss, float* g_a, float* g_b, float* g_probe, float* g_shift,
                        double* g_gaps, float* intensity, bool with_loss) {
   using C = TileCfg<N, L, K>;
-  MsParams P = make_params<N, L>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
+  MsParams P = make_params<N, probe_lanes<N>()>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
                                     with_loss ? g_a : nullptr, with_loss ? g_b : nullptr, intensity);
   P.ksplit = K;
   P.gaps = gaps;
@@ -1292,13 +1298,13 @@ adorym_status run_gaps(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
   P.gd_part = with_loss ? reinterpret_cast<double*>(static_cast<char*>(ws) + ws_layout(g, batch).total) : nullptr;
   hipStream_t st = ctx->stream;
   const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
-  launch_prologue<N, L>(P, probe, g, st);
+  launch_prologue<N, probe_lanes<N>()>(P, probe, g, st);
   if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
   if (with_loss) launch_ms<C, true, true>(P, g->obj_repr, st);
   else launch_ms<C, false, true>(P, g->obj_repr, st);
   if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
   if (with_loss) {
-    launch_epilogue<N, L>(P, ws, g, loss, g_probe, g_shift, st);
+    launch_epilogue<N, probe_lanes<N>()>(P, ws, g, loss, g_probe, g_shift, st);
     if (g_gaps && P.S > 1) {
       const double scale = -M_PI * P.chirp_per_m / ((double)N * N * N);
       hipLaunchKernelGGL(gap_reduce_kernel, dim3(P.S - 1), dim3(256), 0, st, P.gd_part, P.B * K, P.S - 1, scale,
@@ -1383,7 +1389,7 @@ adorym_status run_nf(adorym_ctx* ctx, const adorym_geom* g, const float* a, cons
                      const int32_t* dist_idx, const float* i_meas, void* ws, double* loss, float* g_a, float* g_b,
                      float* g_probe, float* g_shift, double* g_dist, float* intensity, bool with_loss) {
   using C = TileCfg<N, L, K>;
-  MsParams P = make_params<N, L>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
+  MsParams P = make_params<N, probe_lanes<N>()>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
                                     with_loss ? g_a : nullptr, with_loss ? g_b : nullptr, intensity);
   P.ksplit = K;
   const NfLayout l = nf_layout(g, batch, n_dist);
@@ -1398,13 +1404,13 @@ adorym_status run_nf(adorym_ctx* ctx, const adorym_geom* g, const float* a, cons
   hipLaunchKernelGGL(nf_table_kernel, dim3((N * N + 255) / 256), dim3(256), 0, st, N, g->wavelength_m, g->pixel_m,
                      kind, dist, n_dist, reinterpret_cast<float2*>(base + l.h), reinterpret_cast<float*>(base + l.dph));
   const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
-  launch_prologue<N, L>(P, probe, g, st);
+  launch_prologue<N, probe_lanes<N>()>(P, probe, g, st);
   if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
   if (with_loss) launch_ms<C, true, false, true>(P, g->obj_repr, st);
   else launch_ms<C, false, false, true>(P, g->obj_repr, st);
   if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
   if (with_loss) {
-    launch_epilogue<N, L>(P, ws, g, loss, g_probe, g_shift, st);
+    launch_epilogue<N, probe_lanes<N>()>(P, ws, g, loss, g_probe, g_shift, st);
     if (g_dist)
       hipLaunchKernelGGL(dist_reduce_kernel, dim3(n_dist), dim3(256), 0, st, P.nd_part, dist_idx, P.B, K, g_dist,
                          (g->flags & ADORYM_ACCUMULATE_GRADS) ? 1 : 0);
@@ -1433,19 +1439,19 @@ adorym_status run_split(adorym_ctx* ctx, const adorym_geom* g, const float* a, c
                         float2* ckpt, float2* exit_wave, double* loss, float* g_a, float* g_b, float* g_probe,
                         float* g_shift, float* intensity, bool with_loss) {
   using C = TileCfg<N, L, K>;
-  MsParams P = make_params<N, L>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
+  MsParams P = make_params<N, probe_lanes<N>()>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
                                     with_loss ? g_a : nullptr, with_loss ? g_b : nullptr, intensity);
   P.ksplit = K;
   P.ckpt = ckpt;
   P.exit_wave = exit_wave;
   hipStream_t st = ctx->stream;
   const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
-  launch_prologue<N, L>(P, probe, g, st);
+  launch_prologue<N, probe_lanes<N>()>(P, probe, g, st);
   if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
   if (with_loss) launch_ms<C, true, false, false, true>(P, g->obj_repr, st);
   else launch_ms<C, false, false, false, true>(P, g->obj_repr, st);
   if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
-  if (with_loss) launch_epilogue<N, L>(P, ws, g, loss, g_probe, g_shift, st);
+  if (with_loss) launch_epilogue<N, probe_lanes<N>()>(P, ws, g, loss, g_probe, g_shift, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
   return ADORYM_OK;

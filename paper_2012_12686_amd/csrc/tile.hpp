@@ -202,12 +202,13 @@ struct Dft {
 };
 
 // ----------------------------------------------------------------------------
-// DPP lane exchanges within a lane group of L lanes (L = 4 or 8)
+// DPP lane exchanges within a lane group of L lanes (L = 4, 8 or 16)
 // ----------------------------------------------------------------------------
 enum : int {
   kDppQuadXor1 = 0xB1,     // quad_perm [1,0,3,2]
   kDppQuadXor2 = 0x4E,     // quad_perm [2,3,0,1]
   kDppHalfMirror = 0x141,  // row_half_mirror: lane i <- lane 7-i within 8
+  kDppMirror = 0x140,      // row_mirror: lane i <- lane 15-i within 16
 };
 
 template <int CTRL>
@@ -220,7 +221,8 @@ __device__ __forceinline__ float2 dpp2(float2 v) {
 }
 template <int L, int H>
 __device__ __forceinline__ float2 partner(float2 v) {
-  if constexpr (L == 8 && H == 4) return dpp2<kDppHalfMirror>(v);
+  if constexpr (L == 16 && H == 8) return dpp2<kDppMirror>(v);
+  else if constexpr (L >= 8 && H == 4) return dpp2<kDppHalfMirror>(v);
   else if constexpr (H == 2) return dpp2<kDppQuadXor2>(v);
   else return dpp2<kDppQuadXor1>(v);
 }
@@ -276,7 +278,12 @@ struct Lane {
     int lane = t & 63;
     g = lane / C::L;
     l = lane % C::L;
-    q = (C::L == 8 && l >= 4) ? 11 - l : l;
+    // logical index of the lane: the DPP partner of every radix-2 span is
+    // the lane holding logical index q ^ span (L = 8: lanes 4..7 hold 7..4;
+    // L = 16: lanes 8..15 hold the L = 8 order of lanes 7..0, plus 8)
+    const int l8 = C::L == 16 && l >= 8 ? 15 - l : l;
+    const int q8 = (C::L >= 8 && l8 >= 4) ? 11 - l8 : l8;
+    q = (C::L == 16 && l >= 8) ? (q8 ^ 8) : q8;
     k1 = bitrev_n(q, C::LOGL);
     line = part * C::LINES + w * C::RPW + g;
   }
