@@ -5,12 +5,12 @@
 
 using namespace adorym_ms;
 
-extern template ADORYM_RUN_SIGNATURE(64, 4, 1);
-extern template ADORYM_BATCHED_SIGNATURE(64, 4, 1);
-extern template ADORYM_RUN_SIGNATURE(64, 4, 2);
-extern template ADORYM_BATCHED_SIGNATURE(64, 4, 2);
-extern template ADORYM_RUN_SIGNATURE(64, 4, 4);
-extern template ADORYM_BATCHED_SIGNATURE(64, 4, 4);
+extern template ADORYM_RUN_SIGNATURE(64, 8, 1);
+extern template ADORYM_BATCHED_SIGNATURE(64, 8, 1);
+extern template ADORYM_RUN_SIGNATURE(64, 8, 2);
+extern template ADORYM_BATCHED_SIGNATURE(64, 8, 2);
+extern template ADORYM_RUN_SIGNATURE(64, 8, 4);
+extern template ADORYM_BATCHED_SIGNATURE(64, 8, 4);
 extern template ADORYM_RUN_SIGNATURE(96, 8, 1);
 extern template ADORYM_BATCHED_SIGNATURE(96, 8, 1);
 extern template ADORYM_RUN_SIGNATURE(96, 8, 2);
@@ -29,24 +29,24 @@ extern template ADORYM_RUN_SIGNATURE(192, 8, 2);
 extern template ADORYM_BATCHED_SIGNATURE(192, 8, 2);
 extern template ADORYM_RUN_SIGNATURE(192, 8, 4);
 extern template ADORYM_BATCHED_SIGNATURE(192, 8, 4);
-extern template ADORYM_RUN_SIGNATURE(192, 8, 6);
-extern template ADORYM_BATCHED_SIGNATURE(192, 8, 6);
+extern template ADORYM_RUN_SIGNATURE(192, 16, 6);
+extern template ADORYM_BATCHED_SIGNATURE(192, 16, 6);
 extern template ADORYM_RUN_SIGNATURE(96, 8, 3);
 extern template ADORYM_BATCHED_SIGNATURE(96, 8, 3);
-extern template ADORYM_RUN_SIGNATURE(192, 8, 8);
-extern template ADORYM_BATCHED_SIGNATURE(192, 8, 8);
-extern template ADORYM_RUN_SPLIT_SIGNATURE(64, 4, 1);
+extern template ADORYM_RUN_SIGNATURE(192, 16, 8);
+extern template ADORYM_BATCHED_SIGNATURE(192, 16, 8);
+extern template ADORYM_RUN_SPLIT_SIGNATURE(64, 8, 1);
 extern template ADORYM_RUN_SPLIT_SIGNATURE(96, 8, 1);
 extern template ADORYM_RUN_SPLIT_SIGNATURE(128, 16, 4);
-extern template ADORYM_RUN_SPLIT_SIGNATURE(192, 8, 6);
-extern template ADORYM_RUN_NF_SIGNATURE(64, 4, 1);
+extern template ADORYM_RUN_SPLIT_SIGNATURE(192, 16, 6);
+extern template ADORYM_RUN_NF_SIGNATURE(64, 8, 1);
 extern template ADORYM_RUN_NF_SIGNATURE(96, 8, 1);
 extern template ADORYM_RUN_NF_SIGNATURE(128, 16, 4);
-extern template ADORYM_RUN_NF_SIGNATURE(192, 8, 6);
-extern template ADORYM_RUN_GAPS_SIGNATURE(64, 4, 1);
+extern template ADORYM_RUN_NF_SIGNATURE(192, 16, 6);
+extern template ADORYM_RUN_GAPS_SIGNATURE(64, 8, 1);
 extern template ADORYM_RUN_GAPS_SIGNATURE(96, 8, 1);
 extern template ADORYM_RUN_GAPS_SIGNATURE(128, 16, 4);
-extern template ADORYM_RUN_GAPS_SIGNATURE(192, 8, 6);
+extern template ADORYM_RUN_GAPS_SIGNATURE(192, 16, 6);
 extern template ADORYM_PARAMS_SIGNATURE(64, 4);
 extern template ADORYM_PROLOGUE_SIGNATURE(64, 4);
 extern template ADORYM_EPILOGUE_SIGNATURE(64, 4);
@@ -77,7 +77,7 @@ int split_of(const adorym_ctx* ctx, int n) {
 int pick_split(const adorym_ctx* ctx, int n, int batch) {
   const int forced = split_of(ctx, n);
   if (forced > 0) return forced;
-  // N = 192: six workgroups of four waves (one wave per SIMD; fastest)
+  // N = 192: six workgroups of eight waves (two per SIMD)
   if (n == 192) return 6;
   // largest power-of-two split that keeps the grid within one workgroup per CU
   const int kmax = n == 128 ? 8 : 4;
@@ -96,9 +96,9 @@ adorym_status dispatch(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
                          intensity, with_loss)
   if (g->n == 64) {
     switch (k) {
-      case 1: ADORYM_RUN(64, 4, 1);
-      case 2: ADORYM_RUN(64, 4, 2);
-      case 4: ADORYM_RUN(64, 4, 4);
+      case 1: ADORYM_RUN(64, 8, 1);
+      case 2: ADORYM_RUN(64, 8, 2);
+      case 4: ADORYM_RUN(64, 8, 4);
     }
   } else if (g->n == 96) {
     switch (k) {
@@ -118,8 +118,8 @@ adorym_status dispatch(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
     switch (k) {
       case 2: ADORYM_RUN(192, 8, 2);
       case 4: ADORYM_RUN(192, 8, 4);
-      case 6: ADORYM_RUN(192, 8, 6);
-      case 8: ADORYM_RUN(192, 8, 8);
+      case 6: ADORYM_RUN(192, 16, 6);
+      case 8: ADORYM_RUN(192, 16, 8);
     }
   }
 #undef ADORYM_RUN
@@ -138,10 +138,10 @@ adorym_status dispatch_gaps(adorym_ctx* ctx, const adorym_geom* g, const float* 
   static_assert(det_split(64) == 1 && det_split(96) == 1 && det_split(128) == 4 && det_split(192) == 6,
                 "unequal-spacing kernels are instantiated for the deterministic splits");
   switch (g->n) {
-    case 64: ADORYM_RUN_GAPS(64, 4, 1);
+    case 64: ADORYM_RUN_GAPS(64, 8, 1);
     case 96: ADORYM_RUN_GAPS(96, 8, 1);
     case 128: ADORYM_RUN_GAPS(128, 16, 4);
-    case 192: ADORYM_RUN_GAPS(192, 8, 6);
+    case 192: ADORYM_RUN_GAPS(192, 16, 6);
   }
 #undef ADORYM_RUN_GAPS
   return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size");
@@ -157,10 +157,10 @@ adorym_status dispatch_nf(adorym_ctx* ctx, const adorym_geom* g, const float* a,
   return run_nf<N_, L_, K_>(ctx, g, a, b, probe, corner, shift, batch, kind, dist, n_dist, idx, i_meas, ws, loss, g_a, \
                             g_b, g_probe, g_shift, g_dist, intensity, with_loss)
   switch (g->n) {
-    case 64: ADORYM_RUN_NF(64, 4, 1);
+    case 64: ADORYM_RUN_NF(64, 8, 1);
     case 96: ADORYM_RUN_NF(96, 8, 1);
     case 128: ADORYM_RUN_NF(128, 16, 4);
-    case 192: ADORYM_RUN_NF(192, 8, 6);
+    case 192: ADORYM_RUN_NF(192, 16, 6);
   }
 #undef ADORYM_RUN_NF
   return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size");
@@ -228,7 +228,7 @@ void class_launch(const PlanClass& c, const MsParams* d_params, int* err, hipStr
   launch_batched<N_, L_, K_>(d_params, c.items, c.n_items, ticket, mailbox, counters, xcc, c.xbuf, err, c.groups, \
                              c.repr, st)
   if (c.n == 64) {
-    if (c.k == 1) ADORYM_BATCH(64, 4, 1); else if (c.k == 2) ADORYM_BATCH(64, 4, 2); else ADORYM_BATCH(64, 4, 4);
+    if (c.k == 1) ADORYM_BATCH(64, 8, 1); else if (c.k == 2) ADORYM_BATCH(64, 8, 2); else ADORYM_BATCH(64, 8, 4);
   } else if (c.n == 96) {
     if (c.k == 1) ADORYM_BATCH(96, 8, 1);
     else if (c.k == 2) ADORYM_BATCH(96, 8, 2);
@@ -242,8 +242,8 @@ void class_launch(const PlanClass& c, const MsParams* d_params, int* err, hipStr
   } else {
     if (c.k == 2) ADORYM_BATCH(192, 8, 2);
     else if (c.k == 4) ADORYM_BATCH(192, 8, 4);
-    else if (c.k == 6) ADORYM_BATCH(192, 8, 6);
-    else ADORYM_BATCH(192, 8, 8);
+    else if (c.k == 6) ADORYM_BATCH(192, 16, 6);
+    else ADORYM_BATCH(192, 16, 8);
   }
 #undef ADORYM_BATCH
 }
@@ -456,10 +456,10 @@ adorym_status adorym_loss_grad_modes(adorym_ctx* ctx, const adorym_geom* g, cons
                                ckpt_of(m), exit_of(m), with_loss ? loss : nullptr, with_loss ? g_a : nullptr,      \
                                with_loss ? g_b : nullptr, gp, with_loss ? g_shift : nullptr, inten, with_loss)
     switch (g->n) {
-      case 64: ADORYM_RUN_SPLIT(64, 4, 1);
+      case 64: ADORYM_RUN_SPLIT(64, 8, 1);
       case 96: ADORYM_RUN_SPLIT(96, 8, 1);
       case 128: ADORYM_RUN_SPLIT(128, 16, 4);
-      case 192: ADORYM_RUN_SPLIT(192, 8, 6);
+      case 192: ADORYM_RUN_SPLIT(192, 16, 6);
     }
 #undef ADORYM_RUN_SPLIT
     return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size");
