@@ -97,7 +97,7 @@ def main():
                     help="workgroups per position (0 = the library's automatic choice)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters)")
-    ap.add_argument("--workload", default="multislice", choices=["multislice", "batching", "serving", "sparse", "priors", "mdh"],
+    ap.add_argument("--workload", default="multislice", choices=["multislice", "batching", "serving", "sparse", "priors", "mdh", "differentiation"],
                     help="multislice: the 64-slice minibatch (default line); batching: 32 mixed scans, "
                          "batched vs per-job; serving: the request loop")
     ap.add_argument("--ckpt", type=int, default=16, help="slice checkpoint interval of the adjoint")
@@ -133,6 +133,8 @@ def main():
         return bench_priors(args)
     if args.workload == "mdh":
         return bench_mdh(args)
+    if args.workload == "differentiation":
+        return bench_differentiation(args)
 
     import synth
     from paper_2012_12686_amd import Context, Geometry, split_positions
@@ -338,6 +340,98 @@ def bench_sparse(args):
         dt = time.perf_counter() - t
         line["cpu_baseline"] = {"value": sample / dt, "unit": "positions/s", "cores": om._WORKERS, "kind": "oracle",
                                 "sample": f"FP64 oracle loss_grad_gaps on {sample} positions of the first minibatch"}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def bench_differentiation(args):
+    """The 128-slice differentiation workload: 512 x 512 x 128 object, 128
+    probe, minibatches of 200 of 1024 positions, checkpoints every 16 slices,
+    evaluated at half the true object, a perturbed probe and nominal
+    positions (the true ones are shifted by up to 1 px)."""
+    import torch
+
+    import synth
+    from paper_2012_12686_amd import Context, Geometry, split_positions
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    sc = synth.config3()
+    n, s, mb = sc.n, sc.n_slices, sc.minibatch
+    n_mb = len(sc.positions) // mb
+    ctx = Context(dev)
+    geom = Geometry.from_scan(sc, ckpt_every=args.ckpt, deterministic=args.deterministic)
+    if args.split:
+        ctx.set_split(n, args.split)
+    to_t = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device=dev)
+    ta, tb = to_t(sc.obj_a, torch.float32), to_t(sc.obj_b, torch.float32)
+    corner_t, shift_t = split_positions(to_t(sc.positions, torch.float64))
+    probe_t = to_t(sc.probe, torch.complex64)
+    i_meas = torch.cat([ctx.forward(geom, ta, tb, probe_t, corner_t[k * mb:(k + 1) * mb],
+                                    shift_t[k * mb:(k + 1) * mb]) for k in range(n_mb)])
+    del ta, tb
+    a, b = to_t(sc.eval_obj_a, torch.float32), to_t(sc.eval_obj_b, torch.float32)
+    probe = to_t(sc.eval_probe, torch.complex64)
+    corner, shift = split_positions(to_t(sc.eval_positions, torch.float64))
+    ws = ctx.workspace(geom, mb)
+    out = {"loss": torch.empty((), dtype=torch.float64, device=dev), "g_a": torch.empty_like(a),
+           "g_b": torch.empty_like(b), "g_probe": torch.empty_like(probe),
+           "g_shift": torch.empty((mb, 2), dtype=torch.float32, device=dev)}
+
+    def step(k):
+        sl = slice((k % n_mb) * mb, (k % n_mb + 1) * mb)
+        ctx.loss_grad(geom, a, b, probe, corner[sl], shift[sl], i_meas[sl], out=out, workspace=ws)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    ctx.sync_error()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ctx.profile_start(args.steps + 8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record()
+        step(k)
+        ends[k].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_ms, kern_n = ctx.profile_stop()
+    ctx.sync_error()
+    lat = sorted(st.elapsed_time(en) for st, en in zip(starts, ends))
+    kern_avg_s = kern_ms / max(kern_n, 1) / 1e3
+    bytes_launch = algorithmic_bytes_per_position(n, s, args.ckpt) * mb
+    achieved = bytes_launch / kern_avg_s / 1e9
+    flops = algorithmic_flops_per_position(n, s) * mb / kern_avg_s / 1e12
+    line = {
+        "metric": "multislice fwd+adjoint positions/s, % HBM roofline (differentiation workload)",
+        "value": mb * args.steps / elapsed, "unit": "positions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "multislice N=128 S=128 object 512x512x128 (10 nm, 10 keV), minibatch 200 of "
+                               "1024 positions, Gaussian loss, checkpoints every 16 slices, gradients for "
+                               "delta, beta, probe and shifts", "global_batch": mb, "seq_len": s,
+                   "parallelism": "none"},
+        "p50_iter_ms": float(np.percentile(lat, 50)), "p99_iter_ms": float(np.percentile(lat, 99)),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "multislice_kernel<N=128, delta/beta, Gaussian, loss+adjoint>",
+                     "kernel_avg_ms": kern_avg_s * 1e3, "kernel_launches": kern_n,
+                     "algorithmic_bytes_per_launch": bytes_launch, "fp32_tflops": flops,
+                     "fp32_frac": flops / FP32_PEAK_TFLOPS},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import multislice as om
+        sample = 8
+        og = om.Geometry.from_scan(sc)
+        im = i_meas[:sample].cpu().numpy().astype(np.float64)
+        t = time.perf_counter()
+        om.loss_grad(og, sc.eval_obj_a, sc.eval_obj_b, sc.eval_probe, np.asarray(sc.eval_positions)[:sample], im)
+        dt = time.perf_counter() - t
+        line["cpu_baseline"] = {"value": sample / dt, "unit": "positions/s", "cores": om._WORKERS, "kind": "oracle",
+                                "sample": f"FP64 oracle loss_grad on {sample} positions of the first minibatch, "
+                                          f"{dt:.1f} s"}
     print(json.dumps(line), flush=True)
     ctx.close()
 
