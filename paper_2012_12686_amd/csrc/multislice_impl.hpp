@@ -34,10 +34,6 @@
 
 using namespace adorym;
 
-#ifndef ADORYM_L128
-#define ADORYM_L128 8
-#endif
-
 #include "context.hpp"
 
 namespace adorym_ms {
@@ -988,14 +984,26 @@ __global__ void __launch_bounds__(C::THREADS) probe_grad_kernel(const float2* __
 
 
 // Object gradient from the staged per-position contributions.  One
-// workgroup per 64 x 16 voxel tile of one slice: it lists, in index order,
-// the positions whose chunk overlaps the tile (chunks outside the object are
-// skipped, as in the multislice kernel); every voxel then sums the
+// workgroup per kRedTx x kRedTy voxel tile of one slice: it lists, in index
+// order, the positions whose chunk overlaps the tile (chunks outside the
+// object are skipped, as in the multislice kernel); every voxel then sums the
 // contributions of those positions in that order in FP64 and is written once,
-// rounded to float32.  Loads of kRedUnroll positions are issued together;
-// voxels a chunk does not cover read 0 through the buffer range check (an
-// added +0.0 leaves an FP64 sum unchanged).
-constexpr int kRedTx = 64, kRedTy = 16, kRedList = 2048, kRedUnroll = 8;
+// rounded to float32.  A lane covers kRedTx / 64 columns 64 apart and a wave
+// kRedTy / 4 rows, so every load instruction reads 64 consecutive floats of
+// a staged row; wide tiles split a chunk's 512-byte rows at fewer places
+// (each split re-reads one cache line).  Loads of kRedUnroll positions are
+// issued together; voxels a chunk does not cover read 0 through the buffer
+// range check (an added +0.0 leaves an FP64 sum unchanged).
+#ifndef ADORYM_RED_TX
+#define ADORYM_RED_TX 256
+#endif
+#ifndef ADORYM_RED_TY
+#define ADORYM_RED_TY 4
+#endif
+#ifndef ADORYM_RED_UNROLL
+#define ADORYM_RED_UNROLL 4
+#endif
+constexpr int kRedTx = ADORYM_RED_TX, kRedTy = ADORYM_RED_TY, kRedList = 2048, kRedUnroll = ADORYM_RED_UNROLL;
 constexpr uint32_t kRedOutside = 0xFFFFFFF0u;   // beyond any plane: reads 0
 static __global__ void __launch_bounds__(256) grad_reduce_kernel(const float* __restrict__ stage,
                                                                  const int32_t* __restrict__ corner, int n, int B,
@@ -1004,13 +1012,15 @@ static __global__ void __launch_bounds__(256) grad_reduce_kernel(const float* __
   __shared__ int lb[kRedList], lcy[kRedList], lcx[kRedList];
   __shared__ int wave_cnt[4];
   constexpr int RY = kRedTy / 4;                  // rows per thread
+  constexpr int RX = kRedTx / 64;                 // columns per thread
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tx0 = blockIdx.x * kRedTx, ty0 = blockIdx.y * kRedTy, j = blockIdx.z;
-  const int x = tx0 + lane;
   const uint32_t plane_bytes = (uint32_t)(n * n * 4);
-  double acc_a[RY], acc_b[RY];
+  double acc_a[RY][RX], acc_b[RY][RX];
 #pragma unroll
-  for (int r = 0; r < RY; ++r) acc_a[r] = acc_b[r] = 0.0;
+  for (int r = 0; r < RY; ++r)
+#pragma unroll
+    for (int c = 0; c < RX; ++c) acc_a[r][c] = acc_b[r][c] = 0.0;
   for (int w0 = 0; w0 < B; w0 += kRedList) {
     const int w1 = min(B, w0 + kRedList);
     int count = 0;                                  // uniform over the workgroup
@@ -1034,7 +1044,7 @@ static __global__ void __launch_bounds__(256) grad_reduce_kernel(const float* __
       __syncthreads();
     }
     for (int i0 = 0; i0 < count; i0 += kRedUnroll) {
-      float va[kRedUnroll][RY], vb[kRedUnroll][RY];
+      float va[kRedUnroll][RY][RX], vb[kRedUnroll][RY][RX];
 #pragma unroll
       for (int u = 0; u < kRedUnroll; ++u) {
         const int i = min(i0 + u, count - 1);
@@ -1045,36 +1055,45 @@ static __global__ void __launch_bounds__(256) grad_reduce_kernel(const float* __
         const float* base = stage + ((size_t)pb * S + j) * 2 * (size_t)n * n;
         const rsrc_t ra = make_rsrc(base, plane_bytes);
         const rsrc_t rb = make_rsrc(base + (size_t)n * n, plane_bytes);
-        const int lx = x - cx;
-        const bool xin = live && lx >= 0 && lx < n;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
           const int ly = ty0 + wave + 4 * r - cy;
-          const uint32_t off = (xin && ly >= 0 && ly < n) ? (uint32_t)(ly * n + lx) * 4 : kRedOutside;
-          va[u][r] = bload(ra, off, 0);
-          vb[u][r] = bload(rb, off, 0);
+#pragma unroll
+          for (int c = 0; c < RX; ++c) {
+            const int lx = tx0 + lane + 64 * c - cx;
+            const bool in = live && lx >= 0 && lx < n && ly >= 0 && ly < n;
+            const uint32_t off = in ? (uint32_t)(ly * n + lx) * 4 : kRedOutside;
+            va[u][r][c] = bload(ra, off, 0);
+            vb[u][r][c] = bload(rb, off, 0);
+          }
         }
       }
 #pragma unroll
       for (int u = 0; u < kRedUnroll; ++u)
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-          acc_a[r] += (double)va[u][r];
-          acc_b[r] += (double)vb[u][r];
-        }
+        for (int r = 0; r < RY; ++r)
+#pragma unroll
+          for (int c = 0; c < RX; ++c) {
+            acc_a[r][c] += (double)va[u][r][c];
+            acc_b[r][c] += (double)vb[u][r][c];
+          }
     }
     __syncthreads();                                // the list is rebuilt for the next window
   }
-  if (x >= Lx) return;
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     const int y = ty0 + wave + 4 * r;
     if (y >= Ly) continue;
-    const size_t idx = ((size_t)j * Ly + y) * Lx + x;
-    double va = acc_a[r], vb = acc_b[r];
-    if (accumulate) { va += (double)g_a[idx]; vb += (double)g_b[idx]; }
-    g_a[idx] = (float)va;
-    g_b[idx] = (float)vb;
+#pragma unroll
+    for (int c = 0; c < RX; ++c) {
+      const int x = tx0 + lane + 64 * c;
+      if (x >= Lx) continue;
+      const size_t idx = ((size_t)j * Ly + y) * Lx + x;
+      double va = acc_a[r][c], vb = acc_b[r][c];
+      if (accumulate) { va += (double)g_a[idx]; vb += (double)g_b[idx]; }
+      g_a[idx] = (float)va;
+      g_b[idx] = (float)vb;
+    }
   }
 }
 
