@@ -1,5 +1,5 @@
-// Kernel instantiations: N=96 K=3 (32 lines per workgroup: four waves, one per SIMD).
+// Kernel instantiations: N=96 K=3 (16 lanes per line: eight waves, two per SIMD).
 #include "multislice_impl.hpp"
 
-template ADORYM_RUN_SIGNATURE(96, 8, 3);
-template ADORYM_BATCHED_SIGNATURE(96, 8, 3);
+template ADORYM_RUN_SIGNATURE(96, 16, 3);
+template ADORYM_BATCHED_SIGNATURE(96, 16, 3);

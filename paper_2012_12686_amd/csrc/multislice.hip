@@ -31,8 +31,8 @@ extern template ADORYM_RUN_SIGNATURE(192, 8, 4);
 extern template ADORYM_BATCHED_SIGNATURE(192, 8, 4);
 extern template ADORYM_RUN_SIGNATURE(192, 16, 6);
 extern template ADORYM_BATCHED_SIGNATURE(192, 16, 6);
-extern template ADORYM_RUN_SIGNATURE(96, 8, 3);
-extern template ADORYM_BATCHED_SIGNATURE(96, 8, 3);
+extern template ADORYM_RUN_SIGNATURE(96, 16, 3);
+extern template ADORYM_BATCHED_SIGNATURE(96, 16, 3);
 extern template ADORYM_RUN_SIGNATURE(192, 16, 8);
 extern template ADORYM_BATCHED_SIGNATURE(192, 16, 8);
 extern template ADORYM_RUN_SPLIT_SIGNATURE(64, 8, 1);
@@ -104,7 +104,7 @@ adorym_status dispatch(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
     switch (k) {
       case 1: ADORYM_RUN(96, 8, 1);
       case 2: ADORYM_RUN(96, 8, 2);
-      case 3: ADORYM_RUN(96, 8, 3);
+      case 3: ADORYM_RUN(96, 16, 3);
       case 4: ADORYM_RUN(96, 8, 4);
     }
   } else if (g->n == 128) {
@@ -232,7 +232,7 @@ void class_launch(const PlanClass& c, const MsParams* d_params, int* err, hipStr
   } else if (c.n == 96) {
     if (c.k == 1) ADORYM_BATCH(96, 8, 1);
     else if (c.k == 2) ADORYM_BATCH(96, 8, 2);
-    else if (c.k == 3) ADORYM_BATCH(96, 8, 3);
+    else if (c.k == 3) ADORYM_BATCH(96, 16, 3);
     else ADORYM_BATCH(96, 8, 4);
   } else if (c.n == 128) {
     if (c.k == 1) ADORYM_BATCH(128, 8, 1);
