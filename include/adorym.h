@@ -232,6 +232,30 @@ adorym_status adorym_loss_grad_modes(adorym_ctx* ctx, const adorym_geom* g,
                                      double* loss, float* g_a, float* g_b, float* g_probe,
                                      float* g_shift, float* intensity);
 
+/* Loss now, gradients later (a torch.autograd.Function's forward and
+ * backward).  adorym_loss_fwd runs the forward model, keeps every
+ * position's slice checkpoints and exit wave in the workspace (of
+ * adorym_loss_fwd_workspace_size bytes), writes *loss (device double) and,
+ * if `intensity` is not NULL, the predicted intensities.  adorym_loss_bwd,
+ * called later with the same arguments and the untouched workspace, resumes
+ * from what the forward kept (no second forward sweep) and writes the
+ * gradients of grad_scale * L (grad_scale a finite float32 value; the
+ * reverse sweep is linear in it).  Gradient pointers and
+ * ADORYM_ACCUMULATE_GRADS as in adorym_loss_grad.  Both run with the fixed
+ * split of ADORYM_DETERMINISTIC; with grad_scale = 1 the gradients equal,
+ * bit for bit, those of adorym_loss_grad with ADORYM_DETERMINISTIC. */
+size_t adorym_loss_fwd_workspace_size(const adorym_geom* g, int32_t batch);
+adorym_status adorym_loss_fwd(adorym_ctx* ctx, const adorym_geom* g,
+                              const float* obj_a, const float* obj_b, const float* probe,
+                              const int32_t* corner, const float* shift, int32_t batch,
+                              const float* i_meas, void* workspace, size_t ws_bytes,
+                              double* loss, float* intensity);
+adorym_status adorym_loss_bwd(adorym_ctx* ctx, const adorym_geom* g,
+                              const float* obj_a, const float* obj_b, const float* probe,
+                              const int32_t* corner, const float* shift, int32_t batch,
+                              const float* i_meas, void* workspace, size_t ws_bytes, double grad_scale,
+                              float* g_a, float* g_b, float* g_probe, float* g_shift);
+
 /* Tilt rotation of a slice-major float32 object [lz][ly][lx] about the y
  * axis (Sec. S1.D.2, Eq. rotation_transform): every xz-plane is resampled
  * by bilinear interpolation at (x0, z0) = R(theta)(x_t - cx, z_t - cz) + c,
@@ -302,6 +326,20 @@ typedef struct {
 } adorym_job;
 typedef struct adorym_plan adorym_plan;
 adorym_status adorym_plan_create(adorym_ctx* ctx, const adorym_job* jobs, int32_t n_jobs, adorym_plan** out);
+/* One-shot batched evaluation: plan_create, plan_run, a stream
+ * synchronisation and plan_destroy (it allocates and synchronises; for
+ * repeated iterations keep a plan). */
+adorym_status adorym_loss_grad_batched(adorym_ctx* ctx, const adorym_job* jobs, int32_t n_jobs);
+/* Autotuner of the split per probe size: for every probe size among the
+ * jobs (deterministic jobs excepted: their split is fixed) it times `reps`
+ * plan runs of those jobs with each supported split (N = 64: 1, 2, 4;
+ * 96: 1, 2, 3, 4; 128: 1, 2, 4, 8; 192: 2, 4, 6, 8), keeps the fastest and
+ * sets it on the context (as adorym_set_split).  chosen, if not NULL,
+ * receives the split for N = 64, 96, 128, 192 (the context's current
+ * value, 0 = automatic, for sizes without jobs).  The jobs' outputs are
+ * overwritten.  Allocates and synchronises: a set-up call. */
+adorym_status adorym_autotune(adorym_ctx* ctx, const adorym_job* jobs, int32_t n_jobs, int32_t reps,
+                              int32_t* chosen);
 adorym_status adorym_plan_run(adorym_ctx* ctx, adorym_plan* plan);
 adorym_status adorym_plan_destroy(adorym_plan* plan);
 

@@ -69,6 +69,13 @@ SIGNATURES = {
     "adorym_loss_grad_nearfield": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P,
                                                   ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P, _P, _P, _P, _P,
                                                   _P, _P]),
+    "adorym_loss_fwd_workspace_size": (ctypes.c_size_t, [_GP, ctypes.c_int32]),
+    "adorym_loss_fwd": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
+                                       _P]),
+    "adorym_loss_bwd": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t,
+                                       ctypes.c_double, _P, _P, _P, _P]),
+    "adorym_loss_grad_batched": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "adorym_autotune": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
     "adorym_gaps_workspace_size": (ctypes.c_size_t, [_GP, ctypes.c_int32]),
     "adorym_forward_gaps": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P,
                                            ctypes.c_size_t]),

@@ -422,6 +422,59 @@ class Context:
         """A batched plan over many jobs; see ``Plan``."""
         return Plan(self, jobs)
 
+    def loss_grad_batched(self, jobs):
+        """One-shot batched loss and gradients of ``jobs`` (outputs in each job's ``out``)."""
+        self._bind_stream()
+        jobs = list(jobs)
+        cjobs = _job_structs(self, jobs)
+        check(load().adorym_loss_grad_batched(self._ctx, cjobs, len(jobs)), self._ctx)
+        return jobs
+
+    def autotune(self, jobs, reps: int = 2):
+        """Library autotuner: the fastest split per probe size among ``jobs``, set on this
+        context.  Returns {N: split}."""
+        self._bind_stream()
+        jobs = list(jobs)
+        cjobs = _job_structs(self, jobs)
+        chosen = (ctypes.c_int32 * 4)()
+        check(load().adorym_autotune(self._ctx, cjobs, len(jobs), reps, chosen), self._ctx)
+        present = {j.geom.n for j in jobs if not j.geom.deterministic}
+        return {n: int(k) for n, k in zip((64, 96, 128, 192), chosen) if n in present}
+
+    # ------------------------------------------------- loss now, gradients later
+    def loss_fwd_workspace_size(self, geom: Geometry, batch: int) -> int:
+        return int(load().adorym_loss_fwd_workspace_size(ctypes.byref(geom.to_c()), batch))
+
+    def loss_fwd(self, geom, obj_a, obj_b, probe, corner, shift, i_meas, workspace=None, intensity=False):
+        """Loss only; the workspace keeps what :meth:`loss_bwd` needs.  Returns (loss, workspace[, intensity])."""
+        self._bind_stream()
+        b = self._check_inputs(geom, obj_a, obj_b, probe, corner, shift)
+        ws = workspace if workspace is not None else torch.empty(self.loss_fwd_workspace_size(geom, b),
+                                                                 dtype=torch.uint8, device=self.device)
+        loss = torch.empty((), dtype=torch.float64, device=self.device)
+        inten = torch.empty((b, geom.n, geom.n), dtype=torch.float32, device=self.device) if intensity else None
+        check(load().adorym_loss_fwd(self._ctx, ctypes.byref(geom.to_c()), _ptr(obj_a), _ptr(obj_b),
+                                     _ptr(torch.view_as_real(probe)), _ptr(corner), _ptr(shift), b, _ptr(i_meas),
+                                     _ptr(ws), ws.numel(), _ptr(loss), _ptr(inten)), self._ctx)
+        return (loss, ws, inten) if intensity else (loss, ws)
+
+    def loss_bwd(self, geom, obj_a, obj_b, probe, corner, shift, i_meas, workspace, grad_scale=1.0, out=None):
+        """Gradients of grad_scale * L from a :meth:`loss_fwd` workspace."""
+        self._bind_stream()
+        b = self._check_inputs(geom, obj_a, obj_b, probe, corner, shift)
+        out = dict(out or {})
+        dev = self.device
+        for name, shape, dt in (("g_a", obj_a.shape, torch.float32), ("g_b", obj_b.shape, torch.float32),
+                                ("g_probe", probe.shape, torch.complex64), ("g_shift", (b, 2), torch.float32)):
+            if name not in out:
+                out[name] = (torch.zeros if geom.accumulate else torch.empty)(shape, dtype=dt, device=dev)
+        check(load().adorym_loss_bwd(self._ctx, ctypes.byref(geom.to_c()), _ptr(obj_a), _ptr(obj_b),
+                                     _ptr(torch.view_as_real(probe)), _ptr(corner), _ptr(shift), b, _ptr(i_meas),
+                                     _ptr(workspace), workspace.numel(), float(grad_scale), _ptr(out["g_a"]),
+                                     _ptr(out["g_b"]), _ptr(torch.view_as_real(out["g_probe"])),
+                                     _ptr(out["g_shift"])), self._ctx)
+        return out
+
 
 @dataclasses.dataclass
 class Job:
@@ -449,31 +502,9 @@ class Plan:
     def __init__(self, ctx: "Context", jobs):
         self.ctx = ctx
         self.jobs = list(jobs)
-        dev = ctx.device
-        cjobs = (_lib.Job * len(self.jobs))()
-        for i, j in enumerate(self.jobs):
-            b = ctx._check_inputs(j.geom, j.obj_a, j.obj_b, j.probe, j.corner, j.shift)
-            o = j.out
-            o.setdefault("loss", torch.empty((), dtype=torch.float64, device=dev))
-            o.setdefault("g_a", torch.empty_like(j.obj_a))
-            o.setdefault("g_b", torch.empty_like(j.obj_b))
-            o.setdefault("g_probe", torch.empty_like(j.probe))
-            o.setdefault("g_shift", torch.empty((b, 2), dtype=torch.float32, device=dev))
-            if j.workspace is None:
-                j.workspace = ctx.workspace(j.geom, b)
-            cj = cjobs[i]
-            cj.g = j.geom.to_c()
-            cj.obj_a, cj.obj_b = j.obj_a.data_ptr(), j.obj_b.data_ptr()
-            cj.probe = torch.view_as_real(j.probe).data_ptr()
-            cj.corner, cj.shift, cj.batch = j.corner.data_ptr(), j.shift.data_ptr(), b
-            cj.i_meas = j.i_meas.data_ptr()
-            cj.loss, cj.g_a, cj.g_b = o["loss"].data_ptr(), o["g_a"].data_ptr(), o["g_b"].data_ptr()
-            cj.g_probe = torch.view_as_real(o["g_probe"]).data_ptr()
-            cj.g_shift = o["g_shift"].data_ptr()
-            cj.workspace, cj.ws_bytes = j.workspace.data_ptr(), j.workspace.numel()
-        self._cjobs = cjobs
+        self._cjobs = _job_structs(ctx, self.jobs)
         self._plan = ctypes.c_void_p(0)
-        check(load().adorym_plan_create(ctx._ctx, cjobs, len(self.jobs), ctypes.byref(self._plan)), ctx._ctx)
+        check(load().adorym_plan_create(ctx._ctx, self._cjobs, len(self.jobs), ctypes.byref(self._plan)), ctx._ctx)
 
     def run(self):
         self.ctx._bind_stream()
@@ -489,6 +520,33 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _job_structs(ctx: "Context", jobs):
+    """C job table of ``jobs`` (allocating missing outputs and workspaces)."""
+    dev = ctx.device
+    cjobs = (_lib.Job * len(jobs))()
+    for i, j in enumerate(jobs):
+        b = ctx._check_inputs(j.geom, j.obj_a, j.obj_b, j.probe, j.corner, j.shift)
+        o = j.out
+        o.setdefault("loss", torch.empty((), dtype=torch.float64, device=dev))
+        o.setdefault("g_a", torch.empty_like(j.obj_a))
+        o.setdefault("g_b", torch.empty_like(j.obj_b))
+        o.setdefault("g_probe", torch.empty_like(j.probe))
+        o.setdefault("g_shift", torch.empty((b, 2), dtype=torch.float32, device=dev))
+        if j.workspace is None:
+            j.workspace = ctx.workspace(j.geom, b)
+        cj = cjobs[i]
+        cj.g = j.geom.to_c()
+        cj.obj_a, cj.obj_b = j.obj_a.data_ptr(), j.obj_b.data_ptr()
+        cj.probe = torch.view_as_real(j.probe).data_ptr()
+        cj.corner, cj.shift, cj.batch = j.corner.data_ptr(), j.shift.data_ptr(), b
+        cj.i_meas = j.i_meas.data_ptr()
+        cj.loss, cj.g_a, cj.g_b = o["loss"].data_ptr(), o["g_a"].data_ptr(), o["g_b"].data_ptr()
+        cj.g_probe = torch.view_as_real(o["g_probe"]).data_ptr()
+        cj.g_shift = o["g_shift"].data_ptr()
+        cj.workspace, cj.ws_bytes = j.workspace.data_ptr(), j.workspace.numel()
+    return cjobs
 
 
 def supports_n(n: int) -> bool:

@@ -52,9 +52,41 @@ class MultisliceLoss(torch.autograd.Function):
         return ga, gb, gp, gs, None, None, None
 
 
+class MultisliceLossLazy(torch.autograd.Function):
+    """The same loss with gradients only when backward runs: forward computes
+    the loss and keeps the slice checkpoints and exit waves in a workspace
+    (adorym_loss_fwd); backward resumes from them (adorym_loss_bwd)."""
+
+    @staticmethod
+    def forward(fctx, obj_a, obj_b, probe, positions, i_meas, geom: Geometry, lib: Optional[Context]):
+        lib = lib or _context(obj_a.device)
+        corner, shift = split_positions(positions.detach())
+        args = (obj_a.detach().contiguous(), obj_b.detach().contiguous(), probe.detach().contiguous(), corner,
+                shift, i_meas.contiguous())
+        loss, ws = lib.loss_fwd(geom, *args)
+        fctx.lib, fctx.geom, fctx.args, fctx.ws = lib, geom, args, ws
+        fctx.pos_dtype = positions.dtype
+        return loss
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        out = fctx.lib.loss_bwd(fctx.geom, *fctx.args, workspace=fctx.ws)
+        fctx.ws = None
+        s = grad_out.to(torch.float32)
+        ga = out["g_a"] * s if fctx.needs_input_grad[0] else None
+        gb = out["g_b"] * s if fctx.needs_input_grad[1] else None
+        gp = out["g_probe"] * s.to(torch.complex64) if fctx.needs_input_grad[2] else None
+        gs = (out["g_shift"] * s).to(fctx.pos_dtype) if fctx.needs_input_grad[3] else None
+        return ga, gb, gp, gs, None, None, None
+
+
 def multislice_loss(obj_a: torch.Tensor, obj_b: torch.Tensor, probe: torch.Tensor, positions: torch.Tensor,
-                    i_meas: torch.Tensor, geom: Geometry, ctx: Optional[Context] = None) -> torch.Tensor:
-    """Differentiable loss of one minibatch; see the module docstring."""
+                    i_meas: torch.Tensor, geom: Geometry, ctx: Optional[Context] = None,
+                    lazy: bool = False) -> torch.Tensor:
+    """Differentiable loss of one minibatch; see the module docstring.  With
+    ``lazy`` the gradients are computed only if backward runs."""
+    if lazy:
+        return MultisliceLossLazy.apply(obj_a, obj_b, probe, positions, i_meas, geom, ctx)
     return MultisliceLoss.apply(obj_a, obj_b, probe, positions, i_meas, geom, ctx)
 
 

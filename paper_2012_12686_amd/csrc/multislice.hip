@@ -454,7 +454,7 @@ adorym_status adorym_loss_grad_modes(adorym_ctx* ctx, const adorym_geom* g, cons
 #define ADORYM_RUN_SPLIT(N_, L_, K_)                                                                               \
   return run_split<N_, L_, K_>(ctx, gm, obj_a, obj_b, pm, corner, shift, batch, with_loss ? i_meas : nullptr, ws, \
                                ckpt_of(m), exit_of(m), with_loss ? loss : nullptr, with_loss ? g_a : nullptr,      \
-                               with_loss ? g_b : nullptr, gp, with_loss ? g_shift : nullptr, inten, with_loss)
+                               with_loss ? g_b : nullptr, gp, with_loss ? g_shift : nullptr, inten, with_loss, 1.0f)
     switch (g->n) {
       case 64: ADORYM_RUN_SPLIT(64, 8, 1);
       case 96: ADORYM_RUN_SPLIT(96, 8, 1);
@@ -488,6 +488,156 @@ adorym_status adorym_loss_grad_modes(adorym_ctx* ctx, const adorym_geom* g, cons
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
   return ADORYM_OK;
+}
+
+// ---- Loss first, gradients later -----------------------------------------
+// Workspace: a loss-and-gradient workspace, the intensity plane, the
+// checkpoints and exit waves kept between the calls, loss partials and a
+// scratch loss.
+namespace {
+struct FwdLayout { size_t inten, ckpt, exit, part, scratch, total; };
+FwdLayout fwd_layout(const adorym_geom* g, int batch) {
+  FwdLayout l{};
+  size_t off = adorym_workspace_size(g, batch);
+  l.inten = off; off += align256((size_t)batch * g->n * g->n * sizeof(float));
+  l.ckpt = off; off += split_ckpt_bytes(g, batch);
+  l.exit = off; off += split_exit_bytes(g, batch);
+  l.part = off; off += align256(kLossBlocks * sizeof(double));
+  l.scratch = off; off += 256;
+  l.total = off;
+  return l;
+}
+
+adorym_status split_pass(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b, const float* probe,
+                         const int32_t* corner, const float* shift, int batch, const float* i_meas, void* ws,
+                         float2* ckpt, float2* exit_wave, double* loss, float* g_a, float* g_b, float* g_probe,
+                         float* g_shift, float* intensity, bool with_loss, float adj_scale) {
+#define ADORYM_RUN_SPLIT(N_, L_, K_)                                                                                \
+  return run_split<N_, L_, K_>(ctx, g, a, b, probe, corner, shift, batch, i_meas, ws, ckpt, exit_wave, loss, g_a, \
+                               g_b, g_probe, g_shift, intensity, with_loss, adj_scale)
+  switch (g->n) {
+    case 64: ADORYM_RUN_SPLIT(64, 8, 1);
+    case 96: ADORYM_RUN_SPLIT(96, 8, 1);
+    case 128: ADORYM_RUN_SPLIT(128, 16, 4);
+    case 192: ADORYM_RUN_SPLIT(192, 16, 6);
+  }
+#undef ADORYM_RUN_SPLIT
+  return set_err(ctx, ADORYM_EUNSUPPORTED, "no kernel for this probe size");
+}
+}  // namespace
+
+size_t adorym_loss_fwd_workspace_size(const adorym_geom* g, int32_t batch) {
+  if (adorym_workspace_size(g, batch) == 0) return 0;
+  return fwd_layout(g, batch).total;
+}
+
+adorym_status adorym_loss_fwd(adorym_ctx* ctx, const adorym_geom* g, const float* obj_a, const float* obj_b,
+                              const float* probe, const int32_t* corner, const float* shift, int32_t batch,
+                              const float* i_meas, void* workspace, size_t ws_bytes, double* loss,
+                              float* intensity) {
+  adorym_status st = check_geom(ctx, g, batch);
+  if (st != ADORYM_OK) return st;
+  if (!obj_a || !obj_b || !probe || !corner || !shift || !i_meas || !workspace || !loss)
+    return set_err(ctx, ADORYM_EINVAL, "NULL array argument");
+  if (ws_bytes < adorym_loss_fwd_workspace_size(g, batch)) return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
+  const FwdLayout l = fwd_layout(g, batch);
+  char* base = static_cast<char*>(workspace);
+  float* inten = reinterpret_cast<float*>(base + l.inten);
+  st = split_pass(ctx, g, obj_a, obj_b, probe, corner, shift, batch, nullptr, workspace,
+                  reinterpret_cast<float2*>(base + l.ckpt), reinterpret_cast<float2*>(base + l.exit), nullptr, nullptr,
+                  nullptr, nullptr, nullptr, inten, false, 1.0f);
+  if (st != ADORYM_OK) return st;
+  const size_t n = (size_t)batch * g->n * g->n;
+  double* part = reinterpret_cast<double*>(base + l.part);
+  hipLaunchKernelGGL(loss_value_kernel, dim3(kLossBlocks), dim3(256), 0, ctx->stream, inten, i_meas, n, g->loss,
+                     (float)g->eps, part);
+  hipLaunchKernelGGL(finish_loss_kernel, dim3(1), dim3(256), 0, ctx->stream, part, 1.0 / (double)n, loss);
+  if (intensity) (void)hipMemcpyAsync(intensity, inten, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
+  return ADORYM_OK;
+}
+
+adorym_status adorym_loss_bwd(adorym_ctx* ctx, const adorym_geom* g, const float* obj_a, const float* obj_b,
+                              const float* probe, const int32_t* corner, const float* shift, int32_t batch,
+                              const float* i_meas, void* workspace, size_t ws_bytes, double grad_scale, float* g_a,
+                              float* g_b, float* g_probe, float* g_shift) {
+  adorym_status st = check_geom(ctx, g, batch);
+  if (st != ADORYM_OK) return st;
+  if (!obj_a || !obj_b || !probe || !corner || !shift || !i_meas || !workspace)
+    return set_err(ctx, ADORYM_EINVAL, "NULL array argument");
+  if ((g_a == nullptr) != (g_b == nullptr)) return set_err(ctx, ADORYM_EINVAL, "g_a and g_b must both be given");
+  if (!(grad_scale == grad_scale) || grad_scale > 3.0e38 || grad_scale < -3.0e38)
+    return set_err(ctx, ADORYM_EINVAL, "grad_scale must be a finite float32 value");
+  if (ws_bytes < adorym_loss_fwd_workspace_size(g, batch)) return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
+  const FwdLayout l = fwd_layout(g, batch);
+  char* base = static_cast<char*>(workspace);
+  return split_pass(ctx, g, obj_a, obj_b, probe, corner, shift, batch, i_meas, workspace,
+                    reinterpret_cast<float2*>(base + l.ckpt), reinterpret_cast<float2*>(base + l.exit),
+                    reinterpret_cast<double*>(base + l.scratch), g_a, g_b, g_probe, g_shift, nullptr, true,
+                    (float)grad_scale);
+}
+
+// ---- Many jobs in one call ---------------------------------------------------
+adorym_status adorym_loss_grad_batched(adorym_ctx* ctx, const adorym_job* jobs, int32_t n_jobs) {
+  adorym_plan* plan = nullptr;
+  adorym_status st = adorym_plan_create(ctx, jobs, n_jobs, &plan);
+  if (st != ADORYM_OK) return st;
+  st = adorym_plan_run(ctx, plan);
+  const hipError_t e = hipStreamSynchronize(ctx->stream);     // the plan's tables are freed next
+  const adorym_status st2 = adorym_plan_destroy(plan);
+  if (st != ADORYM_OK) return st;
+  if (e != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
+  return st2;
+}
+
+// ---- Split per probe size from timed plan runs ------------------------------
+adorym_status adorym_autotune(adorym_ctx* ctx, const adorym_job* jobs, int32_t n_jobs, int32_t reps,
+                              int32_t* chosen) {
+  if (!ctx) return ADORYM_EINVAL;
+  if (!jobs || n_jobs < 1 || reps < 1) return set_err(ctx, ADORYM_EINVAL, "jobs and reps >= 1 are required");
+  static const int kSizes[4] = {64, 96, 128, 192};
+  static const int kCand[4][4] = {{1, 2, 4, 0}, {1, 2, 3, 4}, {1, 2, 4, 8}, {2, 4, 6, 8}};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, "event creation failed");
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return set_err(ctx, ADORYM_EDEVICE, "event creation failed"); }
+  adorym_status st = ADORYM_OK;
+  for (int si = 0; si < 4 && st == ADORYM_OK; ++si) {
+    const int n = kSizes[si];
+    std::vector<adorym_job> sub;
+    for (int i = 0; i < n_jobs; ++i)
+      if (jobs[i].g.n == n && !(jobs[i].g.flags & ADORYM_DETERMINISTIC)) sub.push_back(jobs[i]);
+    if (sub.empty()) {
+      if (chosen) chosen[si] = split_of(ctx, n);
+      continue;
+    }
+    int best = 0;
+    float best_ms = 0.f;
+    for (int c = 0; c < 4 && st == ADORYM_OK; ++c) {
+      const int k = kCand[si][c];
+      if (k == 0) continue;
+      st = adorym_set_split(ctx, n, k);
+      adorym_plan* plan = nullptr;
+      if (st == ADORYM_OK) st = adorym_plan_create(ctx, sub.data(), (int32_t)sub.size(), &plan);
+      if (st != ADORYM_OK) break;
+      st = adorym_plan_run(ctx, plan);                     // warm-up
+      (void)hipEventRecord(e0, ctx->stream);
+      for (int r = 0; r < reps && st == ADORYM_OK; ++r) st = adorym_plan_run(ctx, plan);
+      (void)hipEventRecord(e1, ctx->stream);
+      float ms = 0.f;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        st = set_err(ctx, ADORYM_EDEVICE, "timing failed");
+      (void)adorym_plan_destroy(plan);
+      if (st == ADORYM_OK && (best == 0 || ms < best_ms)) { best = k; best_ms = ms; }
+    }
+    if (st == ADORYM_OK) {
+      st = adorym_set_split(ctx, n, best);
+      if (chosen) chosen[si] = best;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
 }
 
 adorym_status adorym_sync_error(adorym_ctx* ctx) {

@@ -73,6 +73,7 @@ struct MsParams {
   int loss;                // ADORYM_LOSS_*
   int ksplit;              // workgroups per position of the launch that fills the partials
   float kdz;               // k * dz
+  float adj_scale;         // multiplies the adjoint's seed, so every gradient (1: dL/d.)
   double chirp;            // lambda dz / dx^2
   double eps;
   double inv_n;            // 1 / (B N^2)
@@ -722,7 +723,7 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
       }
       lsum += (double)term;
       // far-field residual 2 dL/dI Psi, scaled by 1/N for the adjoint DFT
-      v[m] = cscale(psi_det, 2.0f * dldi * inv_nf);
+      v[m] = cscale(psi_det, 2.0f * dldi * (inv_nf * P.adj_scale));
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -1196,6 +1197,7 @@ MsParams make_params(adorym_ctx* ctx, const adorym_geom* g, const float* a, cons
   P.kdz = (float)(2.0 * M_PI / g->wavelength_m * g->slice_dz_m);
   P.chirp = g->wavelength_m * g->slice_dz_m / (g->pixel_m * g->pixel_m);
   P.eps = g->eps;
+  P.adj_scale = 1.0f;
   P.inv_n = 1.0 / ((double)batch * g->n * g->n);
   return P;
 }
@@ -1439,6 +1441,46 @@ adorym_status run_nf(adorym_ctx* ctx, const adorym_geom* g, const float* a, cons
   return ADORYM_OK;
 }
 
+// Loss of predicted intensities (per-pixel terms in FP32 as in the fused
+// kernel, the mean over the n pixels in FP64): a fixed grid-stride split and
+// a fixed-order tree per workgroup, partials summed by finish_loss_kernel.
+constexpr int kLossBlocks = 256;
+static __global__ void __launch_bounds__(256) loss_value_kernel(const float* __restrict__ ip,
+                                                                const float* __restrict__ im, size_t n, int kind,
+                                                                float eps, double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const float p = ip[i], m = im[i];
+    float term;
+    if (kind == ADORYM_LOSS_GAUSSIAN) {
+      const float d = sqrtf(p + eps) - sqrtf(m + eps);
+      term = d * d;
+    } else {
+      term = p - m * logf(p + eps);
+    }
+    s += (double)term;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+static __global__ void __launch_bounds__(256) finish_loss_kernel(const double* __restrict__ part, double inv_n,
+                                                                 double* __restrict__ loss) {
+  __shared__ double red[256];
+  red[threadIdx.x] = part[threadIdx.x];      // kLossBlocks == 256
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = red[0] * inv_n;
+}
+
 // ---- Split evaluation (several probe modes) ------------------------------
 // Per-mode storage between the passes: the checkpoints and the exit wave.
 inline size_t split_ckpt_bytes(const adorym_geom* g, int batch) {
@@ -1456,13 +1498,14 @@ template <int N, int L, int K>
 adorym_status run_split(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b, const float* probe,
                         const int32_t* corner, const float* shift, int batch, const float* i_meas, void* ws,
                         float2* ckpt, float2* exit_wave, double* loss, float* g_a, float* g_b, float* g_probe,
-                        float* g_shift, float* intensity, bool with_loss) {
+                        float* g_shift, float* intensity, bool with_loss, float adj_scale) {
   using C = TileCfg<N, L, K>;
   MsParams P = make_params<N, probe_lanes<N>()>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
                                     with_loss ? g_a : nullptr, with_loss ? g_b : nullptr, intensity);
   P.ksplit = K;
   P.ckpt = ckpt;
   P.exit_wave = exit_wave;
+  P.adj_scale = adj_scale;
   hipStream_t st = ctx->stream;
   const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
   launch_prologue<N, probe_lanes<N>()>(P, probe, g, st);
@@ -1510,7 +1553,7 @@ void launch_batched(const MsParams* jobs, const int2* items, int n_items, int* t
   adorym_status adorym_ms::run_split<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, const float*, \
                                                  const float*, const int32_t*, const float*, int, const float*, \
                                                  void*, float2*, float2*, double*, float*, float*, float*, float*, \
-                                                 float*, bool)
+                                                 float*, bool, float)
 #define ADORYM_RUN_NF_SIGNATURE(N_, L_, K_) \
   adorym_status adorym_ms::run_nf<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, const float*, \
                                               const float*, const int32_t*, const float*, int, int, const double*, \
