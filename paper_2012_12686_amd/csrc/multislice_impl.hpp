@@ -178,11 +178,18 @@ __device__ __forceinline__ void xfer2(float2 (&v0)[C::R], float2 (&v1)[C::R], Ms
 }
 
 // Fresnel propagation of one field along the thread's lines; the input is
-// stashed in the thread's own cells of the LDS field buffer.  K == 1 tiles
+// stashed in the thread's own cells of the LDS field buffer (or, for split
+// fields with at most 8 values per lane, in registers).  K == 1 tiles
 // share that buffer with the transposes, so they wait first: other waves may
 // still be reading the row from the last transpose.
 template <class C, bool CONJ>
 __device__ __forceinline__ void prop(float2 (&v)[C::R], MsShared<C>& sh, const Lane<C>& ln) {
+  // split fields with at most 8 values per lane keep the input in registers
+  // (no LDS round trip; the register budget allows it)
+  if constexpr (C::K > 1 && C::R <= 8) {
+    propagate_line<C, CONJ>(v, sh.tb, ln);
+    return;
+  }
   if constexpr (C::K == 1) __syncthreads();
   propagate_line<C, CONJ>(v, sh.tb, ln, sh.buf + (ln.w * C::RPW + ln.g) * C::PITCH);
 }
