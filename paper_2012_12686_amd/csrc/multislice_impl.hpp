@@ -179,14 +179,15 @@ __device__ __forceinline__ void xfer2(float2 (&v0)[C::R], float2 (&v1)[C::R], Ms
 
 // Fresnel propagation of one field along the thread's lines; the input is
 // stashed in the thread's own cells of the LDS field buffer (or, for split
-// fields with at most 8 values per lane, in registers).  K == 1 tiles
-// share that buffer with the transposes, so they wait first: other waves may
-// still be reading the row from the last transpose.
-template <class C, bool CONJ>
+// fields with at most 8 values per lane, in registers, unless REGS is
+// false).  K == 1 tiles share that buffer with the transposes, so they wait
+// first: other waves may still be reading the row from the last transpose.
+template <class C, bool CONJ, bool REGS = true>
 __device__ __forceinline__ void prop(float2 (&v)[C::R], MsShared<C>& sh, const Lane<C>& ln) {
   // split fields with at most 8 values per lane keep the input in registers
-  // (no LDS round trip; the register budget allows it)
-  if constexpr (C::K > 1 && C::R <= 8) {
+  // (no LDS round trip; the register budget allows it except where the
+  // unequal-spacing gradient already holds more live values)
+  if constexpr (REGS && C::K > 1 && C::R <= 8) {
     propagate_line<C, CONJ>(v, sh.tb, ln);
     return;
   }
@@ -377,9 +378,9 @@ __device__ __forceinline__ void forward_slice(float2 (&v)[C::R], float (&ca)[C::
   modulate<C, REPR>(v, ca, cb, P.kdz);
   if (j < P.S - 1) {
     if constexpr (VAR) gap_table<C>(sh, P, wk.ln, j);
-    prop<C, false>(v, sh, wk.ln);
+    prop<C, false, !VAR>(v, sh, wk.ln);
     xfer<C>(v, sh, wk, false, false);
-    prop<C, false>(v, sh, wk.ln);
+    prop<C, false, !VAR>(v, sh, wk.ln);
   }
 }
 
@@ -436,17 +437,17 @@ __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam
         gap_table<C>(sh, P, ln, j - 1);
         gacc = gap_term<C>(psi, lam, sh.tb, ln);
       }
-      prop<C, true>(psi, sh, ln);
-      prop<C, true>(lam, sh, ln);
+      prop<C, true, !VAR>(psi, sh, ln);
+      prop<C, true, !VAR>(lam, sh, ln);
       xfer2<C>(psi, lam, sh, wk, false, false);
       if constexpr (VAR) gacc += gap_term<C>(psi, lam, sh.tb, ln);
-      prop<C, true>(psi, sh, ln);
-      prop<C, true>(lam, sh, ln);
+      prop<C, true, !VAR>(psi, sh, ln);
+      prop<C, true, !VAR>(lam, sh, ln);
       if constexpr (VAR) gap_store<C>(P, sh, wk, j - 1, gacc);
     } else {
-      prop<C, true>(lam, sh, ln);
+      prop<C, true, !VAR>(lam, sh, ln);
       xfer<C>(lam, sh, wk, false, false);
-      prop<C, true>(lam, sh, ln);
+      prop<C, true, !VAR>(lam, sh, ln);
     }
   }
 }
@@ -467,11 +468,11 @@ __device__ __forceinline__ void forward_slice_pf(float2 (&v)[C::R], float2 (&t)[
     if constexpr (VAR) gap_table<C>(sh, P, wk.ln, j);
     float ca[C::R], cb[C::R];
     load_chunk<C, !ROW>(ca, cb, P, o, j + 1);   // in flight during the propagation
-    prop<C, false>(v, sh, wk.ln);
+    prop<C, false, !VAR>(v, sh, wk.ln);
     xfer_begin<C, 1>(v, v, sh, wk, false, false);
     make_trans<C, REPR, false>(t, g2, ca, cb, P.kdz);
     xfer_end<C, 1>(v, v, wk, false);
-    prop<C, false>(v, sh, wk.ln);
+    prop<C, false, !VAR>(v, sh, wk.ln);
   }
 }
 
@@ -520,21 +521,21 @@ __device__ __forceinline__ void backward_slice_pf(float2 (&psi)[C::R], float2 (&
     // unequal spacing: the gap gradient needs psi across the gap every time
     const bool need_psi = VAR || !is_ckpt(j - 1, P.S, P.ckpt_every);
     if (need_psi) {
-      prop<C, true>(psi, sh, ln);
-      prop<C, true>(lam, sh, ln);
+      prop<C, true, !VAR>(psi, sh, ln);
+      prop<C, true, !VAR>(lam, sh, ln);
       xfer_begin<C, 2>(psi, lam, sh, wk, false, false);
       make_trans<C, REPR, true>(t, g2, ca, cb, kdz);
       xfer_end<C, 2>(psi, lam, wk, false);
       if constexpr (VAR) gacc += gap_term<C>(psi, lam, sh.tb, ln);
-      prop<C, true>(psi, sh, ln);
-      prop<C, true>(lam, sh, ln);
+      prop<C, true, !VAR>(psi, sh, ln);
+      prop<C, true, !VAR>(lam, sh, ln);
       if constexpr (VAR) gap_store<C>(P, sh, wk, j - 1, gacc);
     } else {
-      prop<C, true>(lam, sh, ln);
+      prop<C, true, !VAR>(lam, sh, ln);
       xfer_begin<C, 1>(lam, lam, sh, wk, false, false);
       make_trans<C, REPR, true>(t, g2, ca, cb, kdz);
       xfer_end<C, 1>(lam, lam, wk, false);
-      prop<C, true>(lam, sh, ln);
+      prop<C, true, !VAR>(lam, sh, ln);
     }
   }
 }
