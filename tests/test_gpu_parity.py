@@ -179,6 +179,52 @@ def test_chunk_out_of_range_is_flagged_and_skipped(ctx):
     ctx.sync_error()   # flag was cleared
 
 
+def test_empty_minibatch_is_rejected_and_the_context_stays_usable(ctx):
+    """The loss is a mean over the B N^2 pixels of the minibatch (Eqs.
+    lsq_loss, poisson_loss, normalised per pixel), undefined for B = 0: every
+    entry point refuses an empty minibatch with EINVAL before any device
+    work, and later calls are unaffected."""
+    import torch
+    from paper_2012_12686_amd._lib import AdorymError, EINVAL
+    sc = synth.small_case(seed=35, n=64, n_slices=3, lateral=96, n_pos=3, strength=30.0)
+    case = Case(sc)
+    inp, i_meas = case.torch_inputs()
+    g = _geom(case)
+    before = ctx.loss_grad(g, **inp, i_meas=i_meas, intensity=True)
+    before = {k: v.cpu().numpy() for k, v in before.items()}
+    empty = dict(inp, corner=inp["corner"][:0].contiguous(), shift=inp["shift"][:0].contiguous())
+    i0 = i_meas[:0].contiguous()
+    dev = inp["obj_a"].device
+    gaps = torch.full((sc.n_slices - 1,), 1e-8, dtype=torch.float64, device=dev)
+    dists = torch.tensor([1e-6], dtype=torch.float64, device=dev)
+    idx0 = torch.zeros(0, dtype=torch.int32, device=dev)
+    probes = inp["probe"][None].contiguous()
+    modes_inp = {k: v for k, v in empty.items() if k != "probe"}
+    calls = {
+        "forward": lambda: ctx.forward(g, **empty),
+        "loss_grad": lambda: ctx.loss_grad(g, **empty, i_meas=i0),
+        "forward_gaps": lambda: ctx.forward_gaps(g, **empty, gaps=gaps),
+        "loss_grad_gaps": lambda: ctx.loss_grad_gaps(g, **empty, gaps=gaps, i_meas=i0),
+        "forward_nearfield": lambda: ctx.forward_nearfield(g, **empty, dists=dists, dist_idx=idx0),
+        "loss_grad_nearfield": lambda: ctx.loss_grad_nearfield(g, **empty, dists=dists, dist_idx=idx0, i_meas=i0),
+        "loss_grad_modes": lambda: ctx.loss_grad_modes(g, probes=probes, **modes_inp, i_meas=i0),
+        "loss_fwd": lambda: ctx.loss_fwd(g, **empty, i_meas=i0),
+    }
+    for name, call in calls.items():
+        with pytest.raises(AdorymError) as ei:
+            call()
+        assert ei.value.status == EINVAL, name
+        assert "batch" in str(ei.value), (name, str(ei.value))
+    torch.cuda.synchronize()
+    ctx.sync_error()          # nothing was enqueued, no deferred error
+    after = ctx.loss_grad(g, **inp, i_meas=i_meas, intensity=True)
+    after = {k: v.cpu().numpy() for k, v in after.items()}
+    assert np.array_equal(before["intensity"], after["intensity"])
+    for k in ("g_a", "g_b", "g_probe", "g_shift"):
+        assert rel_l2(after[k], before[k]) <= 1e-6, k
+    assert rel_l2(after["intensity"], case.oracle_forward()) <= TOL_I
+
+
 def test_loss_is_deterministic(ctx):
     sc = synth.small_case(seed=34, n=64, n_slices=6, lateral=96, n_pos=5, strength=30.0)
     case = Case(sc)
