@@ -409,7 +409,7 @@ def test_config3_full_minibatch_sampled_positions(ctx):
     pos_t = (inp["corner"].double() + inp["shift"].double()).requires_grad_(True)
     loss = multislice_loss(a, inp["obj_b"], inp["probe"], pos_t, im, geom, ctx)
     loss.backward()
-    assert float(loss) == float(out["loss"])
+    assert float(loss.detach()) == float(out["loss"])
     assert torch.equal(a.grad, out["g_a"])
     assert torch.equal(pos_t.grad.float(), out["g_shift"])
 
