@@ -172,7 +172,7 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    sc = synth.config2()
+    sc = synth.multislice_n128_s64()
     n, s = sc.n, sc.n_slices
     mb = sc.minibatch
     n_mb = len(sc.positions) // mb
@@ -387,7 +387,7 @@ def bench_differentiation(args):
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    sc = synth.config3()
+    sc = synth.multislice_n128_s128()
     n, s, mb = sc.n, sc.n_slices, sc.minibatch
     n_mb = len(sc.positions) // mb
     ctx = Context(dev)
@@ -562,7 +562,7 @@ def bench_priors(args):
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    sc = synth.config3()
+    sc = synth.multislice_n128_s128()
     ctx = Context(dev)
     a = torch.as_tensor(sc.obj_a, dtype=torch.float32, device=dev).contiguous()
     b = torch.as_tensor(sc.obj_b, dtype=torch.float32, device=dev).contiguous()
@@ -630,7 +630,7 @@ def bench_batching(args):
     torch.cuda.set_device(dev)
     ctx = Context(dev)
     t0 = time.perf_counter()
-    scans = [to_device_scan(ctx, sc, seed=i) for i, sc in enumerate(synth.config4_jobs())]
+    scans = [to_device_scan(ctx, sc, seed=i) for i, sc in enumerate(synth.mixed_scan_jobs())]
     torch.cuda.synchronize()
     prep_s = time.perf_counter() - t0
     runner = BatchRunner(ctx, scans)

@@ -526,16 +526,16 @@ def poisson_arrivals(rate_per_s: float, count: int, seed: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# The serving workload: Poisson arrivals of c1 / c2 / c3 / tilt-series jobs
+# The serving workload: Poisson arrivals of 2D, 64-slice, 128-slice and tilt-series jobs
 # ---------------------------------------------------------------------------
 
 def build_templates(ctx: Context, tilt_angles: int = 20) -> Dict[str, Template]:
     """The four job types of the serving mix (synthetic inputs, see synth)."""
     import synth
     tpl = {
-        "c1": scan_template(ctx, synth.config1(), "c1", seed=11, lr=1e-3),
-        "c2": scan_template(ctx, synth.config2(), "c2", seed=12),
-        "c3": scan_template(ctx, synth.config3(), "c3", seed=13),
+        "ptycho2d_n64": scan_template(ctx, synth.ptycho2d_n64(), "ptycho2d_n64", seed=11, lr=1e-3),
+        "multislice_s64": scan_template(ctx, synth.multislice_n128_s64(), "multislice_s64", seed=12),
+        "multislice_s128": scan_template(ctx, synth.multislice_n128_s128(), "multislice_s128", seed=13),
     }
     scan, angles = synth.tilt_job()
     # a job's 20 iterations visit 20 of the 90 angles, spread over 180 degrees
@@ -548,7 +548,7 @@ def build_templates(ctx: Context, tilt_angles: int = 20) -> Dict[str, Template]:
 def serving_requests(templates: Dict[str, Template], n_jobs: int, rate: float, seed: int = 5,
                      iterations: int = 20) -> List[Request]:
     rng = np.random.default_rng(seed)
-    names = sorted(templates)
+    names = list(templates)          # job types in the dict's insertion order
     kinds = rng.integers(0, len(names), size=n_jobs)
     times = poisson_arrivals(rate, n_jobs, seed + 1)
     return [Request(float(t), templates[names[k]], iterations) for t, k in zip(times, kinds)]
@@ -592,7 +592,9 @@ def bench_serving(args):
         "value": streamed["positions_per_s"], "unit": "positions/s", "n_gpus": 1, "steps": streamed["ticks"],
         "warmup": 1, "ms_per_step": streamed["wall_s"] * 1e3 / max(streamed["ticks"], 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{n_jobs} jobs, Poisson arrivals {rate}/s, types c1/c2/c3/tilt uniform, "
+        "config": {"workload": f"{n_jobs} jobs, Poisson arrivals {rate}/s, types uniform over 2D ptychography "
+                               "(N=64, 128x128), 64-slice (N=128, 256x256x64), 128-slice (N=128, 512x512x128) "
+                               "and tilt series (N=128, 256^3), "
                                "20 iterations each (minibatch or angle + Adam); jobs admitted by HBM footprint "
                                "and iterating concurrently on 4 streams"},
         "p50_iter_ms": streamed["p50_iter_ms"], "p99_iter_ms": streamed["p99_iter_ms"],

@@ -145,7 +145,7 @@ def raster(side_y, side_x, origin, step, jitter=0.0, rng=None):
 # The five workloads
 # ---------------------------------------------------------------------------
 
-def config1(seed: int = 1) -> Scan:
+def ptycho2d_n64(seed: int = 1) -> Scan:
     """Plain 2D ptychography, one thin slice, complex (real/imag) object.
 
     Object 128x128: amplitude U[0.9, 1], phase Gaussian-smoothed (sigma 3 px)
@@ -159,14 +159,14 @@ def config1(seed: int = 1) -> Scan:
     obj = amp * np.exp(1j * ph)
     probe = gaussian_probe(rng, 64, 12.0, 4.0)
     pos = raster(8, 8, 4.0, 8.0)
-    return Scan(name="c1_ptycho2d_n64", n=64, obj_a=obj.real[None].copy(), obj_b=obj.imag[None].copy(),
+    return Scan(name="ptycho2d_n64", n=64, obj_a=obj.real[None].copy(), obj_b=obj.imag[None].copy(),
                 probe=probe, positions=pos, wavelength_m=wavelength_from_energy(8801.0),
                 pixel_m=13.2e-9, slice_dz_m=13.2e-9, obj_repr="real_imag", loss="gaussian",
                 minibatch=64,
                 eval_obj_a=np.ones((1, 128, 128)), eval_obj_b=np.zeros((1, 128, 128)))
 
 
-def config2(seed: int = 2, n_slices: int = 64, lateral: int = 256) -> Scan:
+def multislice_n128_s64(seed: int = 2, n_slices: int = 64, lateral: int = 256) -> Scan:
     """Multislice ptychography at 10 keV, delta/beta volume 256x256x64, 10 nm.
 
     24 random ellipsoids; probe 128x128 (Gaussian sigma 24 px, smooth phase);
@@ -179,13 +179,13 @@ def config2(seed: int = 2, n_slices: int = 64, lateral: int = 256) -> Scan:
     probe = gaussian_probe(rng, 128, 24.0, 8.0)
     pos = raster(20, 20, 7.0, 6.0, jitter=2.0, rng=rng)
     z = np.zeros_like(delta)
-    return Scan(name="c2_multislice_n128_s64", n=128, obj_a=delta, obj_b=beta, probe=probe,
+    return Scan(name="multislice_n128_s64", n=128, obj_a=delta, obj_b=beta, probe=probe,
                 positions=pos, wavelength_m=wavelength_from_energy(10000.0), pixel_m=10e-9,
                 slice_dz_m=10e-9, obj_repr="delta_beta", loss="poisson", minibatch=50,
                 eval_obj_a=z, eval_obj_b=z, photons=1e4)
 
 
-def config3(seed: int = 3) -> Scan:
+def multislice_n128_s128(seed: int = 3) -> Scan:
     """Differentiation workload: 512x512x128 delta/beta, 1024 positions.
 
     64 ellipsoids; probe as in config 2; 32x32 raster, origin 6, step 12;
@@ -199,14 +199,14 @@ def config3(seed: int = 3) -> Scan:
     nominal = raster(32, 32, 6.0, 12.0)
     true_pos = nominal + rng.uniform(-1.0, 1.0, size=nominal.shape)
     noise = rng.standard_normal((128, 128)) + 1j * rng.standard_normal((128, 128))
-    return Scan(name="c3_grad_n128_s128", n=128, obj_a=delta, obj_b=beta, probe=probe,
+    return Scan(name="multislice_n128_s128", n=128, obj_a=delta, obj_b=beta, probe=probe,
                 positions=true_pos, wavelength_m=wavelength_from_energy(10000.0), pixel_m=10e-9,
                 slice_dz_m=10e-9, obj_repr="delta_beta", loss="gaussian", minibatch=200,
                 eval_obj_a=0.5 * delta, eval_obj_b=0.5 * beta,
                 eval_probe=probe * (1.0 + 0.05 * noise), eval_positions=nominal)
 
 
-def config3_fd_subcase(seed: int = 3) -> Scan:
+def fd_subcase_n16_s4(seed: int = 3) -> Scan:
     """Tiny finite-difference sub-case: 32x32x4 delta/beta, probe 16x16.
 
     3x3 raster, origin 1, step 7, probe sigma 3 px; fractional positions kept
@@ -217,7 +217,7 @@ def config3_fd_subcase(seed: int = 3) -> Scan:
                                    delta_range=(2e-4, 1e-3))
     probe = gaussian_probe(rng, 16, 3.0, 2.0, total=1e2)
     pos = raster(3, 3, 1.0, 7.0) + rng.uniform(-0.3, 0.3, size=(9, 2))
-    return Scan(name="c3_fd_n16_s4", n=16, obj_a=delta, obj_b=beta, probe=probe, positions=pos,
+    return Scan(name="fd_subcase_n16_s4", n=16, obj_a=delta, obj_b=beta, probe=probe, positions=pos,
                 wavelength_m=wavelength_from_energy(10000.0), pixel_m=10e-9, slice_dz_m=10e-9,
                 obj_repr="delta_beta", loss="gaussian", minibatch=9,
                 eval_obj_a=0.6 * delta, eval_obj_b=0.6 * beta,
@@ -226,7 +226,7 @@ def config3_fd_subcase(seed: int = 3) -> Scan:
                 eval_positions=pos + rng.uniform(-0.1, 0.1, size=pos.shape))
 
 
-def config4_jobs(seed: int = 4, n_jobs: int = 32):
+def mixed_scan_jobs(seed: int = 4, n_jobs: int = 32):
     """Batching workload: independent scans of uneven probe size and depth.
 
     Per job: N ~ U{64, 96, 128, 192}, S ~ U{1..64}, P ~ U{50..500}; raster
@@ -249,7 +249,7 @@ def config4_jobs(seed: int = 4, n_jobs: int = 32):
         delta, beta = ellipsoid_volume(rng, (s, lat, lat), 8 + s // 4)
         probe = gaussian_probe(rng, n, 0.1875 * n, n / 16.0)
         pos = raster(side, side, 2.0 + math.ceil(jit), step, jitter=jit, rng=rng)[:p]
-        jobs.append(Scan(name=f"c4_job{j}_n{n}_s{s}_p{p}", n=n, obj_a=delta, obj_b=beta, probe=probe,
+        jobs.append(Scan(name=f"mixed_job{j}_n{n}_s{s}_p{p}", n=n, obj_a=delta, obj_b=beta, probe=probe,
                          positions=pos, wavelength_m=wavelength_from_energy(10000.0), pixel_m=10e-9,
                          slice_dz_m=10e-9, obj_repr="delta_beta",
                          loss="poisson" if j % 2 == 0 else "gaussian", minibatch=p, photons=1e4,

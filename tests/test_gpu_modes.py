@@ -148,7 +148,7 @@ def test_modes_full_minibatch_sampled_positions(ctx):
     from oracle import multislice as om
     from paper_2012_12686_amd import Geometry
     from tests.fp32_model import loss_grad_fp32_modes
-    sc = synth.config2()
+    sc = synth.multislice_n128_s64()
     bsz, sample = 50, np.array([0, 25, 49])
     geom = om.Geometry.from_scan(sc)
     probes = f32(synth.probe_modes(sc.probe, 2, seed=11))

@@ -235,21 +235,21 @@ def test_loss_is_deterministic(ctx):
 
 # ------------------------------------------------------------------ the named workloads
 
-def test_config1_ptychography_2d(ctx):
+def test_ptychography_2d_n64(ctx):
     """64x64 probe, one slice, complex object 128x128, 64 raster positions, LSQ."""
-    case = Case(synth.config1())
+    case = Case(synth.ptycho2d_n64())
     got = run_grad(ctx, case)
     assert rel_l2(got["intensity"], case.oracle_forward()) <= TOL_I
     check_grads(got, case.oracle_loss_grad(), case)
 
 
-def test_config2_first_minibatch(ctx):
+def test_multislice_n128_s64_first_minibatch(ctx):
     """128x128 probe, 64 slices at 10 nm, 256x256 object, minibatch of 50, Poisson."""
-    sc = synth.config2()
+    sc = synth.multislice_n128_s64()
     case = Case(sc, idx=slice(0, 50), poisson_seed=2)
     got = run_grad(ctx, case)
     err_i = rel_l2(got["intensity"], case.oracle_forward())
-    print("c2 intensity rel-L2", err_i)
+    print("64-slice minibatch intensity rel-L2", err_i)
     assert err_i <= TOL_I
     check_grads(got, case.oracle_loss_grad(), case)
 
@@ -364,7 +364,7 @@ def test_deterministic_jobs_in_a_plan_equal_single_calls_bitwise(ctx):
     plan.close()
 
 
-def test_config3_full_minibatch_sampled_positions(ctx):
+def test_multislice_n128_s128_full_minibatch_sampled_positions(ctx):
     """512x512x128 object, 128 probe, a full minibatch of 200 positions, C = 16.
 
     The oracle evaluates three sampled positions one by one: their intensities
@@ -377,7 +377,7 @@ def test_config3_full_minibatch_sampled_positions(ctx):
     import torch
     from paper_2012_12686_amd import Geometry, multislice_loss
     from tests.fp32_model import loss_grad_fp32
-    sc = synth.config3()
+    sc = synth.multislice_n128_s128()
     bsz, sample = 200, np.array([0, 101, 199])
     case = Case(sc, idx=sample)
     pos_all = np.asarray(sc.eval_positions, dtype=np.float64)[:bsz]
@@ -395,14 +395,14 @@ def test_config3_full_minibatch_sampled_positions(ctx):
     ctx.sync_error()
     got_i = out["intensity"].cpu().numpy()[sample]
     err_i = rel_l2(got_i, case.oracle_forward())
-    print("c3 sampled intensity rel-L2", err_i)
+    print("128-slice minibatch, sampled intensity rel-L2", err_i)
     assert err_i <= TOL_I
     scale = len(sample) / bsz
     ref_gs = case.oracle_loss_grad()[4] * scale
     f32_gs = loss_grad_fp32(case.geom, case.a, case.b, case.p, case.pos, case.i_meas)[4] * scale
     got_gs = out["g_shift"].cpu().numpy()[sample]
     e_gpu, e_f32 = rel_l2(got_gs, ref_gs), rel_l2(f32_gs, ref_gs)
-    print(f"c3 sampled shift gradients: GPU rel-L2 {e_gpu:.3e}, float32-model floor {e_f32:.3e}")
+    print(f"128-slice minibatch, sampled shift gradients: GPU rel-L2 {e_gpu:.3e}, float32-model floor {e_f32:.3e}")
     assert e_gpu <= max(TOL_G, 3.0 * e_f32)
     # the autograd front end on the same inputs
     a = inp["obj_a"].clone().requires_grad_(True)
@@ -414,14 +414,14 @@ def test_config3_full_minibatch_sampled_positions(ctx):
     assert torch.equal(pos_t.grad.float(), out["g_shift"])
 
 
-def test_config2_first_minibatch_at_half_the_object(ctx):
+def test_multislice_n128_s64_first_minibatch_at_half_the_object(ctx):
     """The same minibatch evaluated at half the true object.  At the
     benchmark's vacuum start the far-field intensity does not depend on the
     probe position, so the shift gradients vanish there and are only
     compared against float32 noise; here they are non-zero and checked to
     the gradient tolerance like the others."""
     import dataclasses
-    sc = synth.config2()
+    sc = synth.multislice_n128_s64()
     sc = dataclasses.replace(sc, eval_obj_a=0.5 * sc.obj_a, eval_obj_b=0.5 * sc.obj_b)
     case = Case(sc, idx=slice(0, 50), poisson_seed=2)
     got = run_grad(ctx, case)

@@ -120,7 +120,7 @@ def test_prior_on_the_full_128_slice_object(ctx):
     128-slice workload, l1 + TV, added onto a data gradient; reproducible
     bit for bit."""
     import torch
-    sc = synth.config3()
+    sc = synth.multislice_n128_s128()
     a = sc.obj_a.astype(np.float32).astype(np.float64)
     b = sc.obj_b.astype(np.float32).astype(np.float64)
     ta, tb = _t(a), _t(b)

@@ -305,7 +305,7 @@ def test_probe_to_exit_map_adjoint():
 # ---------------------------------------------------------------- finite differences
 
 def _fd_case(loss, obj_repr="delta_beta"):
-    sc = synth.config3_fd_subcase()
+    sc = synth.fd_subcase_n16_s4()
     geom = om.Geometry(sc.n, sc.n_slices, sc.wavelength_m, sc.pixel_m, sc.slice_dz_m, obj_repr, loss)
     if obj_repr == "delta_beta":
         a, b = sc.eval_obj_a, sc.eval_obj_b
@@ -429,7 +429,7 @@ def _modes_case(loss="gaussian", n_modes=3):
     geom, a, b, p, pos, _ = _fd_case(loss, "delta_beta")
     rng = np.random.default_rng(7)
     probes = np.stack([p] + [0.4 * p * np.exp(1j * rng.uniform(-1, 1, p.shape)) for _ in range(n_modes - 1)])
-    sc = synth.config3_fd_subcase()
+    sc = synth.fd_subcase_n16_s4()
     i_true = om.forward_modes(geom, sc.obj_a, sc.obj_b, probes * 1.1, sc.positions)
     i_meas = i_true if loss == "gaussian" else rng.poisson(i_true).astype(float)
     return geom, a, b, probes, pos, i_meas
@@ -524,7 +524,7 @@ def _gaps_geom(geom, gaps, loss=None):
 
 def _gaps_case(loss="gaussian"):
     geom, a, b, p, pos, _ = _fd_case(loss)
-    sc = synth.config3_fd_subcase()
+    sc = synth.fd_subcase_n16_s4()
     truth = _gaps_geom(geom, GAPS)
     i_true = om.forward(truth, sc.obj_a, sc.obj_b, sc.probe, sc.positions)
     i_meas = i_true if loss == "gaussian" else np.random.default_rng(3).poisson(i_true).astype(float)
@@ -651,7 +651,7 @@ def test_sommerfeld_reduces_to_paraxial_at_small_angles():
     """H2 exp(+i k d) - H1 = O(k d lambda^4 |nu|^4 / 8): at 1 um pixels and
     hard X-rays the two near-field models agree to that order, and they
     part where the angle is large."""
-    sc = synth.config3_fd_subcase()
+    sc = synth.fd_subcase_n16_s4()
     lam = sc.wavelength_m
     for dx, d, close in ((1e-6, 0.4, True), (2e-10, 3e-8, False)):
         geom = om.Geometry(sc.n, sc.n_slices, lam, dx, sc.slice_dz_m)
@@ -695,7 +695,7 @@ def test_nearfield_distance_is_an_empty_last_slice():
 
 def _nf_case(loss, kind):
     geom, a, b, p, pos, _ = _fd_case(loss)
-    sc = synth.config3_fd_subcase()
+    sc = synth.fd_subcase_n16_s4()
     dists = np.array([0.6e-6, 1.4e-6])
     idx = np.arange(len(pos)) % 2
     i_true = om.forward_nearfield(geom, sc.obj_a, sc.obj_b, sc.probe, sc.positions, dists, idx, kind)
