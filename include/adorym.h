@@ -25,9 +25,13 @@
  *  - Every array pointer is a DEVICE pointer owned by the caller; the
  *    library never frees or retains it past the call.  Complex arrays are
  *    interleaved (re, im) float32 pairs.
- *  - All calls are asynchronous on the context's stream; no call
- *    synchronises the host or allocates device memory, except
- *    adorym_create / adorym_destroy / adorym_sync_error.
+ *  - Compute calls (forward, loss and gradient in every variant, priors,
+ *    rotation, Adam, plan_run) are asynchronous on the context's stream
+ *    and neither synchronise the host nor allocate device memory.  The
+ *    set-up and measurement calls do, as each one's comment says:
+ *    adorym_create / adorym_destroy, adorym_sync_error,
+ *    adorym_plan_create / adorym_plan_destroy, adorym_loss_grad_batched,
+ *    adorym_autotune, adorym_profile_start / adorym_profile_stop.
  *  - Host-checkable errors return at once and enqueue nothing.  Errors
  *    only the device can see (a chunk that leaves the object) set a
  *    sticky flag read by adorym_sync_error; the offending positions
@@ -340,7 +344,10 @@ adorym_status adorym_loss_grad_batched(adorym_ctx* ctx, const adorym_job* jobs, 
  * overwritten.  Allocates and synchronises: a set-up call. */
 adorym_status adorym_autotune(adorym_ctx* ctx, const adorym_job* jobs, int32_t n_jobs, int32_t reps,
                               int32_t* chosen);
+/* Runs every job of the plan on ctx's stream (kernel launches only). */
 adorym_status adorym_plan_run(adorym_ctx* ctx, adorym_plan* plan);
+/* Frees the plan's device tables (hipFree: waits for the device); NULL is
+ * EINVAL.  Call it only after the plan's last run has completed. */
 adorym_status adorym_plan_destroy(adorym_plan* plan);
 
 /* Synchronise the context's stream, return (and clear) any deferred
