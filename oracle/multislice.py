@@ -479,6 +479,37 @@ def loss_grad_nearfield(geom, obj_a, obj_b, probe, positions, i_meas, dists, dis
 
 
 # ---------------------------------------------------------------------------
+# Probe defocus (a refinable experimental parameter, Sec. S1.D): the probe is
+# Fresnel-propagated (Eqs. fresnel_prop, paraxial_kernel) by the defocus
+# distance before it meets the object, and the distance gets a gradient.
+# ---------------------------------------------------------------------------
+
+def defocus_probe(geom, probe, dist_m):
+    """The probe propagated by dist_m metres: F^-1[H(dist_m) F p]."""
+    return fresnel_propagate(probe, fresnel_kernel(geom.n, geom.wavelength_m, geom.pixel_m, dist_m))
+
+
+def forward_defocus(geom, obj_a, obj_b, probe, positions, dist_m):
+    """Far-field intensities with the probe defocused by dist_m."""
+    return forward(geom, obj_a, obj_b, defocus_probe(geom, probe, dist_m), positions)
+
+
+def loss_grad_defocus(geom, obj_a, obj_b, probe, positions, i_meas, dist_m):
+    """Loss and gradients with a defocused probe: (loss, g_a, g_b, g_probe,
+    g_shift, g_defocus).  With p_d = F^-1[H F p] and g_d = dL/dp_d from
+    ``loss_grad`` at p_d, the chain rule gives g_probe = F^-1[conj(H) F g_d]
+    (the adjoint of the propagation) and
+    dL/d(dist) = Re sum conj(F g_d) (i pi lambda |nu|^2) H F p."""
+    h = fresnel_kernel(geom.n, geom.wavelength_m, geom.pixel_m, dist_m)
+    p_d = fresnel_propagate(probe, h)
+    value, g_a, g_b, g_pd, g_shift = loss_grad(geom, obj_a, obj_b, p_d, positions, i_meas)
+    g_probe = fresnel_propagate_adjoint(g_pd, h)
+    dlog = nearfield_kernel_ddist(geom, "paraxial")
+    g_def = float(np.sum(np.real(np.conj(fft2u(g_pd)) * dlog * h * fft2u(probe))))
+    return value, g_a, g_b, g_probe, g_shift, g_def
+
+
+# ---------------------------------------------------------------------------
 # Several mutually incoherent probe modes (Eq. multimode)
 # ---------------------------------------------------------------------------
 

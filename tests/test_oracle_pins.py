@@ -744,3 +744,91 @@ def test_nearfield_gradients_match_central_finite_differences(loss, kind):
             pp[k, c] += 1e-6
             pm[k, c] -= 1e-6
             assert gs[k, c] == pytest.approx((f(pos_=pp) - f(pos_=pm)) / 2e-6, rel=1e-5, abs=1e-7 * np.max(np.abs(gs)))
+
+
+# ---------------------------------------------------------------- probe defocus
+
+DEFOCUS = 0.9e-6        # metres; on the tiny sub-case the Nyquist phase is about 1 rad
+
+
+def _defocus_case(loss="gaussian"):
+    """Measured data at the true defocus, evaluated 10 % away from it."""
+    geom, a, b, p, pos, _ = _fd_case(loss)
+    sc = synth.fd_subcase_n16_s4()
+    i_true = om.forward_defocus(geom, sc.obj_a, sc.obj_b, sc.probe, sc.positions, DEFOCUS)
+    i_meas = i_true if loss == "gaussian" else np.random.default_rng(3).poisson(i_true).astype(float)
+    return geom, a, b, p, pos, i_meas, 1.1 * DEFOCUS
+
+
+def test_zero_defocus_is_the_plain_model():
+    geom, a, b, p, pos, i_meas, _ = _defocus_case("poisson")
+    assert rel(om.forward_defocus(geom, a, b, p, pos, 0.0), om.forward(geom, a, b, p, pos)) < 1e-14
+    got = om.loss_grad_defocus(geom, a, b, p, pos, i_meas, 0.0)
+    ref = om.loss_grad(geom, a, b, p, pos, i_meas)
+    assert got[0] == pytest.approx(ref[0], rel=1e-13)
+    for x, y in zip(got[1:5], ref[1:]):
+        assert rel(x, y) < 1e-12
+
+
+@pytest.mark.parametrize("loss", ["gaussian", "poisson"])
+def test_defocus_is_an_empty_leading_slice(loss):
+    """Defocusing the probe by d is free-space propagation before slice 0, so
+    it equals the same object behind one extra empty slice at gap d (the
+    unequal-spacing model, whose gap gradient comes from the reverse sweep,
+    not from this chain rule).  Intensities, every gradient and dL/dd agree."""
+    geom, a, b, p, pos, i_meas, d = _defocus_case(loss)
+    z = np.zeros_like(a[:1])
+    a1, b1 = np.concatenate([z, a]), np.concatenate([z, b])
+    gaps = np.concatenate([[d], np.full(geom.n_slices - 1, geom.slice_dz_m)])
+    g1 = _gaps_geom(geom, gaps)
+    assert rel(om.forward_defocus(geom, a, b, p, pos, d), om.forward(g1, a1, b1, p, pos)) < 1e-13
+    L, ga, gb, gp, gs, gd = om.loss_grad_defocus(geom, a, b, p, pos, i_meas, d)
+    L1, ga1, gb1, gp1, gs1, gg1 = om.loss_grad_gaps(g1, a1, b1, p, pos, i_meas)
+    assert L == pytest.approx(L1, rel=1e-13)
+    assert rel(ga, ga1[1:]) < 1e-11 and rel(gb, gb1[1:]) < 1e-11
+    assert rel(gp, gp1) < 1e-11 and rel(gs, gs1) < 1e-11
+    assert gd == pytest.approx(gg1[0], rel=1e-9)
+    assert abs(gd) > 0
+
+
+@pytest.mark.parametrize("loss", ["gaussian", "poisson"])
+def test_defocus_gradients_match_central_finite_differences(loss):
+    """dL/dd and dL/dp (complex: dL/dRe + i dL/dIm) by central differences."""
+    geom, a, b, p, pos, i_meas, d = _defocus_case(loss)
+    L, ga, gb, gp, gs, gd = om.loss_grad_defocus(geom, a, b, p, pos, i_meas, d)
+
+    def f(p_=p, d_=d):
+        return loss_value_at(geom, a, b, p_, pos, i_meas, d_)
+
+    h = 3e-11
+    fd = (f(d_=d + h) - f(d_=d - h)) / (2 * h)
+    assert gd == pytest.approx(fd, rel=1e-6)
+    hp = 1e-6 * np.max(np.abs(p))
+    for (y, x) in ((3, 4), (8, 8), (12, 1)):
+        for unit in (1.0, 1j):
+            pp, pm = p.copy(), p.copy()
+            pp[y, x] += hp * unit
+            pm[y, x] -= hp * unit
+            fd = (f(p_=pp) - f(p_=pm)) / (2 * hp)
+            comp = gp[y, x].real if unit == 1.0 else gp[y, x].imag
+            assert comp == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.max(np.abs(gp)))
+
+
+def loss_value_at(geom, a, b, p, pos, i_meas, d):
+    return om.loss_value(geom.loss, om.forward_defocus(geom, a, b, p, pos, d), i_meas, geom.eps)
+
+
+def test_defocus_composes_and_vanishes_in_vacuum():
+    """Two defocus steps add (H(d1) H(d2) = H(d1 + d2)).  With no object the
+    far-field intensity is |F p_s|^2 whatever the defocus (|H| = 1), so the
+    defocus gradient vanishes."""
+    geom, a, b, p, pos, i_meas, d = _defocus_case("gaussian")
+    two = om.defocus_probe(geom, om.defocus_probe(geom, p, 0.3e-6), 0.5e-6)
+    assert rel(two, om.defocus_probe(geom, p, 0.8e-6)) < 1e-13
+    assert rel(om.defocus_probe(geom, p, 0.8e-6), p) > 1e-2
+    zero = np.zeros_like(a)
+    i0 = om.forward_defocus(geom, zero, zero, p, pos, 0.0)
+    assert rel(om.forward_defocus(geom, zero, zero, p, pos, 2e-6), i0) < 1e-13
+    gd_obj = om.loss_grad_defocus(geom, a, b, p, pos, i_meas, d)[5]
+    gd_vac = om.loss_grad_defocus(geom, zero, zero, p, pos, i0 * 1.3, d)[5]
+    assert abs(gd_vac) <= 1e-9 * abs(gd_obj)
