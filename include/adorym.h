@@ -148,6 +148,28 @@ adorym_status adorym_loss_grad(adorym_ctx* ctx, const adorym_geom* g,
                                double* loss, float* g_a, float* g_b, float* g_probe,
                                float* g_shift, float* intensity);
 
+/* ---- Probe defocus (a refinable parameter of the experiment, Sec. S1.D) --
+ * The probe is Fresnel-propagated by defocus_m metres (host double, any
+ * finite value; Eqs. fresnel_prop, paraxial_kernel: its spectrum times
+ * exp(i pi lambda defocus_m |nu|^2)) before it meets the object; `probe` is
+ * the undefocused probe.  adorym_forward_defocus: as adorym_forward, same
+ * workspace.  adorym_loss_grad_defocus: as adorym_loss_grad, same
+ * workspace; g_probe is the gradient with respect to the undefocused probe
+ * and, if g_defocus (DEVICE float64 scalar) is not NULL, it receives
+ * dL/d(defocus_m) in 1/m (overwritten, or added with
+ * ADORYM_ACCUMULATE_GRADS), summed in FP64 in a fixed order.  A non-finite
+ * defocus_m is ADORYM_EINVAL.  defocus_m = 0 gives the plain calls' bits. */
+adorym_status adorym_forward_defocus(adorym_ctx* ctx, const adorym_geom* g,
+                                     const float* obj_a, const float* obj_b, const float* probe,
+                                     const int32_t* corner, const float* shift, int32_t batch,
+                                     double defocus_m, float* intensity, void* workspace, size_t ws_bytes);
+adorym_status adorym_loss_grad_defocus(adorym_ctx* ctx, const adorym_geom* g,
+                                       const float* obj_a, const float* obj_b, const float* probe,
+                                       const int32_t* corner, const float* shift, int32_t batch,
+                                       double defocus_m, const float* i_meas, void* workspace, size_t ws_bytes,
+                                       double* loss, float* g_a, float* g_b, float* g_probe,
+                                       float* g_shift, double* g_defocus, float* intensity);
+
 /* ---- Unequal slice spacing: sparse multislice (Sec. S1.C, the variable-
  * spacing variant; slice positions are refinable parameters, Sec. S1.D) ---
  * gaps: DEVICE float64 [S-1], gaps[j] = free-space distance (metres) from

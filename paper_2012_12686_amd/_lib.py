@@ -63,6 +63,10 @@ SIGNATURES = {
     "adorym_forward": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t]),
     "adorym_loss_grad": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t,
                                         _P, _P, _P, _P, _P, _P]),
+    "adorym_forward_defocus": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_double, _P, _P,
+                                              ctypes.c_size_t]),
+    "adorym_loss_grad_defocus": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_double, _P,
+                                                _P, ctypes.c_size_t, _P, _P, _P, _P, _P, _P, _P]),
     "adorym_nearfield_workspace_size": (ctypes.c_size_t, [_GP, ctypes.c_int32, ctypes.c_int32]),
     "adorym_forward_nearfield": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P,
                                                 ctypes.c_int32, _P, _P, _P, ctypes.c_size_t]),

@@ -174,6 +174,50 @@ class Context:
         check(st, self._ctx)
         return out
 
+    # ------------------------------------------- probe defocus
+    def forward_defocus(self, geom, obj_a, obj_b, probe, corner, shift, defocus_m: float, out=None, workspace=None):
+        """Predicted intensities with the probe Fresnel-propagated by ``defocus_m`` metres first."""
+        self._bind_stream()
+        b = self._check_inputs(geom, obj_a, obj_b, probe, corner, shift)
+        out = out if out is not None else torch.empty((b, geom.n, geom.n), dtype=torch.float32, device=self.device)
+        ws = workspace if workspace is not None else self.workspace(geom, b, forward=True)
+        st = load().adorym_forward_defocus(self._ctx, ctypes.byref(geom.to_c()), _ptr(obj_a), _ptr(obj_b),
+                                           _ptr(torch.view_as_real(probe)), _ptr(corner), _ptr(shift), b,
+                                           float(defocus_m), _ptr(out), _ptr(ws), ws.numel())
+        check(st, self._ctx)
+        return out
+
+    def loss_grad_defocus(self, geom, obj_a, obj_b, probe, corner, shift, defocus_m: float, i_meas, grads=True,
+                          intensity=False, out=None, workspace=None):
+        """As :meth:`loss_grad` with the probe defocused by ``defocus_m``; with
+        ``grads`` the outputs also hold ``g_defocus`` (float64 scalar, dL/d defocus in 1/m)
+        and ``g_probe`` is the gradient with respect to the undefocused probe."""
+        self._bind_stream()
+        b = self._check_inputs(geom, obj_a, obj_b, probe, corner, shift)
+        if tuple(i_meas.shape) != (b, geom.n, geom.n) or i_meas.dtype != torch.float32 or not i_meas.is_contiguous():
+            raise ValueError("i_meas: expected contiguous float32 [B][N][N]")
+        out = dict(out or {})
+        dev = self.device
+        if "loss" not in out:
+            out["loss"] = torch.empty((), dtype=torch.float64, device=dev)
+        if grads:
+            for name, shape, dt in (("g_a", obj_a.shape, torch.float32), ("g_b", obj_b.shape, torch.float32),
+                                    ("g_probe", probe.shape, torch.complex64), ("g_shift", (b, 2), torch.float32),
+                                    ("g_defocus", (), torch.float64)):
+                if name not in out:
+                    out[name] = (torch.zeros if geom.accumulate else torch.empty)(shape, dtype=dt, device=dev)
+        if intensity and "intensity" not in out:
+            out["intensity"] = torch.empty((b, geom.n, geom.n), dtype=torch.float32, device=dev)
+        ws = workspace if workspace is not None else self.workspace(geom, b)
+        gp = out.get("g_probe")
+        st = load().adorym_loss_grad_defocus(
+            self._ctx, ctypes.byref(geom.to_c()), _ptr(obj_a), _ptr(obj_b), _ptr(torch.view_as_real(probe)),
+            _ptr(corner), _ptr(shift), b, float(defocus_m), _ptr(i_meas), _ptr(ws), ws.numel(), _ptr(out["loss"]),
+            _ptr(out.get("g_a")), _ptr(out.get("g_b")), _ptr(torch.view_as_real(gp) if gp is not None else None),
+            _ptr(out.get("g_shift")), _ptr(out.get("g_defocus")), _ptr(out.get("intensity")))
+        check(st, self._ctx)
+        return out
+
     # ------------------------------------------- unequal slice spacing
     def _check_gaps(self, geom, gaps):
         if geom.n_slices == 1 and gaps is None:

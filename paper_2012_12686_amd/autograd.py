@@ -164,6 +164,28 @@ class MultisliceLossNearfield(torch.autograd.Function):
         return ga, gb, gp, (gs.to(fctx.pos_dtype) if gs is not None else None), gd, None, None, None, None, None
 
 
+class MultisliceLossDefocus(torch.autograd.Function):
+    """Loss with the probe defocused first; also differentiable in the
+    defocus distance (a float64 scalar tensor; its value is read on the host)."""
+
+    @staticmethod
+    def forward(fctx, obj_a, obj_b, probe, positions, defocus, i_meas, geom: Geometry, lib: Optional[Context]):
+        lib = lib or _context(obj_a.device)
+        corner, shift = split_positions(positions.detach())
+        out = lib.loss_grad_defocus(geom, obj_a.detach().contiguous(), obj_b.detach().contiguous(),
+                                    probe.detach().contiguous(), corner, shift, float(defocus.detach().item()),
+                                    i_meas.contiguous())
+        g_def = out["g_defocus"].to(defocus.device, defocus.dtype)
+        fctx.save_for_backward(out["g_a"], out["g_b"], out["g_probe"], out["g_shift"], g_def)
+        fctx.pos_dtype = positions.dtype
+        return out["loss"]
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        ga, gb, gp, gs, gd = _scaled(fctx, fctx.saved_tensors, grad_out, fctx.needs_input_grad[:5])
+        return ga, gb, gp, (gs.to(fctx.pos_dtype) if gs is not None else None), gd, None, None, None
+
+
 class ObjectPrior(torch.autograd.Function):
     """l1 / reweighted l1 / total-variation prior of the object (Eq. tikhonov)."""
 
@@ -192,6 +214,10 @@ def multislice_loss_gaps(obj_a, obj_b, probe, positions, gaps, i_meas, geom, ctx
 def multislice_loss_nearfield(obj_a, obj_b, probe, positions, dists, dist_idx, i_meas, geom, kind="paraxial",
                               ctx=None):
     return MultisliceLossNearfield.apply(obj_a, obj_b, probe, positions, dists, dist_idx, i_meas, geom, kind, ctx)
+
+
+def multislice_loss_defocus(obj_a, obj_b, probe, positions, defocus, i_meas, geom, ctx=None):
+    return MultisliceLossDefocus.apply(obj_a, obj_b, probe, positions, defocus, i_meas, geom, ctx)
 
 
 def object_prior(obj_a, obj_b, obj_repr="delta_beta", l1_a=0.0, l1_b=0.0, tv=0.0, weights=None, ctx=None):

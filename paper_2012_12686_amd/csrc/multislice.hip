@@ -89,11 +89,11 @@ int pick_split(const adorym_ctx* ctx, int n, int batch) {
 adorym_status dispatch(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b, const float* probe,
                        const int32_t* corner, const float* shift, int batch, const float* i_meas, void* ws,
                        double* loss, float* g_a, float* g_b, float* g_probe, float* g_shift, float* intensity,
-                       bool with_loss) {
+                       bool with_loss, const Defocus* df = nullptr) {
   const int k = (g->flags & ADORYM_DETERMINISTIC) ? det_split(g->n) : pick_split(ctx, g->n, batch);
 #define ADORYM_RUN(N_, L_, K_) \
   return run<N_, L_, K_>(ctx, g, a, b, probe, corner, shift, batch, i_meas, ws, loss, g_a, g_b, g_probe, g_shift, \
-                         intensity, with_loss)
+                         intensity, with_loss, df)
   if (g->n == 64) {
     switch (k) {
       case 1: ADORYM_RUN(64, 8, 1);
@@ -327,6 +327,52 @@ adorym_status adorym_loss_grad(adorym_ctx* ctx, const adorym_geom* g, const floa
   if (ws_bytes < adorym_workspace_size(g, batch)) return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
   return dispatch(ctx, g, obj_a, obj_b, probe, corner, shift, batch, i_meas, workspace, loss, g_a, g_b, g_probe,
                   g_shift, intensity, true);
+}
+
+// Probe defocus: the plain calls with the probe spectrum multiplied by the
+// paraxial transfer function of the defocus distance (and, for the gradient,
+// the chain rule back to the undefocused probe plus dL/d(defocus)).
+static adorym_status make_defocus(adorym_ctx* ctx, const adorym_geom* g, double defocus_m, double* g_defocus,
+                                  Defocus& df) {
+  if (!std::isfinite(defocus_m)) return set_err(ctx, ADORYM_EINVAL, "defocus must be finite");
+  df.dist = defocus_m;
+  df.c0 = M_PI * g->wavelength_m / ((double)g->n * g->n * g->pixel_m * g->pixel_m);
+  df.g_dist = g_defocus;
+  return ADORYM_OK;
+}
+
+adorym_status adorym_forward_defocus(adorym_ctx* ctx, const adorym_geom* g, const float* obj_a, const float* obj_b,
+                                     const float* probe, const int32_t* corner, const float* shift, int32_t batch,
+                                     double defocus_m, float* intensity, void* workspace, size_t ws_bytes) {
+  adorym_status st = check_geom(ctx, g, batch);
+  if (st != ADORYM_OK) return st;
+  if (!obj_a || !obj_b || !probe || !corner || !shift || !intensity || !workspace)
+    return set_err(ctx, ADORYM_EINVAL, "NULL array argument");
+  if (ws_bytes < adorym_forward_workspace_size(g, batch))
+    return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
+  Defocus df;
+  st = make_defocus(ctx, g, defocus_m, nullptr, df);
+  if (st != ADORYM_OK) return st;
+  return dispatch(ctx, g, obj_a, obj_b, probe, corner, shift, batch, nullptr, workspace, nullptr, nullptr, nullptr,
+                  nullptr, nullptr, intensity, false, &df);
+}
+
+adorym_status adorym_loss_grad_defocus(adorym_ctx* ctx, const adorym_geom* g, const float* obj_a,
+                                       const float* obj_b, const float* probe, const int32_t* corner,
+                                       const float* shift, int32_t batch, double defocus_m, const float* i_meas,
+                                       void* workspace, size_t ws_bytes, double* loss, float* g_a, float* g_b,
+                                       float* g_probe, float* g_shift, double* g_defocus, float* intensity) {
+  adorym_status st = check_geom(ctx, g, batch);
+  if (st != ADORYM_OK) return st;
+  if (!obj_a || !obj_b || !probe || !corner || !shift || !i_meas || !workspace || !loss)
+    return set_err(ctx, ADORYM_EINVAL, "NULL array argument");
+  if ((g_a == nullptr) != (g_b == nullptr)) return set_err(ctx, ADORYM_EINVAL, "g_a and g_b must both be given");
+  if (ws_bytes < adorym_workspace_size(g, batch)) return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
+  Defocus df;
+  st = make_defocus(ctx, g, defocus_m, g_defocus, df);
+  if (st != ADORYM_OK) return st;
+  return dispatch(ctx, g, obj_a, obj_b, probe, corner, shift, batch, i_meas, workspace, loss, g_a, g_b, g_probe,
+                  g_shift, intensity, true, &df);
 }
 
 // ---- Unequal slice spacing (sparse multislice) -----------------------------

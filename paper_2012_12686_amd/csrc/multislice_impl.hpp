@@ -879,6 +879,61 @@ __global__ void __launch_bounds__(C::THREADS) multislice_batched_kernel(const Ms
   }
 }
 
+// Probe defocus (a refinable parameter of the experiment, Sec. S1.D): the
+// probe is Fresnel-propagated (Eqs. fresnel_prop, paraxial_kernel) by a
+// distance d before it meets the object, i.e. its spectrum is multiplied by
+// H(nu) = exp(i pi lambda d |nu|^2).  `c0` is pi lambda / (N dx)^2, so the
+// phase at natural-order frequency (ky, kx) is c0 d (fy^2 + fx^2) with
+// fy = ky or ky - N (NumPy's fftfreq order).  Built in FP64, rounded once.
+struct Defocus {
+  double dist;       // metres
+  double c0;         // pi lambda / (N dx)^2, 1/m
+  double* g_dist;    // device FP64 scalar, or NULL
+};
+
+__device__ __forceinline__ double defocus_nu2(int i, int n) {
+  const int ky = i / n, kx = i - ky * n;
+  const double fy = ky < n / 2 ? ky : ky - n, fx = kx < n / 2 ? kx : kx - n;
+  return fy * fy + fx * fx;
+}
+
+// q <- q H, in place (the spectrum the multislice kernel places).
+static __global__ void __launch_bounds__(256) defocus_spectrum_kernel(float2* __restrict__ q, int n, double c0,
+                                                                      double dist) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * n) return;
+  double sn, cs;
+  sincos(c0 * dist * defocus_nu2(i, n), &sn, &cs);
+  q[i] = cmul(q[i], make_float2((float)cs, (float)sn));
+}
+
+// Before the probe-gradient transform: with G = dL/dq_d (the per-position sum,
+// natural order) and q_d = q H, dL/dd = Re sum conj(G) (i c0 nu2) q_d
+// = -sum c0 nu2 Im(conj(G) q_d), summed in FP64 in a fixed order (strided
+// per thread, then a tree: bitwise reproducible); then G <- conj(H) G, the
+// gradient with respect to the undefocused spectrum.  One workgroup.
+static __global__ void __launch_bounds__(256) defocus_grad_kernel(float2* __restrict__ g, const float2* __restrict__ qd,
+                                                                  int n, double c0, double dist,
+                                                                  double* __restrict__ g_dist, int accumulate) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
+    const double nu2 = defocus_nu2(i, n);
+    const float2 gi = g[i], qi = qd[i];
+    s -= c0 * nu2 * ((double)gi.x * qi.y - (double)gi.y * qi.x);
+    double sn, cs;
+    sincos(c0 * dist * nu2, &sn, &cs);
+    g[i] = cmulc(gi, make_float2((float)cs, (float)sn));
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && g_dist) *g_dist = accumulate ? *g_dist + red[0] : red[0];
+}
+
 // Probe spectrum Q = DFT(p) / N^2 (natural [ky][kx]).  One group of K
 // workgroups (block index = part); K > 1 exchanges through xbuf.
 template <class C>
@@ -1232,7 +1287,7 @@ void launch_prologue(const MsParams& P, const float* probe, const adorym_geom* g
 // Per-job work after it: loss, shift gradients, probe gradient.
 template <int N, int L>
 void launch_epilogue(const MsParams& P, void* ws, const adorym_geom* g, double* loss, float* g_probe,
-                     float* g_shift, hipStream_t st) {
+                     float* g_shift, hipStream_t st, const Defocus* df = nullptr) {
   using PC = ProbeCfg<N, L>;
   const WsLayout w = ws_layout(g, P.B);
   int* aux = reinterpret_cast<int*>(static_cast<char*>(ws) + w.aux);
@@ -1241,6 +1296,9 @@ void launch_epilogue(const MsParams& P, void* ws, const adorym_geom* g, double* 
   const int nn = N * N;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((nn + 255) / 256), dim3(256), 0, st, P.gacc, P.B, nn, gsum,
                      P.loss_part, P.gs_part, P.ksplit, loss, g_shift, accumulate);
+  if (df && P.gacc)
+    hipLaunchKernelGGL(defocus_grad_kernel, dim3(1), dim3(256), 0, st, gsum, P.q, N, df->c0, df->dist, df->g_dist,
+                       accumulate);
   if (g_probe)
     hipLaunchKernelGGL((probe_grad_kernel<PC>), dim3(PC::K), dim3(PC::THREADS), 0, st, gsum,
                        reinterpret_cast<float2*>(g_probe), accumulate, P.xbuf, aux + 1, aux + 16, P.err);
@@ -1266,19 +1324,23 @@ template <int N, int L, int K>
 adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b, const float* probe,
                   const int32_t* corner, const float* shift, int batch, const float* i_meas, void* ws,
                   double* loss, float* g_a, float* g_b, float* g_probe, float* g_shift, float* intensity,
-                  bool with_loss) {
+                  bool with_loss, const Defocus* df = nullptr) {
   using C = TileCfg<N, L, K>;
-  MsParams P = make_params<N, probe_lanes<N>()>(ctx, g, a, b, batch, corner, shift, i_meas, ws, g_probe != nullptr,
+  const bool probe_partials = g_probe != nullptr || (df && df->g_dist);
+  MsParams P = make_params<N, probe_lanes<N>()>(ctx, g, a, b, batch, corner, shift, i_meas, ws, probe_partials,
                                     with_loss ? g_a : nullptr, with_loss ? g_b : nullptr, intensity);
   P.ksplit = K;
   hipStream_t st = ctx->stream;
   const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
   launch_prologue<N, probe_lanes<N>()>(P, probe, g, st);
+  if (df)
+    hipLaunchKernelGGL(defocus_spectrum_kernel, dim3((N * N + 255) / 256), dim3(256), 0, st,
+                       const_cast<float2*>(P.q), N, df->c0, df->dist);
   if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
   if (with_loss) launch_ms<C, true>(P, g->obj_repr, st);
   else launch_ms<C, false>(P, g->obj_repr, st);
   if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
-  if (with_loss) launch_epilogue<N, probe_lanes<N>()>(P, ws, g, loss, g_probe, g_shift, st);
+  if (with_loss) launch_epilogue<N, probe_lanes<N>()>(P, ws, g, loss, g_probe, g_shift, st, df);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
   return ADORYM_OK;
@@ -1552,7 +1614,7 @@ void launch_batched(const MsParams* jobs, const int2* items, int n_items, int* t
   void adorym_ms::launch_prologue<N_, L_>(const adorym_ms::MsParams&, const float*, const adorym_geom*, hipStream_t)
 #define ADORYM_EPILOGUE_SIGNATURE(N_, L_) \
   void adorym_ms::launch_epilogue<N_, L_>(const adorym_ms::MsParams&, void*, const adorym_geom*, double*, float*, \
-                                          float*, hipStream_t)
+                                          float*, hipStream_t, const adorym_ms::Defocus*)
 #define ADORYM_PARAMS_SIGNATURE(N_, L_) \
   adorym_ms::MsParams adorym_ms::make_params<N_, L_>(adorym_ctx*, const adorym_geom*, const float*, \
                                                         const float*, int, const int32_t*, const float*, \
@@ -1575,4 +1637,4 @@ void launch_batched(const MsParams* jobs, const int2* items, int n_items, int* t
 #define ADORYM_RUN_SIGNATURE(N_, L_, K_) \
   adorym_status adorym_ms::run<N_, L_, K_>(adorym_ctx*, const adorym_geom*, const float*, const float*, const float*, \
                                            const int32_t*, const float*, int, const float*, void*, double*, float*, \
-                                           float*, float*, float*, float*, bool)
+                                           float*, float*, float*, float*, bool, const adorym_ms::Defocus*)
