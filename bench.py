@@ -134,6 +134,9 @@ def main():
     ap.add_argument("--ckpt", type=int, default=16, help="slice checkpoint interval of the adjoint")
     ap.add_argument("--deterministic", action="store_true", help="FP64 ordered object-gradient sums")
     ap.add_argument("--modes", type=int, default=1, help="incoherent probe modes (Eq. multimode)")
+    ap.add_argument("--defocus", type=float, default=0.0,
+                    help="probe defocus in metres: data simulated at this defocus, evaluated 10%% away, "
+                         "with the defocus gradient (single probe mode)")
     ap.add_argument("--jobs", type=int, default=200, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=4.0, help="serving: Poisson arrival rate (jobs/s)")
     args = ap.parse_args()
@@ -189,8 +192,14 @@ def main():
     corner, shift = split_positions(to_t(sc.positions, torch.float64))
     # synthetic measurements: Poisson counts of the forward model at the truth
     # (summed over the probe modes)
-    i_true = torch.cat([sum(ctx.forward(geom, true_a, true_b, p, corner[k * mb:(k + 1) * mb],
-                                        shift[k * mb:(k + 1) * mb]) for p in probes) for k in range(n_mb)])
+    defocus = args.defocus if n_modes == 1 else 0.0
+
+    def simulate(p, sl):
+        if defocus:
+            return ctx.forward_defocus(geom, true_a, true_b, p, corner[sl], shift[sl], defocus)
+        return ctx.forward(geom, true_a, true_b, p, corner[sl], shift[sl])
+
+    i_true = torch.cat([sum(simulate(p, slice(k * mb, (k + 1) * mb)) for p in probes) for k in range(n_mb)])
     rng = np.random.default_rng(2)
     i_meas_np = rng.poisson(i_true.cpu().numpy().astype(np.float64)).astype(np.float32)
     i_meas = to_t(i_meas_np, torch.float32)
@@ -206,10 +215,15 @@ def main():
            "g_a": torch.empty_like(a), "g_b": torch.empty_like(b),
            "g_probe": torch.empty_like(probe if n_modes == 1 else probes),
            "g_shift": torch.empty((mb, 2), dtype=torch.float32, device=dev)}
+    if defocus:
+        out["g_defocus"] = torch.empty((), dtype=torch.float64, device=dev)
 
     def step(k):
         sl = slice((k % n_mb) * mb, (k % n_mb + 1) * mb)
-        if n_modes == 1:
+        if defocus:
+            ctx.loss_grad_defocus(geom, a, b, probe, corner[sl], shift[sl], 1.1 * defocus, i_meas[sl], out=out,
+                                  workspace=ws)
+        elif n_modes == 1:
             ctx.loss_grad(geom, a, b, probe, corner[sl], shift[sl], i_meas[sl], out=out, workspace=ws)
         else:
             ctx.loss_grad_modes(geom, a, b, probes, corner[sl], shift[sl], i_meas[sl], out=out, workspace=ws)
@@ -267,7 +281,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "multislice ptychography N=128 S=64 object 256x256x64 (10 nm, 10 keV), "
                                "minibatch 50 of 400 positions, Poisson 1e4 photons, fwd+loss+adjoint"
-                               + (f", {n_modes} incoherent probe modes" if n_modes > 1 else ""),
+                               + (f", {n_modes} incoherent probe modes" if n_modes > 1 else "")
+                               + (f", probe defocused (data at {defocus:g} m, evaluated at {1.1 * defocus:g} m) "
+                                  f"with the defocus gradient" if defocus else ""),
                    "global_batch": mb, "seq_len": s, "parallelism": "none"},
         "p50_iter_ms": p50,
         "p99_iter_ms": p99,
@@ -280,7 +296,7 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "fp32_tflops": achieved_tflops, "fp32_frac": achieved_tflops / FP32_PEAK_TFLOPS},
     }
-    if not args.no_cpu_baseline and n_modes == 1:
+    if not args.no_cpu_baseline and n_modes == 1 and not defocus:
         line["cpu_baseline"] = cpu_baseline(sc, slice(0, mb), i_meas_np[:mb].astype(np.float64))
     print(json.dumps(with_copy_peak(line)), flush=True)
     ctx.close()

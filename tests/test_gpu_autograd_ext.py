@@ -94,5 +94,5 @@ def test_data_loss_plus_prior_gradients_add(ctx):
     direct = ctx.loss_grad(g, **inp, i_meas=i_meas)
     pr = ctx.prior_grad("delta_beta", inp["obj_a"], inp["obj_b"], l1_a=0.3, l1_b=0.1, tv=0.2, accumulate=False)
     torch.cuda.synchronize()
-    assert float(prior) == float(pr["value"])
+    assert float(prior.detach()) == float(pr["value"])
     assert torch.equal(a.grad, direct["g_a"] + pr["g_a"]) and torch.equal(b.grad, direct["g_b"] + pr["g_b"])
