@@ -294,7 +294,11 @@ __device__ __forceinline__ rsrc_t slice_rsrc(const float* base, int j, const Chu
 }
 
 // This position's contribution to one object-gradient plane of slice j,
-// chunk-local [N][N] (row y, column x), plain stores.
+// chunk-local [N][N] (row y, column x).  Written once, read once by the
+// reduction after the kernel.  Whole-field workgroups (K == 1) store it
+// non-temporally (nt) so that it does not displace reused lines; split
+// fields keep plain stores, whose partial lines the L2 combines (measured
+// both ways).
 template <class C>
 __device__ __forceinline__ rsrc_t stage_rsrc(const MsParams& P, int b, int j, int comp) {
   constexpr int NN = C::N * C::N;
@@ -305,7 +309,8 @@ __device__ __forceinline__ void stage_store(rsrc_t r, const Lane<C>& ln, int m, 
   constexpr int N = C::N;
   const uint32_t off = ROW ? (uint32_t)((ln.line * N + ln.q) * 4) : (uint32_t)((ln.q * N + ln.line) * 4);
   const uint32_t step = ROW ? 4 * C::L : 4 * C::L * N;
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off + (uint32_t)m * step, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off + (uint32_t)m * step, 0,
+                                        C::K == 1 ? kNonTemporal : 0);
 }
 
 // Object values of slice j on this thread's elements (layout ROW/COL).

@@ -482,6 +482,8 @@ __device__ void adorym_raw_store_v2f32(f32x2 v, rsrc_t rsrc, int voffset, int so
 // stores write through every cache level, loads miss in every cache), used
 // for data that other workgroups read within the same kernel.
 constexpr int kCoherent = 1 | 16;
+// nt: streaming data, a hint to keep it from displacing reused lines.
+constexpr int kNonTemporal = 2;
 
 template <int AUX = 0>
 __device__ __forceinline__ float2 bload2(rsrc_t r, uint32_t voff, uint32_t soff) {
