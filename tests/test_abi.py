@@ -155,3 +155,6 @@ def test_extension_entry_points_reject_bad_arguments_without_a_device():
     assert lib.adorym_prior_grad(None, 0, P, P, 1, 1, 1, 0.0, 0.0, 0.0, P, P, P, 0, P, P, P, 1) == _lib.EINVAL
     assert lib.adorym_prior_weights(None, 0, P, P, 1, 1, 1, 1e-3, P, 0, P, P) == _lib.EINVAL
     assert lib.adorym_support_project(None, 0, P, P, P, 4) == _lib.EINVAL
+    assert lib.adorym_forward_defocus(None, ctypes.byref(g), P, P, P, P, P, 1, 1e-6, P, P, 0) == _lib.EINVAL
+    assert lib.adorym_loss_grad_defocus(None, ctypes.byref(g), P, P, P, P, P, 1, 1e-6, P, P, 0, P, P, P, P, P, P,
+                                        P) == _lib.EINVAL
