@@ -336,11 +336,15 @@ adorym_status adorym_adam(adorym_ctx* ctx, float* x, const float* g, float* m, f
  * object, probe, positions, measurements, outputs and workspace of
  * adorym_workspace_size(&g, batch) bytes).  adorym_plan_create validates the
  * jobs and uploads a job table (it allocates and synchronises: call it
- * outside timed or captured regions).  adorym_plan_run then evaluates every
- * job's loss and gradients: per probe size, one persistent launch whose
- * workgroup groups draw (job, position) items from a device queue, longest
- * first; it only launches kernels, so a whole iteration can be captured in
- * a HIP graph.  The arrays named in the jobs must stay valid while the plan
+ * outside timed or captured regions; it also creates the plan's own
+ * streams).  adorym_plan_run then evaluates every job's loss and gradients:
+ * per probe size, one persistent launch whose workgroup groups draw (job,
+ * position) items from a device queue, longest first.  Sizes split over
+ * several workgroups run first on ctx's stream; sizes with one workgroup
+ * per position then run concurrently on the plan's streams, forked from
+ * and joined back to ctx's stream by events.  It only launches kernels and
+ * records and waits on events, so a whole iteration can be captured in a
+ * HIP graph.  The arrays named in the jobs must stay valid while the plan
  * is used.  Supported probe sizes as adorym_supports_n. */
 typedef struct {
   adorym_geom g;

@@ -186,6 +186,13 @@ struct adorym_plan {
   std::vector<MsParams> params;     // host copy
   MsParams* d_params = nullptr;     // device job table
   std::vector<PlanClass> classes;
+  std::vector<std::vector<int>> class_jobs;   // job indices of each class
+  // Classes of one workgroup per position (K == 1) have no group barriers,
+  // so they may share the chip: each runs on a stream of its own, forked
+  // from the caller's stream and joined back (capturable in a HIP graph).
+  std::vector<hipStream_t> side;    // one per K == 1 class, default priority
+  std::vector<hipEvent_t> side_done;
+  hipEvent_t fork = nullptr;
   int device = 0;
 };
 
@@ -757,6 +764,10 @@ adorym_status adorym_plan_create(adorym_ctx* ctx, const adorym_job* jobs, int32_
       }
       for (int b = 0; b < j.batch; ++b) work.push_back({(double)j.g.n_slices * j.g.n * j.g.n, make_int2(i, b)});
     }
+    std::vector<int> members;
+    for (int i = 0; i < n_jobs; ++i)
+      if (same(key_of(plan->jobs[i]), key)) members.push_back(i);
+    plan->class_jobs.push_back(members);
     std::stable_sort(work.begin(), work.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
     std::vector<int2> items;
     for (const auto& w : work) items.push_back(w.second);
@@ -774,6 +785,22 @@ adorym_status adorym_plan_create(adorym_ctx* ctx, const adorym_job* jobs, int32_
     adorym_plan_destroy(plan);
     return set_err(ctx, ADORYM_EDEVICE, "plan allocation failed");
   }
+  if (plan->classes.size() > 1) {
+    bool ok = hipEventCreateWithFlags(&plan->fork, hipEventDisableTiming) == hipSuccess;
+    for (const PlanClass& c : plan->classes) {
+      if (!ok || c.k != 1) continue;
+      hipStream_t s = nullptr;
+      hipEvent_t e = nullptr;
+      ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+      if (ok) plan->side.push_back(s);
+      ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+      if (ok) plan->side_done.push_back(e);
+    }
+    if (!ok) {
+      adorym_plan_destroy(plan);
+      return set_err(ctx, ADORYM_EDEVICE, "plan stream creation failed");
+    }
+  }
   *out = plan;
   return ADORYM_OK;
 }
@@ -784,15 +811,44 @@ adorym_status adorym_plan_run(adorym_ctx* ctx, adorym_plan* plan) {
   for (size_t i = 0; i < plan->jobs.size(); ++i) job_prologue(plan->params[i], plan->jobs[i], st);
   const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
   if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
-  for (const PlanClass& c : plan->classes) class_launch(c, plan->d_params, ctx->d_err, st);
-  if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
-  for (size_t i = 0; i < plan->jobs.size(); ++i) job_epilogue(plan->params[i], plan->jobs[i], st);
+  if (plan->side.empty()) {
+    for (const PlanClass& c : plan->classes) class_launch(c, plan->d_params, ctx->d_err, st);
+    if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
+    for (size_t i = 0; i < plan->jobs.size(); ++i) job_epilogue(plan->params[i], plan->jobs[i], st);
+  } else {
+    // split classes first, alone (their groups need co-resident workgroups);
+    // then every K == 1 class with its jobs' epilogues on its own stream,
+    // while the split classes' epilogues run here
+    for (const PlanClass& c : plan->classes)
+      if (c.k != 1) class_launch(c, plan->d_params, ctx->d_err, st);
+    (void)hipEventRecord(plan->fork, st);
+    size_t side = 0;
+    for (size_t ci = 0; ci < plan->classes.size(); ++ci) {
+      const PlanClass& c = plan->classes[ci];
+      if (c.k != 1) continue;
+      hipStream_t s = plan->side[side];
+      (void)hipStreamWaitEvent(s, plan->fork, 0);
+      class_launch(c, plan->d_params, ctx->d_err, s);
+      for (int i : plan->class_jobs[ci]) job_epilogue(plan->params[i], plan->jobs[i], s);
+      (void)hipEventRecord(plan->side_done[side], s);
+      ++side;
+    }
+    for (size_t ci = 0; ci < plan->classes.size(); ++ci)
+      if (plan->classes[ci].k != 1)
+        for (int i : plan->class_jobs[ci]) job_epilogue(plan->params[i], plan->jobs[i], st);
+    for (hipEvent_t e : plan->side_done) (void)hipStreamWaitEvent(st, e, 0);
+    if (timed) { (void)hipEventRecord(ctx->ev[ctx->ev_used + 1], st); ctx->ev_used += 2; }
+  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? ADORYM_OK : set_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
 }
 
 adorym_status adorym_plan_destroy(adorym_plan* plan) {
   if (!plan) return ADORYM_EINVAL;
+  for (hipStream_t s : plan->side) (void)hipStreamSynchronize(s);
+  for (hipStream_t s : plan->side) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : plan->side_done) (void)hipEventDestroy(e);
+  if (plan->fork) (void)hipEventDestroy(plan->fork);
   for (PlanClass& c : plan->classes) {
     if (c.items) (void)hipFree(c.items);
     if (c.state) (void)hipFree(c.state);
