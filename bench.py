@@ -128,8 +128,8 @@ def cpu_baseline(sc, mb, i_meas_np, min_seconds=10.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--split", type=int, default=0,
                     help="workgroups per position (0 = the library's automatic choice)")
@@ -273,6 +273,8 @@ def main():
     flops_launch = algorithmic_flops_per_position(n, s) * mb
     achieved_tflops = flops_launch / kern_avg_s / 1e12
 
+    traffic = measured_traffic() if n_modes == 1 else None
+    step_gbs = value * bytes_launch * (1 if n_modes == 1 else 2 * n_modes) / mb / 1e9
     line = {
         "metric": "multislice fwd+adjoint positions/s, % HBM roofline; p50/p99 iter latency",
         "value": value,
@@ -296,11 +298,15 @@ def main():
         "p99_iter_ms": p99,
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if n_modes == 1 else None,
+                     "traffic": traffic,
                      "kernel": "multislice_kernel<N=128, delta/beta, Poisson, loss+adjoint>" if n_modes == 1 else
                                "multislice_kernel<N=128>: forward and loss+adjoint launches, averaged",
                      "kernel_avg_ms": kern_avg_s * 1e3, "kernel_launches": kern_n,
                      "algorithmic_bytes_per_launch": bytes_launch,
+                     # the measured HBM bytes of one launch over its duration
+                     "traffic_GBps": traffic / kern_avg_s / 1e9 if traffic else None,
+                     # whole step: positions/s x algorithmic bytes per position
+                     "step_effective_GBps": step_gbs, "step_frac": step_gbs / HBM_PEAK_GBS,
                      "fp32_tflops": achieved_tflops, "fp32_frac": achieved_tflops / FP32_PEAK_TFLOPS},
     }
     if not args.no_cpu_baseline and n_modes == 1 and not defocus:
