@@ -914,15 +914,19 @@ static __global__ void __launch_bounds__(256) defocus_spectrum_kernel(float2* __
 
 // Before the probe-gradient transform: with G = dL/dq_d (the per-position sum,
 // natural order) and q_d = q H, dL/dd = Re sum conj(G) (i c0 nu2) q_d
-// = -sum c0 nu2 Im(conj(G) q_d), summed in FP64 in a fixed order (strided
-// per thread, then a tree: bitwise reproducible); then G <- conj(H) G, the
-// gradient with respect to the undefocused spectrum.  One workgroup.
+// = -sum c0 nu2 Im(conj(G) q_d); then G <- conj(H) G, the gradient with
+// respect to the undefocused spectrum.  kDefocusParts workgroups each sum a
+// fixed contiguous share (strided per thread, then a tree) into `part`;
+// defocus_finish_kernel adds the shares in order: FP64, bitwise reproducible.
+constexpr int kDefocusParts = 64;
 static __global__ void __launch_bounds__(256) defocus_grad_kernel(float2* __restrict__ g, const float2* __restrict__ qd,
                                                                   int n, double c0, double dist,
-                                                                  double* __restrict__ g_dist, int accumulate) {
+                                                                  double* __restrict__ part) {
   __shared__ double red[256];
+  const int share = (n * n + kDefocusParts - 1) / kDefocusParts;
+  const int lo = blockIdx.x * share, hi = min(n * n, lo + share);
   double s = 0.0;
-  for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
+  for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     const double nu2 = defocus_nu2(i, n);
     const float2 gi = g[i], qi = qd[i];
     s -= c0 * nu2 * ((double)gi.x * qi.y - (double)gi.y * qi.x);
@@ -933,6 +937,18 @@ static __global__ void __launch_bounds__(256) defocus_grad_kernel(float2* __rest
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+static __global__ void __launch_bounds__(kDefocusParts) defocus_finish_kernel(const double* __restrict__ part,
+                                                                              double* __restrict__ g_dist,
+                                                                              int accumulate) {
+  __shared__ double red[kDefocusParts];
+  red[threadIdx.x] = part[threadIdx.x];
+  __syncthreads();
+  for (int h = kDefocusParts / 2; h > 0; h >>= 1) {
     if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
@@ -1301,9 +1317,14 @@ void launch_epilogue(const MsParams& P, void* ws, const adorym_geom* g, double* 
   const int nn = N * N;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((nn + 255) / 256), dim3(256), 0, st, P.gacc, P.B, nn, gsum,
                      P.loss_part, P.gs_part, P.ksplit, loss, g_shift, accumulate);
-  if (df && P.gacc)
-    hipLaunchKernelGGL(defocus_grad_kernel, dim3(1), dim3(256), 0, st, gsum, P.q, N, df->c0, df->dist, df->g_dist,
-                       accumulate);
+  if (df && P.gacc) {
+    // the per-position probe partials are consumed by now: their first bytes
+    // hold the defocus-gradient shares
+    double* part = reinterpret_cast<double*>(P.gacc);
+    hipLaunchKernelGGL(defocus_grad_kernel, dim3(kDefocusParts), dim3(256), 0, st, gsum, P.q, N, df->c0, df->dist,
+                       part);
+    hipLaunchKernelGGL(defocus_finish_kernel, dim3(1), dim3(kDefocusParts), 0, st, part, df->g_dist, accumulate);
+  }
   if (g_probe)
     hipLaunchKernelGGL((probe_grad_kernel<PC>), dim3(PC::K), dim3(PC::THREADS), 0, st, gsum,
                        reinterpret_cast<float2*>(g_probe), accumulate, P.xbuf, aux + 1, aux + 16, P.err);
