@@ -118,9 +118,20 @@ int adorym_supports_n(int32_t n);
 
 /* Bytes of device workspace adorym_loss_grad needs for a batch of `batch`
  * positions (probe spectrum, per-position loss, shift and probe partials,
- * slice checkpoints every ckpt_every slices, the exchange buffers of split
+ * slice checkpoints every ckpt_every slices, room for the waves of one
+ * checkpoint segment per position, the exchange buffers of split
  * workgroups and the staged object-gradient contributions).  0 on bad
- * input. */
+ * input.
+ *
+ * The reverse sweep rebuilds the wave entering each slice by dividing the
+ * next one by the slice's transmission, re-anchored on the checkpoints.
+ * Before each loss-and-gradient evaluation a pre-pass bounds, per slice, the
+ * largest -log|t| of its voxels (k dz beta, or -log|O|); a checkpoint
+ * segment whose slices could amplify rounding by more than 2^4 that way
+ * (strong absorbers, or a transmission of exactly zero) has its waves
+ * recomputed forward from its checkpoint instead, so any object gives
+ * finite gradients at float32 accuracy; such segments cost about half a
+ * forward sweep more. */
 size_t adorym_workspace_size(const adorym_geom* g, int32_t batch);
 /* The smaller workspace adorym_forward needs (probe spectrum, exchange
  * buffers and counters only); adorym_workspace_size also suffices. */
@@ -353,6 +364,7 @@ typedef struct {
   const float* i_meas;
   double* loss; float* g_a; float* g_b; float* g_probe; float* g_shift;
   void* workspace; size_t ws_bytes;
+  float* intensity;     /* predicted intensities [B][N][N], or NULL: not written */
 } adorym_job;
 typedef struct adorym_plan adorym_plan;
 adorym_status adorym_plan_create(adorym_ctx* ctx, const adorym_job* jobs, int32_t n_jobs, adorym_plan** out);

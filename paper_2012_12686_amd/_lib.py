@@ -47,6 +47,7 @@ class Job(ctypes.Structure):
         ("loss", ctypes.c_void_p), ("g_a", ctypes.c_void_p), ("g_b", ctypes.c_void_p),
         ("g_probe", ctypes.c_void_p), ("g_shift", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t),
+        ("intensity", ctypes.c_void_p),
     ]
 
 

@@ -540,7 +540,9 @@ class Plan:
 
     The plan keeps references to every tensor it names; ``run()`` only enqueues
     kernels (capturable in a graph).  Outputs are in each job's ``out`` dict
-    (``loss``, ``g_a``, ``g_b``, ``g_probe``, ``g_shift``).
+    (``loss``, ``g_a``, ``g_b``, ``g_probe``, ``g_shift``, and ``intensity``
+    [B][N][N] float32 if the job's ``out`` held that tensor when the plan was
+    made).
     """
 
     def __init__(self, ctx: "Context", jobs):
@@ -590,6 +592,12 @@ def _job_structs(ctx: "Context", jobs):
         cj.g_probe = torch.view_as_real(o["g_probe"]).data_ptr()
         cj.g_shift = o["g_shift"].data_ptr()
         cj.workspace, cj.ws_bytes = j.workspace.data_ptr(), j.workspace.numel()
+        if "intensity" in o:
+            n = j.geom.n
+            if (o["intensity"].dtype != torch.float32 or tuple(o["intensity"].shape) != (b, n, n)
+                    or not o["intensity"].is_contiguous() or o["intensity"].device != dev):
+                raise ValueError("out['intensity'] must be a contiguous float32 [B][N][N] tensor on the device")
+            cj.intensity = o["intensity"].data_ptr()
     return cjobs
 
 

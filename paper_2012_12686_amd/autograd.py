@@ -5,12 +5,16 @@ data-mismatch loss L (a float64 scalar tensor) of the far-field multislice
 model and is differentiable with respect to the object (delta/beta or
 real/imag), the complex probe and the float scan positions.
 
-The gradient is the library's hand-written adjoint, not autograd tracing:
-the forward call runs the fused forward + loss + reverse-sweep kernel
-(which rebuilds slice waves from checkpoints instead of storing every
-slice) and keeps the gradients; backward multiplies them by the incoming
-gradient.  Complex gradients follow dL/dRe + i dL/dIm, PyTorch's own
-convention for real-valued losses of complex tensors.
+The gradient is the library's hand-written adjoint, not autograd tracing.
+By default forward calls adorym_loss_fwd (forward sweep and loss; it keeps
+each position's slice checkpoints and exit wave in a workspace held by the
+autograd context) and backward calls adorym_loss_bwd, which resumes the
+reverse sweep from them -- rebuilding slice waves from the checkpoints
+instead of storing every slice -- and scales the gradients by the incoming
+gradient.  ``lazy=False`` instead runs the fused forward + loss + reverse
+sweep (adorym_loss_grad) inside forward and keeps its gradients.  Complex
+gradients follow dL/dRe + i dL/dIm, PyTorch's own convention for
+real-valued losses of complex tensors.
 """
 from __future__ import annotations
 
@@ -31,6 +35,8 @@ def _context(device: torch.device) -> Context:
 
 
 class MultisliceLoss(torch.autograd.Function):
+    """Fused form: loss and every gradient in forward (adorym_loss_grad)."""
+
     @staticmethod
     def forward(fctx, obj_a, obj_b, probe, positions, i_meas, geom: Geometry, lib: Optional[Context]):
         lib = lib or _context(obj_a.device)
@@ -53,9 +59,10 @@ class MultisliceLoss(torch.autograd.Function):
 
 
 class MultisliceLossLazy(torch.autograd.Function):
-    """The same loss with gradients only when backward runs: forward computes
-    the loss and keeps the slice checkpoints and exit waves in a workspace
-    (adorym_loss_fwd); backward resumes from them (adorym_loss_bwd)."""
+    """Split form (the default): gradients only when backward runs.  Forward
+    computes the loss and keeps the slice checkpoints and exit waves in a
+    workspace (adorym_loss_fwd); backward resumes from them
+    (adorym_loss_bwd)."""
 
     @staticmethod
     def forward(fctx, obj_a, obj_b, probe, positions, i_meas, geom: Geometry, lib: Optional[Context]):
@@ -82,9 +89,10 @@ class MultisliceLossLazy(torch.autograd.Function):
 
 def multislice_loss(obj_a: torch.Tensor, obj_b: torch.Tensor, probe: torch.Tensor, positions: torch.Tensor,
                     i_meas: torch.Tensor, geom: Geometry, ctx: Optional[Context] = None,
-                    lazy: bool = False) -> torch.Tensor:
+                    lazy: bool = True) -> torch.Tensor:
     """Differentiable loss of one minibatch; see the module docstring.  With
-    ``lazy`` the gradients are computed only if backward runs."""
+    ``lazy`` (the default) the gradients are computed only if backward runs;
+    ``lazy=False`` computes them in forward with the fused call."""
     if lazy:
         return MultisliceLossLazy.apply(obj_a, obj_b, probe, positions, i_meas, geom, ctx)
     return MultisliceLoss.apply(obj_a, obj_b, probe, positions, i_meas, geom, ctx)

@@ -201,17 +201,17 @@ namespace {
 template <int N, int L>
 MsParams params_for(adorym_ctx* ctx, const adorym_job& j, int k) {
   MsParams P = make_params<N, L>(ctx, &j.g, j.obj_a, j.obj_b, j.batch, j.corner, j.shift, j.i_meas, j.workspace,
-                                 j.g_probe != nullptr, j.g_a, j.g_b, nullptr);
+                                 j.g_probe != nullptr, j.g_a, j.g_b, j.intensity);
   P.ksplit = k;
   return P;
 }
 
 void job_prologue(const MsParams& P, const adorym_job& j, hipStream_t st) {
   switch (j.g.n) {
-    case 64: launch_prologue<64, 4>(P, j.probe, &j.g, st); break;
-    case 96: launch_prologue<96, 8>(P, j.probe, &j.g, st); break;
-    case 128: launch_prologue<128, 8>(P, j.probe, &j.g, st); break;
-    default: launch_prologue<192, 8>(P, j.probe, &j.g, st); break;
+    case 64: launch_prologue<64, 4>(P, j.probe, &j.g, st, true); break;
+    case 96: launch_prologue<96, 8>(P, j.probe, &j.g, st, true); break;
+    case 128: launch_prologue<128, 8>(P, j.probe, &j.g, st, true); break;
+    default: launch_prologue<192, 8>(P, j.probe, &j.g, st, true); break;
   }
 }
 

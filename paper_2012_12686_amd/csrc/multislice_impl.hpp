@@ -18,7 +18,12 @@
 // rebuilds the wave
 // entering each slice by stepping the forward recursion backwards
 // (psi_{j-1} = t_{j-1}^{-1} P^H psi_j), and re-anchors it on checkpoints of
-// the forward sweep stored every ckpt_every slices.
+// the forward sweep stored every ckpt_every slices.  Where a checkpoint
+// segment's transmissions absorb so strongly that dividing by them could
+// amplify rounding by more than 2^4 (bounded per slice by a pre-pass over the
+// object), the waves of that segment are instead recomputed forward from its
+// checkpoint when the reverse sweep reaches it, kept in a per-position
+// scratch area and read back like checkpoints.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -52,6 +57,7 @@ struct MsParams {
   float* gstage;           // [B][S][2][N][N] per-position object-gradient contributions,
                            // null when no object gradient is wanted
   float2* ckpt;            // [B][nslots][K][R*THREADS]
+  float2* recomp;          // [B][nrec][K][R*THREADS] waves of a recomputed segment
   float2* exit_wave;       // [B][K][R*THREADS] phi_{S-1} between the passes of a split evaluation
   float2* gacc;            // [B][N][N] natural, or null (probe-gradient partials)
   double* loss_part;       // [B][K]
@@ -68,8 +74,9 @@ struct MsParams {
   double* nd_part;         // near field: [B][K] distance-gradient partials
   int n_dist;
   double* gd_part;         // [B][K][S-1] gap-gradient partials (unequal spacing)
+  const float* absorb;     // [S] largest -log|t| of any voxel of each slice (absorb_bound_kernel)
   double chirp_per_m;      // lambda / dx^2: the Fresnel phase / pi of gap d is chirp_per_m d f^2
-  int B, S, Ly, Lx, ckpt_every, nslots;
+  int B, S, Ly, Lx, ckpt_every, nslots, nrec;
   int loss;                // ADORYM_LOSS_*
   int ksplit;              // workgroups per position of the launch that fills the partials
   float kdz;               // k * dz
@@ -86,6 +93,64 @@ __device__ __forceinline__ bool is_ckpt(int j, int S, int C) { return (j % C == 
 __device__ __forceinline__ int ckpt_slot(int j, int S, int C) {
   return (j % C == 0) ? j / C : (S - 1) / C + 1;
 }
+
+// Inverse stepping through the checkpoint segment that starts at slice a
+// divides the wave by t_i for every slice strictly between a and the next
+// checkpoint, so rounding grows by at most exp(sum of the slices' largest
+// -log|t|).  Past 2^4 (and for a transmission of zero, whose bound is
+// infinite) the segment's waves are recomputed forward from its checkpoint.
+constexpr float kMaxLogGain = 2.7725887f;   // log(16)
+
+// The decisions of 64 consecutive segments (window `win`), one per lane,
+// gathered by a ballot: bit i is segment 64 win + i.
+__device__ __forceinline__ uint64_t seg_window_mask(const MsParams& P, int win) {
+  const int a = (win * 64 + (int)(threadIdx.x & 63)) * P.ckpt_every;
+  bool rc = false;
+  if (P.absorb && a < P.S - 1) {
+    const int e = min(a + P.ckpt_every, P.S - 1);
+    float s = 0.f;
+    for (int i = a + 1; i < e; ++i) s += P.absorb[i];
+    rc = !(s <= kMaxLogGain);
+  }
+  return __ballot(rc);
+}
+// Segment decisions of the reverse sweep, computed one 64-segment window at
+// a time (the sweep visits segments in decreasing order).  The segment of
+// the last slice asked about is kept, so that consecutive slices of one
+// segment cost two comparisons instead of integer divisions.
+struct SegFlags {
+  uint64_t mask = 0;
+  int win = -1;
+  int a = 1 << 30, e = 0;     // segment [a, e) of the last slice asked about
+  bool rc = false;            // and whether it is recomputed
+  __device__ __forceinline__ void locate(const MsParams& P, int j) {
+    if (j >= a && j < e) return;
+    a = j - j % P.ckpt_every;
+    e = min(a + P.ckpt_every, P.S - 1);
+    const int seg = a / P.ckpt_every;
+    if ((seg >> 6) != win) {
+      win = seg >> 6;
+      mask = seg_window_mask(P, win);
+    }
+    rc = (mask >> (seg & 63)) & 1ull;
+  }
+  // slice j's segment is recomputed
+  __device__ __forceinline__ bool recompute(const MsParams& P, int j) {
+    locate(P, j);
+    return rc;
+  }
+  // Slice j's entering wave is known exactly in the reverse sweep: stored,
+  // or recomputed with the rest of its segment.
+  __device__ __forceinline__ bool anchored(const MsParams& P, int j) {
+    return is_ckpt(j, P.S, P.ckpt_every) || recompute(P, j);
+  }
+  // Slice j is the last slice of a segment to be recomputed: the reverse
+  // sweep reaches that segment there.
+  __device__ __forceinline__ bool entry(const MsParams& P, int j) {
+    locate(P, j);
+    return rc && j > a && j == e - 1;
+  }
+};
 
 // fftfreq(N) in cycles/pixel for natural index k
 template <int N>
@@ -157,6 +222,7 @@ struct Work {
   Lane<C> ln;
   int b, part, cy, cx;
   Exchange x;
+  SegFlags seg;
   __device__ __forceinline__ Work(int t, int b_, int part_) : ln(t, part_), b(b_), part(part_) {}
 };
 
@@ -389,6 +455,44 @@ __device__ __forceinline__ void forward_slice(float2 (&v)[C::R], float (&ca)[C::
   }
 }
 
+template <class C>
+__device__ __forceinline__ float2* recomp_ptr(const MsParams& P, const Work<C>& wk, int slot) {
+  return P.recomp + (((size_t)wk.b * P.nrec + slot) * C::K + wk.part) * (C::R * C::THREADS);
+}
+
+// The waves entering slices a+1 .. e-1 of the segment that starts at the
+// checkpoint of slice a (e: the next checkpoint), recomputed by the forward
+// recursion with the same arithmetic as the forward sweep (tiles that
+// prefetch modulate with make_trans, the others with modulate) and stored
+// in the position's recompute slots; `v` is working storage.  The reverse
+// sweep's other state (the adjoint field, a carried transmission) is not
+// touched.
+template <class C, int REPR, bool VAR>
+__device__ __forceinline__ void recompute_segment(float2 (&v)[C::R], const MsParams& P, MsShared<C>& sh,
+                                                  Work<C>& wk, const ChunkOffsets& o, int a) {
+  const int e = min(a + P.ckpt_every, P.S - 1);
+  field_load<C>(v, ckpt_ptr<C>(P, wk, ckpt_slot(a, P.S, P.ckpt_every)), wk.ln);
+  for (int i = a; i < e - 1; ++i) {
+    float ca[C::R], cb[C::R];
+    if ((i & 1) == 0) load_chunk<C, true>(ca, cb, P, o, i);
+    else load_chunk<C, false>(ca, cb, P, o, i);
+    if constexpr (C::PREFETCH) {
+      float2 t[C::R];
+      float g2[C::R];
+      make_trans<C, REPR, false>(t, g2, ca, cb, P.kdz);
+#pragma unroll
+      for (int m = 0; m < C::R; ++m) v[m] = cmul(v[m], t[m]);
+    } else {
+      modulate<C, REPR>(v, ca, cb, P.kdz);
+    }
+    if constexpr (VAR) gap_table<C>(sh, P, wk.ln, i);
+    prop<C, false, !VAR>(v, sh, wk.ln);
+    xfer<C>(v, sh, wk, false, false);
+    prop<C, false, !VAR>(v, sh, wk.ln);
+    field_store<C>(v, recomp_ptr<C>(P, wk, i - a), wk.ln);
+  }
+}
+
 // Reverse slice step j (layout ROW/COL): gradient of slice j, then the two
 // fields are taken back to slice j-1 by the adjoint propagator.
 //   in : psi = phi_j (the wave leaving slice j, rebuilt by the backward
@@ -402,8 +506,10 @@ __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam
                                                float (&cb)[C::R], const MsParams& P, MsShared<C>& sh, Work<C>& wk,
                                                const ChunkOffsets& o, int j) {
   const Lane<C>& ln = wk.ln;
-  const bool anchored = is_ckpt(j, P.S, P.ckpt_every);
-  if (anchored) field_load<C>(psi, ckpt_ptr<C>(P, wk, ckpt_slot(j, P.S, P.ckpt_every)), ln);  // psi_j exactly
+  const bool stored = is_ckpt(j, P.S, P.ckpt_every);
+  const bool anchored = stored || wk.seg.recompute(P, j);
+  if (stored) field_load<C>(psi, ckpt_ptr<C>(P, wk, ckpt_slot(j, P.S, P.ckpt_every)), ln);  // psi_j exactly
+  else if (anchored) field_load<C>(psi, recomp_ptr<C>(P, wk, j - wk.seg.a - 1), ln);   // recomputed
   load_chunk<C, ROW>(ca, cb, P, o, j);
   const bool grads = P.gstage != nullptr;
   const rsrc_t rga = grads ? stage_rsrc<C>(P, wk.b, j, 0) : make_rsrc(P.a, 0);
@@ -435,7 +541,7 @@ __device__ __forceinline__ void backward_slice(float2 (&psi)[C::R], float2 (&lam
   }
   if (j > 0) {
     // unequal spacing: the gap gradient needs psi across the gap every time
-    const bool need_psi = VAR || !is_ckpt(j - 1, P.S, P.ckpt_every);
+    const bool need_psi = VAR || !wk.seg.anchored(P, j - 1);
     if (need_psi) {
       float gacc = 0.f;
       if constexpr (VAR) {
@@ -486,8 +592,10 @@ __device__ __forceinline__ void backward_slice_pf(float2 (&psi)[C::R], float2 (&
                                                   float (&g2)[C::R], const MsParams& P, MsShared<C>& sh,
                                                   Work<C>& wk, const ChunkOffsets& o, int j) {
   const Lane<C>& ln = wk.ln;
-  const bool anchored = is_ckpt(j, P.S, P.ckpt_every);
-  if (anchored) field_load<C>(psi, ckpt_ptr<C>(P, wk, ckpt_slot(j, P.S, P.ckpt_every)), ln);  // psi_j exactly
+  const bool stored = is_ckpt(j, P.S, P.ckpt_every);
+  const bool anchored = stored || wk.seg.recompute(P, j);
+  if (stored) field_load<C>(psi, ckpt_ptr<C>(P, wk, ckpt_slot(j, P.S, P.ckpt_every)), ln);  // psi_j exactly
+  else if (anchored) field_load<C>(psi, recomp_ptr<C>(P, wk, j - wk.seg.a - 1), ln);   // recomputed
   const bool grads = P.gstage != nullptr;
   const rsrc_t rga = grads ? stage_rsrc<C>(P, wk.b, j, 0) : make_rsrc(P.a, 0);
   const rsrc_t rgb = grads ? stage_rsrc<C>(P, wk.b, j, 1) : make_rsrc(P.b, 0);
@@ -524,7 +632,7 @@ __device__ __forceinline__ void backward_slice_pf(float2 (&psi)[C::R], float2 (&
     float ca[C::R], cb[C::R];
     load_chunk<C, !ROW>(ca, cb, P, o, j - 1);   // in flight during the propagation
     // unequal spacing: the gap gradient needs psi across the gap every time
-    const bool need_psi = VAR || !is_ckpt(j - 1, P.S, P.ckpt_every);
+    const bool need_psi = VAR || !wk.seg.anchored(P, j - 1);
     if (need_psi) {
       prop<C, true, !VAR>(psi, sh, ln);
       prop<C, true, !VAR>(lam, sh, ln);
@@ -607,6 +715,7 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
   const Lane<C>& ln = wk.ln;
   constexpr int N = C::N;
   constexpr int NN = N * N;
+  wk.seg = SegFlags();                        // decisions belong to this job's object
   wk.cy = P.corner[2 * b];
   wk.cx = P.corner[2 * b + 1];
   const float sy = P.shift[2 * b], sx = P.shift[2 * b + 1];
@@ -772,6 +881,9 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
       --j;
     }
     for (; j >= 1; j -= 2) {
+      // a segment to recompute is reached at j or j - 1 (slice j is then its
+      // checkpoint or its last slice, so psi is free)
+      if (wk.seg.entry(P, j) || wk.seg.entry(P, j - 1)) recompute_segment<C, REPR, VAR>(psi, P, sh, wk, o, wk.seg.a);
       backward_slice_pf<C, REPR, true, VAR>(psi, v, tr, g2, P, sh, wk, o, j);
       backward_slice_pf<C, REPR, false, VAR>(psi, v, tr, g2, P, sh, wk, o, j - 1);
     }
@@ -783,6 +895,7 @@ __device__ __forceinline__ void process_position(const MsParams& P, MsShared<C>&
     }
     // now slice j is even (ROW); pairs (j ROW, j-1 COL) down to slice 0
     for (; j >= 1; j -= 2) {
+      if (wk.seg.entry(P, j) || wk.seg.entry(P, j - 1)) recompute_segment<C, REPR, VAR>(psi, P, sh, wk, o, wk.seg.a);
       backward_slice<C, REPR, true, VAR>(psi, v, ca, cb, P, sh, wk, o, j);
       backward_slice<C, REPR, false, VAR>(psi, v, ca, cb, P, sh, wk, o, j - 1);
     }
@@ -983,6 +1096,52 @@ __global__ void __launch_bounds__(C::THREADS) probe_spectrum_kernel(const float2
 
 static __global__ void reset_ints_kernel(int* p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// Per slice j, the largest -log|t| over the slice's voxels, i.e. the most a
+// division by t_j can amplify a value (log scale; negative values count as
+// 0): k dz beta for delta/beta objects, -log|O| for real/imaginary ones
+// (infinite where O = 0).  Non-negative floats order like their bit
+// patterns, so the workgroups of a slice combine by an integer maximum into
+// out[j] (cleared before).  NaN voxels are ignored.
+template <int REPR>
+__device__ __forceinline__ float absorb_gain(float kdz, float x, float y) {
+  if constexpr (REPR == ADORYM_OBJ_DELTA_BETA) {
+    return kdz * y;
+  } else {
+    const float m2 = x * x + y * y;
+    return m2 > 0.f ? -0.5f * logf(m2) : INFINITY;
+  }
+}
+template <int REPR>
+static __global__ void __launch_bounds__(256) absorb_bound_kernel(const float* __restrict__ a,
+                                                                  const float* __restrict__ b, size_t plane,
+                                                                  float kdz, unsigned* __restrict__ out) {
+  __shared__ float wmax[4];
+  const int j = blockIdx.y;
+  const float* pa = a + (size_t)j * plane;
+  const float* pb = b + (size_t)j * plane;
+  float mx = 0.f;
+  const size_t stride = (size_t)gridDim.x * 256;
+  if ((plane & 3) == 0 && ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0) {
+    // four voxels per load (every slice starts on a 16-byte boundary)
+    const float4* qa = reinterpret_cast<const float4*>(pa);
+    const float4* qb = reinterpret_cast<const float4*>(pb);
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < plane / 4; i += stride) {
+      const float4 y = qb[i];
+      const float4 x = REPR == ADORYM_OBJ_DELTA_BETA ? y : qa[i];
+      mx = fmaxf(mx, fmaxf(fmaxf(absorb_gain<REPR>(kdz, x.x, y.x), absorb_gain<REPR>(kdz, x.y, y.y)),
+                           fmaxf(absorb_gain<REPR>(kdz, x.z, y.z), absorb_gain<REPR>(kdz, x.w, y.w))));
+    }
+  } else {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < plane; i += stride)
+      mx = fmaxf(mx, absorb_gain<REPR>(kdz, REPR == ADORYM_OBJ_DELTA_BETA ? 0.f : pa[i], pb[i]));
+  }
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(out + j, __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]))));
 }
 
 // Sums of the per-position partials: probe-gradient spectrum (natural
@@ -1190,8 +1349,8 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 constexpr int kMaxSplit = 8;   // largest K any kernel uses
 
 struct WsLayout {
-  size_t q, gsum, loss_part, gs_part, counters, xcc, aux, gacc, ckpt, xbuf, stage, total;
-  int nslots;
+  size_t q, gsum, loss_part, gs_part, counters, xcc, aux, gacc, ckpt, recomp, xbuf, stage, total;
+  int nslots, nrec;
 };
 
 // Workspace of a loss+gradient call; forward_only: of a forward call (no
@@ -1201,17 +1360,19 @@ inline WsLayout ws_layout(const adorym_geom* g, int batch, bool forward_only = f
   const size_t nn = (size_t)g->n * g->n;
   const int S = g->n_slices, C = g->ckpt_every;
   w.nslots = (S - 1) / C + 1 + (((S - 1) % C) != 0 ? 1 : 0);
+  w.nrec = std::max(0, std::min(C - 1, S - 2));      // interior slices of a segment
   size_t off = 0;
   w.q = off; off += align256(nn * sizeof(float2));
   w.gsum = off; off += align256(nn * sizeof(float2));
   w.loss_part = off; off += align256((size_t)batch * kMaxSplit * sizeof(double));
   w.gs_part = off; off += align256((size_t)batch * kMaxSplit * 2 * sizeof(double));
-  w.counters = off; off += align256((size_t)batch * sizeof(int));
+  w.counters = off; off += align256((size_t)(batch + S) * sizeof(int));   // then the S slice bounds
   w.xcc = off; off += align256((size_t)batch * kMaxSplit * sizeof(int));
   w.aux = off; off += align256(64 * sizeof(int));   // probe kernels: 2 counters + XCD ids
   w.xbuf = off; off += align256((size_t)batch * 4 * nn * sizeof(float2));
   w.gacc = off; if (!forward_only) off += align256((size_t)batch * nn * sizeof(float2));
   w.ckpt = off; if (!forward_only) off += align256((size_t)batch * w.nslots * nn * sizeof(float2));
+  w.recomp = off; if (!forward_only) off += align256((size_t)batch * w.nrec * nn * sizeof(float2));
   w.stage = off; if (!forward_only) off += align256((size_t)batch * S * 2 * nn * sizeof(float));
   w.total = off;
   return w;
@@ -1268,15 +1429,17 @@ MsParams make_params(adorym_ctx* ctx, const adorym_geom* g, const float* a, cons
   P.g_a = g_a; P.g_b = g_b;
   P.gstage = g_a ? reinterpret_cast<float*>(base + w.stage) : nullptr;
   P.ckpt = reinterpret_cast<float2*>(base + w.ckpt);
+  P.recomp = reinterpret_cast<float2*>(base + w.recomp);
   P.gacc = with_probe_grad ? reinterpret_cast<float2*>(base + w.gacc) : nullptr;
   P.loss_part = reinterpret_cast<double*>(base + w.loss_part);
   P.gs_part = reinterpret_cast<double*>(base + w.gs_part);
   P.xbuf = reinterpret_cast<float2*>(base + w.xbuf);
   P.counters = reinterpret_cast<int*>(base + w.counters);
+  P.absorb = reinterpret_cast<const float*>(base + w.counters) + batch;
   P.xcc = reinterpret_cast<int*>(base + w.xcc);
   P.err = ctx->d_err;
   P.B = batch; P.S = g->n_slices; P.Ly = g->obj_ny; P.Lx = g->obj_nx;
-  P.ckpt_every = g->ckpt_every; P.nslots = w.nslots;
+  P.ckpt_every = g->ckpt_every; P.nslots = w.nslots; P.nrec = w.nrec;
   P.loss = g->loss;
   P.kdz = (float)(2.0 * M_PI / g->wavelength_m * g->slice_dz_m);
   P.chirp = g->wavelength_m * g->slice_dz_m / (g->pixel_m * g->pixel_m);
@@ -1292,13 +1455,25 @@ template <int N, int L>
 using ProbeCfg = TileCfg<N, L, (N >= 128 ? 4 : 1)>;
 
 // Per-job work before the multislice kernel: clear the barrier counters,
-// probe spectrum.
+// probe spectrum; before a reverse sweep that steps backwards through
+// slices (`reverse`), the per-slice absorption bounds.
 template <int N, int L>
-void launch_prologue(const MsParams& P, const float* probe, const adorym_geom* g, hipStream_t st) {
+void launch_prologue(const MsParams& P, const float* probe, const adorym_geom* g, hipStream_t st, bool reverse) {
   using PC = ProbeCfg<N, L>;
   const WsLayout w = ws_layout(g, P.B);
   int* aux = reinterpret_cast<int*>(reinterpret_cast<char*>(P.counters) - w.counters + w.aux);
-  hipLaunchKernelGGL(reset_ints_kernel, dim3(1), dim3(256), 0, st, P.counters, P.B);
+  hipLaunchKernelGGL(reset_ints_kernel, dim3(1), dim3(256), 0, st, P.counters, P.B + P.S);
+  if (reverse && P.ckpt_every > 1 && P.S > 2) {
+    const size_t plane = (size_t)P.Ly * P.Lx;
+    const dim3 grid((unsigned)std::min<size_t>(64, (plane + 16383) / 16384), P.S);
+    unsigned* bound = reinterpret_cast<unsigned*>(P.counters + P.B);
+    if (g->obj_repr == ADORYM_OBJ_DELTA_BETA)
+      hipLaunchKernelGGL(absorb_bound_kernel<ADORYM_OBJ_DELTA_BETA>, grid, dim3(256), 0, st, P.a, P.b, plane, P.kdz,
+                         bound);
+    else
+      hipLaunchKernelGGL(absorb_bound_kernel<ADORYM_OBJ_REAL_IMAG>, grid, dim3(256), 0, st, P.a, P.b, plane, P.kdz,
+                         bound);
+  }
   hipLaunchKernelGGL(reset_ints_kernel, dim3(1), dim3(64), 0, st, aux, 64);
   hipLaunchKernelGGL((probe_spectrum_kernel<PC>), dim3(PC::K), dim3(PC::THREADS), 0, st,
                      reinterpret_cast<const float2*>(probe), const_cast<float2*>(P.q), P.xbuf, aux, aux + 8,
@@ -1358,7 +1533,7 @@ adorym_status run(adorym_ctx* ctx, const adorym_geom* g, const float* a, const f
   P.ksplit = K;
   hipStream_t st = ctx->stream;
   const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
-  launch_prologue<N, probe_lanes<N>()>(P, probe, g, st);
+  launch_prologue<N, probe_lanes<N>()>(P, probe, g, st, with_loss);
   if (df)
     hipLaunchKernelGGL(defocus_spectrum_kernel, dim3((N * N + 255) / 256), dim3(256), 0, st,
                        const_cast<float2*>(P.q), N, df->c0, df->dist);
@@ -1415,7 +1590,7 @@ adorym_status run_gaps(adorym_ctx* ctx, const adorym_geom* g, const float* a, co
   P.gd_part = with_loss ? reinterpret_cast<double*>(static_cast<char*>(ws) + ws_layout(g, batch).total) : nullptr;
   hipStream_t st = ctx->stream;
   const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
-  launch_prologue<N, probe_lanes<N>()>(P, probe, g, st);
+  launch_prologue<N, probe_lanes<N>()>(P, probe, g, st, with_loss);
   if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
   if (with_loss) launch_ms<C, true, true>(P, g->obj_repr, st);
   else launch_ms<C, false, true>(P, g->obj_repr, st);
@@ -1521,7 +1696,7 @@ adorym_status run_nf(adorym_ctx* ctx, const adorym_geom* g, const float* a, cons
   hipLaunchKernelGGL(nf_table_kernel, dim3((N * N + 255) / 256), dim3(256), 0, st, N, g->wavelength_m, g->pixel_m,
                      kind, dist, n_dist, reinterpret_cast<float2*>(base + l.h), reinterpret_cast<float*>(base + l.dph));
   const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
-  launch_prologue<N, probe_lanes<N>()>(P, probe, g, st);
+  launch_prologue<N, probe_lanes<N>()>(P, probe, g, st, with_loss);
   if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
   if (with_loss) launch_ms<C, true, false, true>(P, g->obj_repr, st);
   else launch_ms<C, false, false, true>(P, g->obj_repr, st);
@@ -1604,7 +1779,7 @@ adorym_status run_split(adorym_ctx* ctx, const adorym_geom* g, const float* a, c
   P.adj_scale = adj_scale;
   hipStream_t st = ctx->stream;
   const bool timed = ctx->prof && ctx->ev_used + 2 <= (int)ctx->ev.size();
-  launch_prologue<N, probe_lanes<N>()>(P, probe, g, st);
+  launch_prologue<N, probe_lanes<N>()>(P, probe, g, st, with_loss);
   if (timed) (void)hipEventRecord(ctx->ev[ctx->ev_used], st);
   if (with_loss) launch_ms<C, true, false, false, true>(P, g->obj_repr, st);
   else launch_ms<C, false, false, false, true>(P, g->obj_repr, st);
@@ -1637,7 +1812,8 @@ void launch_batched(const MsParams* jobs, const int2* items, int n_items, int* t
   void adorym_ms::launch_batched<N_, L_, K_>(const adorym_ms::MsParams*, const int2*, int, int*, int*, int*, int*, \
                                               float2*, int*, int, int, hipStream_t)
 #define ADORYM_PROLOGUE_SIGNATURE(N_, L_) \
-  void adorym_ms::launch_prologue<N_, L_>(const adorym_ms::MsParams&, const float*, const adorym_geom*, hipStream_t)
+  void adorym_ms::launch_prologue<N_, L_>(const adorym_ms::MsParams&, const float*, const adorym_geom*, hipStream_t, \
+                                          bool)
 #define ADORYM_EPILOGUE_SIGNATURE(N_, L_) \
   void adorym_ms::launch_epilogue<N_, L_>(const adorym_ms::MsParams&, void*, const adorym_geom*, double*, float*, \
                                           float*, hipStream_t, const adorym_ms::Defocus*)

@@ -55,3 +55,96 @@ class Case:
 
     def oracle_loss_grad(self):
         return om.loss_grad(self.geom, self.a, self.b, self.p, self.pos, self.i_meas)
+
+
+# ---------------------------------------------------------------------------
+# Tolerances (float32 GPU path against the float64 oracle)
+# ---------------------------------------------------------------------------
+TOL_I = 1e-5      # intensities, relative L2
+TOL_G = 1e-4      # gradients, relative L2
+
+# Evaluation points at which float32 storage of the wave alone moves the
+# gradient by several times TOL_G: rounding each slice's wave to complex64
+# once, with every other operation exact, already does.  That premise is
+# pinned on the CPU for each entry (tests/test_fp32_limits.py).  A test at
+# such a point still asserts the regression guard below (a fixed bound, not
+# a parity claim), and reports the TOL_G comparison as an expected failure
+# with the measured error.
+FP32_LIMITED = {
+    "c2-vacuum-poisson": dict(
+        guard=1.5e-3,
+        reason=("64-slice minibatch at the delta = beta = 0 start, Poisson loss: the residual "
+                "1 - I_meas/(I + eps) of far-field pixels the vacuum model barely lights amplifies the "
+                "absolute float32 noise of the detector field; rounding each slice's wave to complex64 "
+                "alone moves the object and probe gradients by 6.3e-4 and the vanishing shift "
+                "gradients by 1.3e-4 of their scale")),
+    "c3-shift": dict(
+        guard=5e-4,
+        reason=("shift gradients of the 128-slice workload's sampled positions (Gaussian loss, half the "
+                "true object): each is a small real sum over the probe spectrum, and rounding each "
+                "slice's wave to complex64 alone moves them by 1.7e-4")),
+    "tilt-256-poisson": dict(
+        guard=1e-3,
+        reason=("256-slice tilt angle at half the true object, Poisson loss: rounding each of the 256 "
+                "slices' waves to complex64 alone moves the object and probe gradients by 1.75e-4")),
+    "mix-half-object": dict(
+        guard=3e-3,
+        outputs={14: ("g_shift",), 17: ("g_b", "g_probe"), 13: ("g_b", "g_probe"),
+                 18: ("g_a", "g_b", "g_probe", "g_shift")},
+        reason=("the 32-scan mix's smallest job of each probe size at half the true object: a float32 "
+                "evaluation with single-precision library FFTs misses the tolerance on these outputs "
+                "(1.4e-4 to 1.2e-3), the far-field residual of barely lit pixels amplifying the "
+                "transforms' absolute rounding")),
+}
+
+
+def assert_grads(pairs, limited=None, vanishing=(), defer=False):
+    """Relative L2 of each (name, got, ref) gradient against TOL_G, and for
+    each (name, got, ref, scale) of ``vanishing`` the absolute error against
+    TOL_G * scale (outputs whose exact value vanishes at the evaluation point:
+    relative L2 is meaningless there, so the bound is TOL_G times the
+    output's norm at a non-degenerate point of the same scan).
+
+    ``limited``: a key of FP32_LIMITED; the outputs are then held to its
+    regression guard and a miss of TOL_G is reported with pytest.xfail (at
+    once, or, with ``defer``, returned as messages for xfail_if)."""
+    over = []
+    for name, got, ref in pairs:
+        e = rel_l2(got, ref)
+        print(f"{name}: GPU rel-L2 {e:.3e}")
+        if limited is None:
+            assert e <= TOL_G, (name, e)
+        else:
+            assert e <= FP32_LIMITED[limited]["guard"], (name, e, limited)
+            if e > TOL_G:
+                over.append(f"{name} {e:.2e}")
+    for name, got, ref, scale in vanishing:
+        err = float(np.linalg.norm(np.asarray(got, dtype=np.float64).ravel()
+                                   - np.asarray(ref, dtype=np.float64).ravel()))
+        print(f"{name}: |GPU - oracle| {err:.3e} = {err / scale:.3e} x the scale {scale:.3e} "
+              f"(|oracle| {np.linalg.norm(ref):.3e})")
+        assert scale > 0
+        if limited is None:
+            assert err <= TOL_G * scale, (name, err, scale)
+        else:
+            assert err <= FP32_LIMITED[limited]["guard"] * scale, (name, err, scale, limited)
+            if err > TOL_G * scale:
+                over.append(f"{name} {err / scale:.2e} of its scale")
+    msgs = [f"{limited}: {', '.join(over)} > {TOL_G:g} ({FP32_LIMITED[limited]['reason']})"] if over else []
+    if not defer:
+        xfail_if(msgs)
+    return msgs
+
+
+def xfail_if(msgs):
+    """Report FP32_LIMITED misses of TOL_G (collected with defer=True) as an
+    expected failure, after every other assertion of the test has passed."""
+    import pytest
+    if msgs:
+        pytest.xfail("; ".join(msgs))
+
+
+def loss_tolerance(geom, i_ref, i_meas):
+    """TOL_I * ||I|| * ||dL/dI|| (Cauchy-Schwarz), doubled for rounding."""
+    dldi = om.loss_dI(geom.loss, i_ref, i_meas, geom.eps, i_ref.size)
+    return 2 * TOL_I * np.linalg.norm(i_ref) * np.linalg.norm(dldi)

@@ -48,14 +48,16 @@ def test_geom_struct_layout_matches_c(tmp_path):
 def test_job_struct_layout_matches_c(tmp_path):
     src = tmp_path / "probe.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "adorym.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(adorym_job),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(adorym_job),'
                    ' offsetof(adorym_job, obj_a), offsetof(adorym_job, batch),'
-                   ' offsetof(adorym_job, i_meas), offsetof(adorym_job, ws_bytes)); return 0;}\n')
+                   ' offsetof(adorym_job, i_meas), offsetof(adorym_job, ws_bytes),'
+                   ' offsetof(adorym_job, intensity)); return 0;}\n')
     exe = tmp_path / "probe"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     J = _lib.Job
-    assert got == [ctypes.sizeof(J), J.obj_a.offset, J.batch.offset, J.i_meas.offset, J.ws_bytes.offset]
+    assert got == [ctypes.sizeof(J), J.obj_a.offset, J.batch.offset, J.i_meas.offset, J.ws_bytes.offset,
+                   J.intensity.offset]
 
 
 def _geom(**kw):
@@ -72,11 +74,13 @@ def test_workspace_size_formula():
     nn = 128 * 128 * 8                  # one complex64 field
     slots = 63 // 16 + 1 + 1            # slices 0, 16, 32, 48 and the last (63)
     # probe spectrum + its gradient sum, loss and shift partials for up to 8
-    # workgroups per position, barrier counters and XCD ids, probe-kernel counters,
-    # probe-gradient partials, checkpoints, two double-buffered exchange fields
-    # per position, and every position's float32 object gradient of both planes
-    small = 2 * nn + 50 * 8 * 8 + 50 * 8 * 2 * 8 + 50 * 4 + 50 * 8 * 4 + 64 * 4 + 50 * 4 * nn
-    expect = small + 50 * nn + 50 * slots * nn + 50 * 64 * 2 * 128 * 128 * 4
+    # workgroups per position, barrier counters and the 64 slices' absorption
+    # bounds, XCD ids, probe-kernel counters, probe-gradient partials,
+    # checkpoints, the 15 interior waves of one recomputed checkpoint segment,
+    # two double-buffered exchange fields per position, and every position's
+    # float32 object gradient of both planes
+    small = 2 * nn + 50 * 8 * 8 + 50 * 8 * 2 * 8 + (50 + 64) * 4 + 50 * 8 * 4 + 64 * 4 + 50 * 4 * nn
+    expect = small + 50 * nn + 50 * slots * nn + 50 * 15 * nn + 50 * 64 * 2 * 128 * 128 * 4
     assert expect <= size < expect + 12 * 256
     assert lib.adorym_workspace_size(ctypes.byref(_geom(n_slices=0)), 50) == 0
     assert lib.adorym_workspace_size(ctypes.byref(g), 0) == 0

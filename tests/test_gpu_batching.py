@@ -68,66 +68,79 @@ def test_autotuner_sets_a_supported_split(ctx, tmp_path):
     r.close()
 
 
-def test_mixed_scan_plan_matches_oracle_on_sampled_positions(ctx):
+# the smallest job of each probe size in the 32-scan mix (positions x slices x N^2)
+COMPARED_JOBS = {64: 14, 96: 17, 128: 13, 192: 18}
+
+
+def test_mixed_scan_plan_matches_oracle_on_one_job_per_probe_size(ctx):
     """The 32-scan mix in the launch configuration the benchmark times
-    (autotuned split per probe size, one captured plan), at half the true
-    object so that shift gradients do not vanish, with seeded Poisson data
-    (no input comes from the GPU).  A position's shift gradient depends on
-    that position alone: the oracle evaluates it on a one-position batch,
-    whose loss is normalised by N^2 instead of B N^2, so the plan's value is
-    that divided by B.  Sampled: first, middle and last position of the first
-    job of each probe size."""
+    (autotuned split per probe size, one captured plan over every job's whole
+    position list), at half the true object.  The smallest job of each probe
+    size gets measured data from the oracle at its true object (Poisson for
+    the Poisson-loss jobs), and its intensities, loss and every gradient are
+    compared with the oracle (no input comes from the GPU).  The other jobs'
+    data are seeded Poisson noise at the probe's mean level: they share the
+    persistent launches but do not enter the compared jobs' outputs.  The
+    outputs FP32_LIMITED['mix-half-object'] lists for each compared job are
+    held to its guard; the others to the tolerance."""
     import torch
     from oracle import multislice as om
     from paper_2012_12686_amd.batch import BatchRunner, DeviceScan
-    from paper_2012_12686_amd import Geometry, split_positions
-    from tests.fp32_model import loss_grad_fp32
-    from tests.gpu_helpers import f32
+    from paper_2012_12686_amd import Geometry
+    from tests.gpu_helpers import FP32_LIMITED, TOL_I, assert_grads, f32, loss_tolerance, xfail_if
     scans = synth.mixed_scan_jobs()
+    assert {scans[j].n: j for j in COMPARED_JOBS.values()} == {n: j for n, j in COMPARED_JOBS.items()}
     dev = ctx.device
     t = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device=dev)
     rng = np.random.default_rng(4040)
-    dscans = []
-    for sc in scans:
-        level = float(np.sum(np.abs(sc.probe) ** 2)) / sc.n ** 2
-        im = rng.poisson(level, size=(len(sc.positions), sc.n, sc.n)).astype(np.float32)
-        corner, shift = split_positions(t(sc.positions, torch.float64))
-        a = t(0.5 * sc.obj_a, torch.float32)
-        b = t(0.5 * sc.obj_b, torch.float32)
+    dscans, refs = [], {}
+    for i, sc in enumerate(scans):
+        geom = om.Geometry.from_scan(sc)
+        a64, b64, p64 = f32(0.5 * sc.obj_a), f32(0.5 * sc.obj_b), f32(sc.probe)
+        corner_np, shift_np = synth.split_positions(np.asarray(sc.positions, dtype=np.float64))
+        shift_np = f32(shift_np)
+        if i in COMPARED_JOBS.values():
+            i_true = om.forward(geom, sc.obj_a, sc.obj_b, sc.probe, np.asarray(sc.positions, dtype=np.float64))
+            if sc.loss == "poisson":
+                i_true = np.random.default_rng(500 + i).poisson(i_true)
+            im = f32(i_true)
+            pos = corner_np + shift_np
+            refs[i] = (om.forward(geom, a64, b64, p64, pos), om.loss_grad(geom, a64, b64, p64, pos, im), geom, im)
+        else:
+            level = float(np.sum(np.abs(sc.probe) ** 2)) / sc.n ** 2
+            im = rng.poisson(level, size=(len(sc.positions), sc.n, sc.n))
+        a, b = t(a64, torch.float32), t(b64, torch.float32)
         z = torch.zeros_like
-        dscans.append(DeviceScan(Geometry.from_scan(sc), a, b, t(sc.probe, torch.complex64), corner, shift,
-                                 t(im, torch.float32), z(a), z(a), z(b), z(b)))
+        dscans.append(DeviceScan(Geometry.from_scan(sc), a, b, t(p64, torch.complex64), t(corner_np, torch.int32),
+                                 t(shift_np, torch.float32), t(im, torch.float32), z(a), z(a), z(b), z(b)))
     r = BatchRunner(ctx, dscans)
-    ctx.autotune(r.jobs, reps=1)
-    r.build_plan()
-    r.capture()
-    r.graph.replay()
-    torch.cuda.synchronize()
-    ctx.sync_error()
-    seen = set()
     try:
-        for sc, ds, job in zip(scans, dscans, r.jobs):
-            if sc.n in seen:
-                continue
-            seen.add(sc.n)
-            B = len(sc.positions)
-            geom = om.Geometry.from_scan(sc)
-            a64, b64, p64 = f32(0.5 * sc.obj_a), f32(0.5 * sc.obj_b), f32(sc.probe)
-            got_all = job.out["g_shift"].cpu().numpy().astype(np.float64)
-            corner = ds.corner.cpu().numpy().astype(np.float64)
-            shift = ds.shift.cpu().numpy().astype(np.float64)
-            im = ds.i_meas.cpu().numpy().astype(np.float64)
-            got, ref, model = [], [], []
-            for bidx in (0, B // 2, B - 1):
-                pos = (corner[bidx] + shift[bidx])[None]
-                g_ref = om.loss_grad(geom, a64, b64, p64, pos, im[bidx:bidx + 1])[4][0] / B
-                g_mod = np.asarray(loss_grad_fp32(geom, a64, b64, p64, pos, im[bidx:bidx + 1])[4][0]) / B
-                got.append(got_all[bidx]); ref.append(g_ref); model.append(g_mod)
-            e_gpu, e_f32 = rel_l2(np.array(got), np.array(ref)), rel_l2(np.array(model), np.array(ref))
-            print(f"{sc.name}: sampled shift gradients GPU rel-L2 {e_gpu:.3e}, float32-model floor {e_f32:.3e}")
-            assert np.linalg.norm(np.array(ref)) > 0
-            assert e_gpu <= max(1e-4, 3.0 * e_f32), (sc.name, e_gpu, e_f32)
-        assert seen == {64, 96, 128, 192}
+        ctx.autotune(r.jobs, reps=1)
+        for i in COMPARED_JOBS.values():
+            sc = scans[i]
+            r.jobs[i].out["intensity"] = torch.empty((len(sc.positions), sc.n, sc.n), dtype=torch.float32,
+                                                     device=dev)
+        r.build_plan()
+        r.capture()
+        r.graph.replay()
+        torch.cuda.synchronize()
+        ctx.sync_error()
+        msgs = []
+        for n, i in COMPARED_JOBS.items():
+            i_ref, (L, ga, gb, gp, gs), geom, im = refs[i]
+            got = {k: v.cpu().numpy() for k, v in r.jobs[i].out.items()}
+            e_i = rel_l2(got["intensity"], i_ref)
+            print(f"job {i} (N={n}, S={scans[i].n_slices}, {len(scans[i].positions)} positions): "
+                  f"intensity rel-L2 {e_i:.3e}")
+            assert e_i <= TOL_I, (n, e_i)
+            assert abs(float(got["loss"]) - L) <= loss_tolerance(geom, i_ref, im), (n, float(got["loss"]), L)
+            assert np.linalg.norm(gs) > 0
+            limited = FP32_LIMITED["mix-half-object"]["outputs"][i]
+            pairs = [(f"N={n} {k}", got[k], ref) for k, ref in (("g_a", ga), ("g_b", gb), ("g_probe", gp),
+                                                                 ("g_shift", gs))]
+            assert_grads([q for q in pairs if q[0].split()[1] not in limited])
+            msgs += assert_grads([q for q in pairs if q[0].split()[1] in limited], "mix-half-object", defer=True)
+        xfail_if(msgs)
     finally:
         for n in (64, 96, 128, 192):
             ctx.set_split(n, 0)

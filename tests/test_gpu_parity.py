@@ -1,25 +1,28 @@
 """GPU parity: the HIP library against the FP64 oracle, through the C ABI.
 
-Tolerances (float32 GPU path vs float64 oracle, same float32-rounded inputs):
+Tolerances (float32 GPU path vs float64 oracle, same float32-rounded inputs;
+tests/gpu_helpers.py):
   * intensities: relative L2 <= 1e-5;
   * loss: |dL| <= 2e-5 ||I|| ||dL/dI|| -- the intensity tolerance pushed
     through the loss by Cauchy-Schwarz (per-pixel terms are float32, the sum
     float64);
-  * gradients: relative L2 <= 1e-4, or, at evaluation points where even a
-    faithful float32 evaluation of the same mathematics cannot reach 1e-4
-    (the float32 reference model of tests/fp32_model.py), <= 3x that
-    model's own error.  Both numbers are printed.
+  * gradients: relative L2 <= 1e-4.  Outputs whose exact value vanishes at
+    the evaluation point (shift gradients at a vacuum object) are held to an
+    absolute bound instead: 1e-4 times their norm at a non-degenerate point
+    of the same scan.  The one evaluation point where float32 storage of the
+    wave alone moves the gradient by several times 1e-4 (the 64-slice
+    minibatch at its vacuum start, FP32_LIMITED) asserts a fixed regression
+    guard and reports the 1e-4 comparison as an expected failure.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
 import synth
-from tests.gpu_helpers import Case, rel_l2
+from tests.gpu_helpers import TOL_G, TOL_I, Case, assert_grads, loss_tolerance as _loss_tol, rel_l2
 
 pytestmark = pytest.mark.gpu
-
-TOL_I = 1e-5
-TOL_G = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -58,23 +61,23 @@ def run_grad(ctx, case, **kw):
 
 def loss_tolerance(case):
     """TOL_I * ||I|| * ||dL/dI|| (Cauchy-Schwarz), doubled for rounding."""
-    from oracle import multislice as om
-    i_ref = case.oracle_forward()
-    dldi = om.loss_dI(case.geom.loss, i_ref, case.i_meas, case.geom.eps, i_ref.size)
-    return 2 * TOL_I * np.linalg.norm(i_ref) * np.linalg.norm(dldi)
+    return _loss_tol(case.geom, case.oracle_forward(), case.i_meas)
 
 
-def check_grads(got, ref, case):
-    from tests.fp32_model import loss_grad_fp32
+def check_grads(got, ref, case, limited=None, shift_scale=None):
+    """Loss within its tolerance; every gradient rel-L2 <= TOL_G (or the
+    FP32_LIMITED entry's guard); with ``shift_scale`` the shift gradients
+    vanish at this point and get the absolute bound instead."""
     L, ga, gb, gp, gs = ref
     tol_l = loss_tolerance(case)
     assert abs(float(got["loss"]) - L) <= tol_l, (float(got["loss"]), L, tol_l)
-    model = loss_grad_fp32(case.geom, case.a, case.b, case.p, case.pos, case.i_meas)
-    names = ("g_a", "g_b", "g_probe", "g_shift")
-    for name, r, m in zip(names, (ga, gb, gp, gs), model[1:]):
-        e_gpu, e_f32 = rel_l2(got[name], r), rel_l2(m, r)
-        print(f"{name}: GPU rel-L2 {e_gpu:.3e}   float32-model floor {e_f32:.3e}")
-        assert e_gpu <= max(TOL_G, 3.0 * e_f32), (name, e_gpu, e_f32)
+    pairs = [("g_a", got["g_a"], ga), ("g_b", got["g_b"], gb), ("g_probe", got["g_probe"], gp)]
+    vanishing = []
+    if shift_scale is None:
+        pairs.append(("g_shift", got["g_shift"], gs))
+    else:
+        vanishing.append(("g_shift", got["g_shift"], gs, shift_scale))
+    assert_grads(pairs, limited, vanishing)
 
 
 # ------------------------------------------------------------------ forward
@@ -235,23 +238,56 @@ def test_loss_is_deterministic(ctx):
 
 # ------------------------------------------------------------------ the named workloads
 
+def _ptycho2d_off_vacuum():
+    """The 2D workload evaluated halfway between vacuum and the true object."""
+    sc = synth.ptycho2d_n64()
+    return dataclasses.replace(sc, eval_obj_a=0.5 * (1.0 + sc.obj_a), eval_obj_b=0.5 * sc.obj_b)
+
+
+def _half_object_64_slices():
+    sc = synth.multislice_n128_s64()
+    return dataclasses.replace(sc, eval_obj_a=0.5 * sc.obj_a, eval_obj_b=0.5 * sc.obj_b)
+
+
 def test_ptychography_2d_n64(ctx):
-    """64x64 probe, one slice, complex object 128x128, 64 raster positions, LSQ."""
+    """64x64 probe, one slice, complex object 128x128, 64 raster positions,
+    LSQ, at the workload's vacuum start (O = 1).  There the far-field
+    intensity does not depend on the probe position, so the shift gradients
+    vanish: they are bounded absolutely by TOL_G times their norm at the
+    off-vacuum point of the next test."""
     case = Case(synth.ptycho2d_n64())
     got = run_grad(ctx, case)
     assert rel_l2(got["intensity"], case.oracle_forward()) <= TOL_I
-    check_grads(got, case.oracle_loss_grad(), case)
+    off = Case(_ptycho2d_off_vacuum())
+    scale = float(np.linalg.norm(off.oracle_loss_grad()[4]))
+    check_grads(got, case.oracle_loss_grad(), case, shift_scale=scale)
+
+
+def test_ptychography_2d_n64_off_vacuum(ctx):
+    """The same scan and data halfway between vacuum and the true object:
+    every output, the shift gradients included, to the tolerances."""
+    case = Case(_ptycho2d_off_vacuum())
+    got = run_grad(ctx, case)
+    assert rel_l2(got["intensity"], case.oracle_forward()) <= TOL_I
+    ref = case.oracle_loss_grad()
+    assert np.linalg.norm(ref[4]) > 0
+    check_grads(got, ref, case)
 
 
 def test_multislice_n128_s64_first_minibatch(ctx):
-    """128x128 probe, 64 slices at 10 nm, 256x256 object, minibatch of 50, Poisson."""
+    """128x128 probe, 64 slices at 10 nm, 256x256 object, minibatch of 50,
+    Poisson, at the benchmark's vacuum start (FP32_LIMITED
+    'c2-vacuum-poisson'; the shift gradients vanish there and are held to
+    TOL_G, or the guard, times their norm at half the true object)."""
     sc = synth.multislice_n128_s64()
     case = Case(sc, idx=slice(0, 50), poisson_seed=2)
     got = run_grad(ctx, case)
     err_i = rel_l2(got["intensity"], case.oracle_forward())
     print("64-slice minibatch intensity rel-L2", err_i)
     assert err_i <= TOL_I
-    check_grads(got, case.oracle_loss_grad(), case)
+    half = Case(_half_object_64_slices(), idx=slice(0, 50), poisson_seed=2)
+    scale = float(np.linalg.norm(half.oracle_loss_grad()[4]))
+    check_grads(got, case.oracle_loss_grad(), case, limited="c2-vacuum-poisson", shift_scale=scale)
 
 
 def test_batched_plan_equals_individual_calls(ctx):
@@ -371,12 +407,14 @@ def test_multislice_n128_s128_full_minibatch_sampled_positions(ctx):
     and shift gradients depend on no other position (the loss is a mean over
     all B N^2 pixels, so the oracle's gradient is rescaled from 3 to 200
     positions).  The measured data of the other positions are copies of a
-    sampled position's (they do not enter the sampled outputs).  The autograd
-    front end must give the call's numbers bit for bit.
+    sampled position's (they do not enter the sampled outputs).  The shift
+    gradients at this point are FP32_LIMITED ('c3-shift').  The fused
+    autograd form must give the call's numbers bit for bit, and the default
+    split form (loss_fwd / loss_bwd, fixed split) those of the call with
+    ADORYM_DETERMINISTIC.
     """
     import torch
     from paper_2012_12686_amd import Geometry, multislice_loss
-    from tests.fp32_model import loss_grad_fp32
     sc = synth.multislice_n128_s128()
     bsz, sample = 200, np.array([0, 101, 199])
     case = Case(sc, idx=sample)
@@ -397,35 +435,110 @@ def test_multislice_n128_s128_full_minibatch_sampled_positions(ctx):
     err_i = rel_l2(got_i, case.oracle_forward())
     print("128-slice minibatch, sampled intensity rel-L2", err_i)
     assert err_i <= TOL_I
-    scale = len(sample) / bsz
-    ref_gs = case.oracle_loss_grad()[4] * scale
-    f32_gs = loss_grad_fp32(case.geom, case.a, case.b, case.p, case.pos, case.i_meas)[4] * scale
+    ref_gs = case.oracle_loss_grad()[4] * (len(sample) / bsz)
     got_gs = out["g_shift"].cpu().numpy()[sample]
-    e_gpu, e_f32 = rel_l2(got_gs, ref_gs), rel_l2(f32_gs, ref_gs)
-    print(f"128-slice minibatch, sampled shift gradients: GPU rel-L2 {e_gpu:.3e}, float32-model floor {e_f32:.3e}")
-    assert e_gpu <= max(TOL_G, 3.0 * e_f32)
-    # the autograd front end on the same inputs
-    a = inp["obj_a"].clone().requires_grad_(True)
-    pos_t = (inp["corner"].double() + inp["shift"].double()).requires_grad_(True)
-    loss = multislice_loss(a, inp["obj_b"], inp["probe"], pos_t, im, geom, ctx)
-    loss.backward()
-    assert float(loss.detach()) == float(out["loss"])
-    assert torch.equal(a.grad, out["g_a"])
-    assert torch.equal(pos_t.grad.float(), out["g_shift"])
+    # the autograd front end on the same inputs, fused and split forms
+    det = ctx.loss_grad(Geometry.from_scan(sc, ckpt_every=16, deterministic=True), **inp, i_meas=im)
+    for lazy, ref in ((False, out), (True, det)):
+        a = inp["obj_a"].clone().requires_grad_(True)
+        pos_t = (inp["corner"].double() + inp["shift"].double()).requires_grad_(True)
+        loss = multislice_loss(a, inp["obj_b"], inp["probe"], pos_t, im, geom, ctx, lazy=lazy)
+        loss.backward()
+        assert float(loss.detach()) == float(ref["loss"]), lazy
+        assert torch.equal(a.grad, ref["g_a"]), lazy
+        assert torch.equal(pos_t.grad.float(), ref["g_shift"]), lazy
+    assert_grads([("g_shift (sampled)", got_gs, ref_gs)], "c3-shift")
+
+
+def test_multislice_n128_s128_three_positions_over_the_full_object(ctx):
+    """The 128-slice workload's three sampled positions as one minibatch over
+    the whole 512x512x128 object (C = 16): every output of the call against
+    the oracle, the object gradients over the full extent included (zero
+    wherever no chunk reaches)."""
+    sc = synth.multislice_n128_s128()
+    case = Case(sc, idx=np.array([0, 101, 199]))
+    got = run_grad(ctx, case, ckpt_every=16)
+    err_i = rel_l2(got["intensity"], case.oracle_forward())
+    print("128-slice, three positions, intensity rel-L2", err_i)
+    assert err_i <= TOL_I
+    ref = case.oracle_loss_grad()
+    L, ga, gb, gp, gs = ref
+    assert abs(float(got["loss"]) - L) <= loss_tolerance(case)
+    for g in (got["g_a"], got["g_b"]):
+        assert g.shape == (128, 512, 512)
+    covered = np.zeros((512, 512), bool)
+    for cy, cx in case.corner:
+        covered[cy:cy + 128, cx:cx + 128] = True
+    assert np.all(got["g_a"][:, ~covered] == 0) and np.all(got["g_b"][:, ~covered] == 0)
+    assert_grads([("g_a", got["g_a"], ga), ("g_b", got["g_b"], gb), ("g_probe", got["g_probe"], gp)])
+    assert_grads([("g_shift", got["g_shift"], gs)], "c3-shift")
 
 
 def test_multislice_n128_s64_first_minibatch_at_half_the_object(ctx):
-    """The same minibatch evaluated at half the true object.  At the
-    benchmark's vacuum start the far-field intensity does not depend on the
-    probe position, so the shift gradients vanish there and are only
-    compared against float32 noise; here they are non-zero and checked to
-    the gradient tolerance like the others."""
-    import dataclasses
-    sc = synth.multislice_n128_s64()
-    sc = dataclasses.replace(sc, eval_obj_a=0.5 * sc.obj_a, eval_obj_b=0.5 * sc.obj_b)
-    case = Case(sc, idx=slice(0, 50), poisson_seed=2)
+    """The same minibatch evaluated at half the true object, where the shift
+    gradients do not vanish: every output to the tolerances."""
+    case = Case(_half_object_64_slices(), idx=slice(0, 50), poisson_seed=2)
     got = run_grad(ctx, case)
     assert rel_l2(got["intensity"], case.oracle_forward()) <= TOL_I
     ref = case.oracle_loss_grad()
     assert np.linalg.norm(ref[4]) > 0
     check_grads(got, ref, case)
+
+
+# ------------------------------------------------------------------ strong absorbers
+
+def _absorbing_case(seed, n, s, lat, npos, repr_, loss):
+    """A scan whose slices absorb strongly: delta/beta with k dz beta up to 0.2
+    per slice (e^-0.2 per slice), or a complex object with |O| mostly near 1
+    and patches down to 0.1 and, in the evaluation object, one voxel at exactly 0 on the first
+    position's beam path.  Inverse stepping through 15 such slices would
+    amplify rounding by up to e^3 (delta/beta) or 10^15 (complex): the
+    reverse sweep must recompute those segments from their checkpoints."""
+    from synth import smooth_random_field
+    sc = synth.small_case(seed=seed, n=n, n_slices=s, lateral=lat, n_pos=npos, obj_repr=repr_, loss=loss,
+                          strength=30.0)
+    rng = np.random.default_rng(seed + 1)
+    shape = sc.obj_shape
+    if repr_ == "delta_beta":
+        kdz = 2 * np.pi / sc.wavelength_m * sc.slice_dz_m
+        beta = smooth_random_field(rng, shape, 2.0, 0.0, 1.0)
+        beta = (beta - beta.min()) / (beta.max() - beta.min()) * 0.2 / kdz
+        return dataclasses.replace(sc, obj_b=beta, eval_obj_b=0.8 * beta)
+    f = smooth_random_field(rng, shape, 2.0, 0.0, 1.0)
+    amp = 1.0 - 0.9 * ((f - f.min()) / (f.max() - f.min())) ** 4     # mostly near 1, patches down to 0.1
+    ph = smooth_random_field(rng, shape, 2.0, -0.5, 0.5)
+    o = amp * np.exp(1j * ph)
+    e = o * (1.0 + 0.02 * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)))
+    cy, cx = np.floor(np.asarray(sc.eval_positions[0]) + 0.5).astype(int)
+    e[s // 2, cy + n // 2, cx + n // 2] = 0.0
+    return dataclasses.replace(sc, obj_a=o.real.copy(), obj_b=o.imag.copy(), eval_obj_a=e.real.copy(),
+                               eval_obj_b=e.imag.copy())
+
+
+@pytest.mark.parametrize("n,s,lat,npos,repr_,loss,k", [
+    (64, 40, 100, 3, "delta_beta", "gaussian", 0),
+    (64, 37, 100, 3, "real_imag", "gaussian", 0),
+    (128, 34, 150, 2, "delta_beta", "poisson", 4),
+    (128, 34, 150, 2, "real_imag", "gaussian", 1),
+    (96, 20, 130, 3, "real_imag", "poisson", 2),
+])
+def test_strong_absorbers_match_oracle(ctx, n, s, lat, npos, repr_, loss, k):
+    """Checkpoints every 16 slices on strongly absorbing objects: every
+    output finite and within the tolerances, and the gradients equal (to
+    float32 rounding) to those of checkpoints at every slice, where the
+    reverse sweep never divides by a transmission."""
+    sc = _absorbing_case(900 + n + s, n, s, lat, npos, repr_, loss)
+    case = Case(sc, poisson_seed=13 if loss == "poisson" else None)
+    if k:
+        ctx.set_split(n, k)
+    try:
+        got = run_grad(ctx, case, ckpt_every=16)
+        every = run_grad(ctx, case, ckpt_every=1)
+    finally:
+        ctx.set_split(n, 0)
+    for key in ("g_a", "g_b", "g_probe", "g_shift", "intensity"):
+        assert np.all(np.isfinite(got[key])), key
+    assert rel_l2(got["intensity"], case.oracle_forward()) <= TOL_I
+    check_grads(got, case.oracle_loss_grad(), case)
+    for key in ("g_a", "g_b", "g_probe", "g_shift"):
+        assert rel_l2(got[key], every[key]) <= TOL_G / 10, key
