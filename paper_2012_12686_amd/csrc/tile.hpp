@@ -227,6 +227,58 @@ __device__ __forceinline__ float2 partner(float2 v) {
   else return dpp2<kDppQuadXor1>(v);
 }
 
+// Fused cross-lane butterfly half: x <- x + s * partner(x), one
+// v_fmac_f32_dpp per value (the partner read through DPP as the
+// multiplicand), where a DPP move and a multiply-add would take two
+// instructions.  The compiler does not form this instruction itself, so it
+// is written out; its operands are plain registers.  A DPP read of a VGPR
+// needs two wait states after the VALU instruction that wrote it, which the
+// compiler cannot see across inline assembly: dpp_enter orders every value's
+// producer before an s_nop 1, dpp_leave puts an s_nop 1 after the last DPP
+// write and orders every consumer after it.  Full waves only (every lane
+// active), as all tile code.
+#ifndef ADORYM_FUSED_DPP
+#define ADORYM_FUSED_DPP 1
+#endif
+template <int L, int H>
+__device__ __forceinline__ void dpp_fmac(float& x, float s) {
+  if constexpr (L == 16 && H == 8)
+    asm volatile("v_fmac_f32_dpp %0, %0, %1 row_mirror row_mask:0xf bank_mask:0xf" : "+v"(x) : "v"(s));
+  else if constexpr (L >= 8 && H == 4)
+    asm volatile("v_fmac_f32_dpp %0, %0, %1 row_half_mirror row_mask:0xf bank_mask:0xf" : "+v"(x) : "v"(s));
+  else if constexpr (H == 2)
+    asm volatile("v_fmac_f32_dpp %0, %0, %1 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf" : "+v"(x) : "v"(s));
+  else
+    asm volatile("v_fmac_f32_dpp %0, %0, %1 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf" : "+v"(x) : "v"(s));
+}
+template <int R>
+__device__ __forceinline__ void dpp_enter(float2 (&v)[R]) {
+#pragma unroll
+  for (int m = 0; m < R; ++m) asm volatile("" : "+v"(v[m].x), "+v"(v[m].y));
+  asm volatile("s_nop 1");
+}
+template <int R>
+__device__ __forceinline__ void dpp_leave(float2 (&v)[R]) {
+  asm volatile("s_nop 1");
+#pragma unroll
+  for (int m = 0; m < R; ++m) asm volatile("" : "+v"(v[m].x), "+v"(v[m].y));
+}
+// v[m] <- v[m] + s * partner(v[m]) for every register: for the lanes of the
+// top half of each pair (s = 1) the butterfly output p + v, for the bottom
+// half (s = -1) its negation -(p - v); rounding is symmetric under
+// negation, so the caller recovers the output bit for bit by multiplying
+// with s, which it folds into the next twiddle.
+template <int L, int H, int R>
+__device__ __forceinline__ void butterfly_fused(float2 (&v)[R], float s) {
+  dpp_enter(v);
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    dpp_fmac<L, H>(v[m].x, s);
+    dpp_fmac<L, H>(v[m].y, s);
+  }
+  dpp_leave(v);
+}
+
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 __host__ __device__ constexpr int bitrev_n(int x, int bits) {
   int r = 0;
@@ -375,12 +427,20 @@ __device__ __forceinline__ void fft_line(float2 (&v)[C::R], const Tables<C>& tb,
     const float sgn = top ? 1.f : -1.f;
     // bottom lanes of a pair take W_{2H}^{q mod H}; top lanes W^0 = 1
     const float2 wl = wn_at<C, SIGN>(tb, top ? 0 : (ln.q & (H - 1)) * (C::N / (2 * H)));
+    if constexpr (ADORYM_FUSED_DPP && H > 1) {
+      // sgn (p + sgn v) in one fused op per value; sgn goes into the twiddle
+      butterfly_fused<C::L, H>(v, sgn);
+      const float2 ws = make_float2(sgn * wl.x, sgn * wl.y);
 #pragma unroll
-    for (int m = 0; m < C::R; ++m) {
-      float2 p = partner<C::L, H>(v[m]);
-      float2 d = make_float2(p.x + sgn * v[m].x, p.y + sgn * v[m].y);
-      if constexpr (H > 1) d = cmul(d, wl);
-      v[m] = d;
+      for (int m = 0; m < C::R; ++m) v[m] = cmul(v[m], ws);
+    } else {
+#pragma unroll
+      for (int m = 0; m < C::R; ++m) {
+        float2 p = partner<C::L, H>(v[m]);
+        float2 d = make_float2(p.x + sgn * v[m].x, p.y + sgn * v[m].y);
+        if constexpr (H > 1) d = cmul(d, wl);
+        v[m] = d;
+      }
     }
   });
 }
@@ -388,18 +448,31 @@ __device__ __forceinline__ void fft_line(float2 (&v)[C::R], const Tables<C>& tb,
 // 1D DFT along the line: spectral order -> natural order.
 template <class C, int SIGN>
 __device__ __forceinline__ void ifft_line(float2 (&v)[C::R], const Tables<C>& tb, const Lane<C>& ln) {
-  // cross-lane DIT, spans 1 ... L/2 (bit-reversed in, natural out)
+  // cross-lane DIT, spans 1 ... L/2 (bit-reversed in, natural out).  The
+  // fused stages (all but the last) leave their output times the lane's
+  // sign `carry`, which the next stage's twiddle takes back.
+  float carry = 1.f;
   CFor<0, C::LOGL>::run([&](auto sc) {
     constexpr int H = 1 << decltype(sc)::value;
     const bool top = (ln.q & H) == 0;
     const float sgn = top ? 1.f : -1.f;
-    const float2 wl = wn_at<C, SIGN>(tb, top ? 0 : (ln.q & (H - 1)) * (C::N / (2 * H)));
+    float2 wl = wn_at<C, SIGN>(tb, top ? 0 : (ln.q & (H - 1)) * (C::N / (2 * H)));
+    if constexpr (ADORYM_FUSED_DPP && H > 1) wl = make_float2(carry * wl.x, carry * wl.y);
+    if constexpr (ADORYM_FUSED_DPP && 2 * H < C::L) {
+      if constexpr (H > 1) {
 #pragma unroll
-    for (int m = 0; m < C::R; ++m) {
-      float2 u = v[m];
-      if constexpr (H > 1) u = cmul(u, wl);
-      float2 p = partner<C::L, H>(u);
-      v[m] = make_float2(p.x + sgn * u.x, p.y + sgn * u.y);
+        for (int m = 0; m < C::R; ++m) v[m] = cmul(v[m], wl);
+      }
+      butterfly_fused<C::L, H>(v, sgn);
+      carry = sgn;
+    } else {
+#pragma unroll
+      for (int m = 0; m < C::R; ++m) {
+        float2 u = v[m];
+        if constexpr (H > 1) u = cmul(u, wl);
+        float2 p = partner<C::L, H>(u);
+        v[m] = make_float2(p.x + sgn * u.x, p.y + sgn * u.y);
+      }
     }
   });
   apply_twiddles<C, SIGN>(v, tb, ln);
