@@ -146,6 +146,22 @@ adorym_status adorym_forward(adorym_ctx* ctx, const adorym_geom* g,
                              const int32_t* corner, const float* shift, int32_t batch,
                              float* intensity, void* workspace, size_t ws_bytes);
 
+/* adorym_forward without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid allocation): the workspace is a static device
+ * array of 64 MiB that the library holds on every GPU it runs on until the
+ * process ends, located at adorym_create.  The call itself allocates
+ * nothing.  Inputs and the output are the caller's, as for adorym_forward.
+ * ADORYM_ENOMEM (nothing enqueued) when adorym_forward_workspace_size(g,
+ * batch) exceeds 64 MiB, e.g. more than 127 positions at N = 128.  Every
+ * call on one GPU uses that GPU's one array: calls that overlap on the
+ * device (other streams, other contexts, other threads) race and must be
+ * ordered by the caller.  Results equal adorym_forward's bit for bit. */
+adorym_status adorym_forward_static(adorym_ctx* ctx, const adorym_geom* g,
+                                    const float* obj_a, const float* obj_b, const float* probe,
+                                    const int32_t* corner, const float* shift, int32_t batch,
+                                    float* intensity);
+
 /* Loss and gradient.  i_meas float32 [B][N][N] (zero frequency at N/2).
  * Writes *loss (device double), and, for every gradient pointer that is
  * not NULL: g_a/g_b [S][Ly][Lx] (dL/ddelta, dL/dbeta or dL/dRe O, dL/dIm O),

@@ -62,6 +62,7 @@ SIGNATURES = {
     "adorym_workspace_size": (ctypes.c_size_t, [_GP, ctypes.c_int32]),
     "adorym_forward_workspace_size": (ctypes.c_size_t, [_GP, ctypes.c_int32]),
     "adorym_forward": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t]),
+    "adorym_forward_static": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P]),
     "adorym_loss_grad": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t,
                                         _P, _P, _P, _P, _P, _P]),
     "adorym_forward_defocus": (ctypes.c_int, [_P, _GP, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_double, _P, _P,

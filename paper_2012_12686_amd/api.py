@@ -141,6 +141,19 @@ class Context:
         check(st, self._ctx)
         return out
 
+    def forward_static(self, geom, obj_a, obj_b, probe, corner, shift, out):
+        """forward() with the library's static 64 MiB device scratch as its
+        workspace (adorym_forward_static): no allocation by the library or
+        here; ``out`` is the caller's float32 [B][N][N] tensor."""
+        self._bind_stream()
+        b = self._check_inputs(geom, obj_a, obj_b, probe, corner, shift)
+        if out.dtype != torch.float32 or tuple(out.shape) != (b, geom.n, geom.n) or not out.is_contiguous():
+            raise ValueError("out: expected contiguous float32 [B][N][N]")
+        st = load().adorym_forward_static(self._ctx, ctypes.byref(geom.to_c()), _ptr(obj_a), _ptr(obj_b),
+                                          _ptr(torch.view_as_real(probe)), _ptr(corner), _ptr(shift), b, _ptr(out))
+        check(st, self._ctx)
+        return out
+
     def loss_grad(self, geom, obj_a, obj_b, probe, corner, shift, i_meas, grads=True, intensity=False,
                   out=None, workspace=None):
         """Loss (device float64 scalar) and gradients.

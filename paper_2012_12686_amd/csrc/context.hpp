@@ -19,4 +19,7 @@ struct adorym_ctx {
   // runs one mode's loss and gradient (the loss is taken at this intensity);
   // null otherwise
   const float* i_total = nullptr;
+  // this device's copy of the static scratch array (adorym_forward_static),
+  // as hipGetSymbolAddress returned it when the context was created
+  void* scratch = nullptr;
 };

@@ -3,6 +3,8 @@
 // instantiated per probe size and split in the ms_n*.hip units.
 #include "multislice_impl.hpp"
 
+#include <mutex>
+
 using namespace adorym_ms;
 
 extern template ADORYM_RUN_SIGNATURE(64, 8, 1);
@@ -265,6 +267,31 @@ __global__ void zero_kernel(float* __restrict__ dst, size_t n) {
     dst[i] = 0.f;
 }
 
+// Workspace of adorym_forward_static: a file-scope device array, one copy per
+// GPU the library runs on, held until the process ends.  Host code never
+// uses its name as an address: each device's copy is looked up once with
+// hipGetSymbolAddress (with that device current) and kept in
+// g_scratch_addr.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// The current device's scratch address, looked up on first use.
+hipError_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -279,6 +306,7 @@ adorym_status adorym_create(adorym_ctx** out, int device, void* stream) {
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
   c->msg[0] = 0;
+  if (scratch_address(device, &c->scratch) != hipSuccess) { delete c; return ADORYM_EDEVICE; }
   if (hipMalloc(&c->d_err, 256) != hipSuccess) { delete c; return ADORYM_EDEVICE; }
   if (hipMemset(c->d_err, 0, 256) != hipSuccess) { (void)hipFree(c->d_err); delete c; return ADORYM_EDEVICE; }
   *out = c;
@@ -320,6 +348,22 @@ adorym_status adorym_forward(adorym_ctx* ctx, const adorym_geom* g, const float*
     return set_err(ctx, ADORYM_ENOMEM, "workspace too small");
   return dispatch(ctx, g, obj_a, obj_b, probe, corner, shift, batch, nullptr, workspace, nullptr, nullptr, nullptr,
                   nullptr, nullptr, intensity, false);
+}
+
+adorym_status adorym_forward_static(adorym_ctx* ctx, const adorym_geom* g, const float* obj_a, const float* obj_b,
+                                    const float* probe, const int32_t* corner, const float* shift, int32_t batch,
+                                    float* intensity) {
+  adorym_status st = check_geom(ctx, g, batch);
+  if (st != ADORYM_OK) return st;
+  if (!obj_a || !obj_b || !probe || !corner || !shift || !intensity)
+    return set_err(ctx, ADORYM_EINVAL, "NULL array argument");
+  const size_t need = adorym_forward_workspace_size(g, batch);
+  if (need > kStaticScratchBytes)
+    return set_err(ctx, ADORYM_ENOMEM,
+                   "forward workspace exceeds the 64 MiB static scratch: use adorym_forward with a workspace");
+  if (!ctx->scratch) return set_err(ctx, ADORYM_EDEVICE, "no static scratch address on this device");
+  return dispatch(ctx, g, obj_a, obj_b, probe, corner, shift, batch, nullptr, ctx->scratch, nullptr, nullptr,
+                  nullptr, nullptr, nullptr, intensity, false);
 }
 
 adorym_status adorym_loss_grad(adorym_ctx* ctx, const adorym_geom* g, const float* obj_a, const float* obj_b,
