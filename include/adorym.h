@@ -357,6 +357,14 @@ adorym_status adorym_support_project(adorym_ctx* ctx, int32_t obj_repr, const ui
  * Complex arrays are updated as independent real and imaginary parts. */
 adorym_status adorym_adam(adorym_ctx* ctx, float* x, const float* g, float* m, float* v, size_t n, double lr,
                           double beta1, double beta2, double eps, int32_t t);
+/* The same Adam step with the iteration count t read from DEVICE memory
+ * (int32 scalar) when the kernel runs, so that a HIP graph holding the whole
+ * iteration (loss, gradients and this step) uses the current count on
+ * every replay; the caller advances *t between iterations (inside the graph
+ * too).  A count below 1 leaves x, m and v unchanged and makes
+ * adorym_sync_error report ADORYM_EINVAL. */
+adorym_status adorym_adam_dev(adorym_ctx* ctx, float* x, const float* g, float* m, float* v, size_t n, double lr,
+                              double beta1, double beta2, double eps, const int32_t* t);
 
 /* ---- Batched evaluation of many independent scans --------------------
  * One job = the arguments of one adorym_loss_grad call (its own geometry,

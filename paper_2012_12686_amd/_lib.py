@@ -101,6 +101,8 @@ SIGNATURES = {
                                      ctypes.c_int]),
     "adorym_adam": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_size_t, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int32]),
+    "adorym_adam_dev": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_size_t, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, _P]),
     "adorym_sync_error": (ctypes.c_int, [_P]),
     "adorym_last_error_message": (ctypes.c_char_p, [_P]),
     "adorym_set_split": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),

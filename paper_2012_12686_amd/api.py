@@ -463,16 +463,25 @@ class Context:
               self._ctx)
         return out
 
-    def adam(self, x: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, t: int, lr: float,
+    def adam(self, x: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, t, lr: float,
              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
-        """In-place Adam step on float32 (or complex64, as pairs of reals) tensors."""
+        """In-place Adam step on float32 (or complex64, as pairs of reals) tensors.
+        ``t``: the 1-based iteration count, a Python int, or a device int32
+        scalar tensor read when the kernel runs (adorym_adam_dev: graph
+        capturable with a count that advances between replays)."""
         self._bind_stream()
         arrs = [torch.view_as_real(a) if a.is_complex() else a for a in (x, g, m, v)]
         n = arrs[0].numel()
         for a in arrs:
             if a.dtype != torch.float32 or a.numel() != n or not a.is_contiguous():
                 raise ValueError("adam: expected contiguous float32/complex64 tensors of one size")
-        check(load().adorym_adam(self._ctx, *[_ptr(a) for a in arrs], n, lr, beta1, beta2, eps, t), self._ctx)
+        if isinstance(t, torch.Tensor):
+            if t.dtype != torch.int32 or t.numel() != 1 or t.device != self.device:
+                raise ValueError("adam: t must be an int32 scalar tensor on the context's device")
+            check(load().adorym_adam_dev(self._ctx, *[_ptr(a) for a in arrs], n, lr, beta1, beta2, eps, _ptr(t)),
+                  self._ctx)
+        else:
+            check(load().adorym_adam(self._ctx, *[_ptr(a) for a in arrs], n, lr, beta1, beta2, eps, t), self._ctx)
 
 
     def plan(self, jobs) -> "Plan":

@@ -2,11 +2,11 @@
 
 ``BatchRunner`` keeps every job's object, probe, positions, measured data,
 outputs and workspace on the device, builds one plan (persistent launches per
-probe size, see ``Plan``) and can capture the loss and gradients of every job
-in one HIP graph; the Adam step on every object follows eagerly (its bias
-correction depends on the iteration count, which a replayed graph would
-freeze).  ``run_per_job`` is the plain form for comparison: the same work as
-one ``loss_grad`` call per job.
+probe size, see ``Plan``) and can capture a whole iteration in one HIP graph:
+the loss and gradients of every job, the advance of a device-side iteration
+count and the Adam step on every object, whose bias correction reads that
+count when it runs (adorym_adam_dev).  ``run_per_job`` is the plain form for
+comparison: the same work as one ``loss_grad`` call per job.
 """
 from __future__ import annotations
 
@@ -72,6 +72,8 @@ class BatchRunner:
         self.scans = scans
         self.lr = lr
         self.t = 0
+        # the iteration count the Adam kernels read (advanced on the device)
+        self.t_dev = torch.zeros(1, dtype=torch.int32, device=ctx.device)
         self.jobs = [Job(geom=s.geom, obj_a=s.a, obj_b=s.b, probe=s.probe, corner=s.corner, shift=s.shift,
                          i_meas=s.i_meas) for s in scans]
         self.plan = None
@@ -83,33 +85,38 @@ class BatchRunner:
         self.plan = self.ctx.plan(self.jobs)
         return self.plan
 
-    def _adam(self, t):
+    def _adam(self):
+        """Advance the device iteration count and take every object's Adam step."""
+        self.t_dev.add_(1)
         for s, j in zip(self.scans, self.jobs):
-            self.ctx.adam(s.a, j.out["g_a"], s.m_a, s.v_a, t, lr=self.lr)
-            self.ctx.adam(s.b, j.out["g_b"], s.m_b, s.v_b, t, lr=self.lr)
+            self.ctx.adam(s.a, j.out["g_a"], s.m_a, s.v_a, self.t_dev, lr=self.lr)
+            self.ctx.adam(s.b, j.out["g_b"], s.m_b, s.v_b, self.t_dev, lr=self.lr)
 
     def step(self, adam: bool = True):
         """One batched iteration (eager launches)."""
         self.t += 1
         self.plan.run()
         if adam:
-            self._adam(self.t)
+            self._adam()
 
-    def capture(self):
-        """Capture plan.run() -- loss and gradients of every job -- in one HIP graph."""
+    def capture(self, adam: bool = True):
+        """Capture one iteration in one HIP graph: plan.run() (loss and
+        gradients of every job) and, with ``adam``, the count's advance and
+        every Adam step."""
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             self.plan.run()
+            if adam:
+                self._adam()
         self.graph = g
+        self.graph_adam = adam
         return g
 
-    def step_graph(self, adam: bool = True):
-        """One iteration: graph replay, then the Adam steps."""
+    def step_graph(self):
+        """One iteration: one graph replay."""
         self.t += 1
         self.graph.replay()
-        if adam:
-            self._adam(self.t)
 
     def run_per_job(self, adam: bool = True):
         """The plain form: one loss_grad call per job (its own launches)."""
@@ -118,7 +125,7 @@ class BatchRunner:
             self.ctx.loss_grad(s.geom, s.a, s.b, s.probe, s.corner, s.shift, s.i_meas, out=j.out,
                                workspace=j.workspace)
         if adam:
-            self._adam(self.t)
+            self._adam()
 
     def positions(self) -> int:
         return sum(int(s.corner.shape[0]) for s in self.scans)

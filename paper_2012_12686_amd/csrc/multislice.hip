@@ -746,6 +746,7 @@ adorym_status adorym_sync_error(adorym_ctx* ctx) {
   if (hipMemset(ctx->d_err, 0, sizeof(int)) != hipSuccess) return set_err(ctx, ADORYM_EDEVICE, "clearing failed");
   if (flag & 2) return set_err(ctx, ADORYM_EDEVICE, "a workgroup group barrier timed out (groups not co-resident)");
   if (flag & 4) return set_err(ctx, ADORYM_EINVAL, "a distance index was outside the distance list; those positions contributed nothing");
+  if (flag & 8) return set_err(ctx, ADORYM_EINVAL, "an Adam step read an iteration count below 1; it changed nothing");
   if (flag & 1) return set_err(ctx, ADORYM_ERANGE, "a chunk left the object; those positions contributed nothing");
   return ADORYM_OK;
 }

@@ -112,6 +112,44 @@ __global__ void adam_kernel(float* __restrict__ x, const float* __restrict__ g, 
   }
 }
 
+// The same step with the iteration count read from device memory when the
+// kernel runs (a replayed HIP graph then uses the current count).  Every
+// workgroup derives the bias corrections once, in FP64, from b1^t and b2^t
+// by repeated squaring; a count below 1 leaves everything unchanged and
+// sets an error bit.
+constexpr int kErrAdamStep = 8;
+__global__ void adam_dev_kernel(float* __restrict__ x, const float* __restrict__ g, float* __restrict__ m,
+                                float* __restrict__ v, size_t n, float lr, double b1, double b2, float eps,
+                                const int32_t* __restrict__ t_dev, int* __restrict__ err) {
+  __shared__ float corr[2];
+  const int t = *t_dev;
+  if (t < 1) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, kErrAdamStep);
+    return;
+  }
+  if (threadIdx.x == 0) {
+    double p1 = 1.0, p2 = 1.0, s1 = b1, s2 = b2;
+    for (int e = t; e > 0; e >>= 1) {
+      if (e & 1) { p1 *= s1; p2 *= s2; }
+      s1 *= s1;
+      s2 *= s2;
+    }
+    corr[0] = (float)(1.0 / (1.0 - p1));
+    corr[1] = (float)(1.0 / (1.0 - p2));
+  }
+  __syncthreads();
+  const float inv_c1 = corr[0], inv_c2 = corr[1];
+  const float fb1 = (float)b1, om1 = (float)(1.0 - b1), fb2 = (float)b2, om2 = (float)(1.0 - b2);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = fb1 * m[i] + om1 * gi;
+    const float vi = fb2 * v[i] + om2 * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    x[i] -= lr * (mi * inv_c1) / (sqrtf(vi * inv_c2) + eps);
+  }
+}
+
 inline int grid_for(size_t n) {
   const size_t blocks = (n + 255) / 256;
   return (int)(blocks < 8192 ? (blocks ? blocks : 1) : 8192);
@@ -154,6 +192,19 @@ adorym_status adorym_adam(adorym_ctx* ctx, float* x, const float* g, float* m, f
   hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, ctx->stream, x, g, m, v, n, (float)lr,
                      (float)beta1, (float)(1.0 - beta1), (float)beta2, (float)(1.0 - beta2), (float)eps,
                      (float)(1.0 / c1), (float)(1.0 / c2));
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ADORYM_OK : rot_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
+}
+
+adorym_status adorym_adam_dev(adorym_ctx* ctx, float* x, const float* g, float* m, float* v, size_t n, double lr,
+                              double beta1, double beta2, double eps, const int32_t* t) {
+  if (!ctx) return ADORYM_EINVAL;
+  if (!x || !g || !m || !v || !t) return rot_err(ctx, ADORYM_EINVAL, "NULL array argument");
+  if (!(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return rot_err(ctx, ADORYM_EINVAL, "need 0 <= beta < 1 and eps > 0");
+  if (n == 0) return ADORYM_OK;
+  hipLaunchKernelGGL(adam_dev_kernel, dim3(grid_for(n)), dim3(256), 0, ctx->stream, x, g, m, v, n, (float)lr,
+                     beta1, beta2, (float)eps, t, ctx->d_err);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? ADORYM_OK : rot_err(ctx, ADORYM_EDEVICE, hipGetErrorString(e));
 }

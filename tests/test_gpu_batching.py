@@ -35,7 +35,7 @@ def test_graph_replays_equal_eager_runs(ctx):
     r.plan.run()
     torch.cuda.synchronize()
     eager = [{k: v.detach().cpu().numpy().copy() for k, v in j.out.items()} for j in r.jobs]
-    r.capture()
+    r.capture(adam=False)
     for rep in range(3):
         # unrelated eager work and a synchronisation between replays
         junk = torch.ones(1 << 20, device="cuda") * rep
@@ -52,6 +52,45 @@ def test_graph_replays_equal_eager_runs(ctx):
             for k in ("g_a", "g_b", "g_probe", "g_shift"):
                 assert rel_l2(got[k], ref[k]) < 1e-5, (rep, k)
     r.close()
+
+
+def test_whole_iteration_with_adam_in_one_graph_equals_eager_iterations(ctx):
+    """The captured graph holds loss, gradients, the advance of the device
+    iteration count and every Adam step: three replays give the same objects
+    and moments, bit for bit, as three eager iterations of an identical
+    runner (deterministic jobs, so both evaluate with the same split), and
+    the count reads 3 on both."""
+    import dataclasses
+    import torch
+    from paper_2012_12686_amd.batch import BatchRunner, to_device_scan
+    specs = [(64, 4, 90, 6, "poisson"), (128, 6, 150, 4, "gaussian"), (192, 3, 220, 3, "poisson")]
+    scans = [synth.small_case(seed=710 + i, n=n, n_slices=s, lateral=lat, n_pos=p, loss=loss, strength=30.0)
+             for i, (n, s, lat, p, loss) in enumerate(specs)]
+
+    def runner():
+        ds = [to_device_scan(ctx, sc, seed=i) for i, sc in enumerate(scans)]
+        ds = [dataclasses.replace(d, geom=dataclasses.replace(d.geom, deterministic=True)) for d in ds]
+        return BatchRunner(ctx, ds, lr=1e-6)
+
+    eager, graph = runner(), runner()
+    eager.build_plan()
+    graph.build_plan()
+    graph.capture(adam=True)
+    for _ in range(3):
+        eager.step(adam=True)
+        graph.step_graph()
+    torch.cuda.synchronize()
+    ctx.sync_error()
+    assert int(eager.t_dev) == 3 and int(graph.t_dev) == 3
+    moved = 0.0
+    for se, sg, sc in zip(eager.scans, graph.scans, scans):
+        for k in ("a", "b", "m_a", "v_a", "m_b", "v_b"):
+            assert torch.equal(getattr(se, k), getattr(sg, k)), k
+        moved += float((se.a - torch.as_tensor(sc.eval_obj_a, dtype=torch.float32, device=se.a.device))
+                       .abs().max())
+    assert moved > 0
+    eager.close()
+    graph.close()
 
 
 def test_autotuner_sets_a_supported_split(ctx, tmp_path):
@@ -121,7 +160,7 @@ def test_mixed_scan_plan_matches_oracle_on_one_job_per_probe_size(ctx):
             r.jobs[i].out["intensity"] = torch.empty((len(sc.positions), sc.n, sc.n), dtype=torch.float32,
                                                      device=dev)
         r.build_plan()
-        r.capture()
+        r.capture(adam=False)
         r.graph.replay()
         torch.cuda.synchronize()
         ctx.sync_error()

@@ -73,6 +73,42 @@ def test_adam_matches_oracle_over_steps(ctx):
     assert rel_l2(vt.cpu().numpy(), vr) < 1e-6
 
 
+def test_adam_with_device_count_matches_oracle_and_refuses_zero(ctx):
+    """adorym_adam_dev reads t from device memory when the kernel runs: the
+    same steps as the oracle's with t advanced on the device, the same bits
+    as adorym_adam, and a count of 0 leaves everything unchanged and is
+    reported by sync_error."""
+    import torch
+    from paper_2012_12686_amd._lib import EINVAL, AdorymError
+    rng = np.random.default_rng(16)
+    n = 10007
+    x = rng.standard_normal(n).astype(np.float32)
+    xt, mt, vt = (torch.tensor(a, device="cuda") for a in (x, np.zeros(n, np.float32), np.zeros(n, np.float32)))
+    xh, mh, vh = xt.clone(), mt.clone(), vt.clone()
+    xr, mr, vr = x.astype(np.float64), np.zeros(n), np.zeros(n)
+    t_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for t in range(1, 6):
+        g = rng.standard_normal(n).astype(np.float32)
+        gt = torch.tensor(g, device="cuda")
+        t_dev.add_(1)
+        ctx.adam(xt, gt, mt, vt, t_dev, lr=1e-3)
+        ctx.adam(xh, gt, mh, vh, t, lr=1e-3)
+        xr, mr, vr = oadam.adam_step(xr, g.astype(np.float64), mr, vr, t, lr=1e-3)
+    torch.cuda.synchronize()
+    ctx.sync_error()
+    assert rel_l2(xt.cpu().numpy(), xr) < 1e-6
+    assert rel_l2(mt.cpu().numpy(), mr) < 1e-6
+    assert rel_l2(vt.cpu().numpy(), vr) < 1e-6
+    for a, b in ((xt, xh), (mt, mh), (vt, vh)):
+        assert torch.equal(a, b)
+    before = xt.clone()
+    ctx.adam(xt, gt, mt, vt, torch.zeros(1, dtype=torch.int32, device="cuda"), lr=1e-3)
+    with pytest.raises(AdorymError) as ei:
+        ctx.sync_error()
+    assert ei.value.status == EINVAL
+    assert torch.equal(xt, before)
+
+
 def test_adam_complex_probe(ctx):
     import torch
     rng = np.random.default_rng(7)
