@@ -139,6 +139,18 @@ def tilt_template(ctx: Context, scan, angles: Sequence[float], name: str = "tilt
 # One admitted job
 # ---------------------------------------------------------------------------
 
+def job_work(tpl: Template, iterations: int) -> float:
+    """Relative cost of a job for scheduling: voxels the multislice sweep
+    visits over all its iterations (positions x slices x N^2, the FFT work
+    per position being ~N^2 S log N), plus the tilt job's rotations and the
+    Adam steps on the object, which touch every voxel of it."""
+    g = tpl.geom
+    s, ly, lx = tpl.a0.shape
+    sweep = tpl.minibatch * g.n_slices * g.n * g.n * np.log2(g.n)
+    per_voxel = (4 if tpl.kind == "tilt" else 0) + 2
+    return float(iterations * (sweep + per_voxel * s * ly * lx))
+
+
 def job_footprint(ctx: Context, tpl: Template, deterministic: bool = False) -> int:
     """Device bytes a job of this type holds while admitted (what ServedJob allocates)."""
     s, ly, lx = tpl.a0.shape
@@ -293,11 +305,22 @@ class Server:
     waiting for each other (continuous batching without lockstep);
     batched=False with max_jobs=1: the plain per-job form, one job at a time,
     each iteration its own loss_grad call.
+
+    order="fifo" admits waiting jobs first come first served (a job that
+    does not fit blocks the ones behind it); order="sjf" admits the waiting
+    job with the least work (job_work) that fits first, so that short jobs
+    are not held behind long ones.
+
+    busy_jobs: with a deep queue (at least busy_queue jobs waiting) the slot
+    limit rises from max_jobs to busy_jobs.  Each concurrent job slows the
+    others, which stretches the long jobs that make up the tail of the job
+    time; a queue that deep is where the extra overlap pays for itself.
     """
 
     def __init__(self, ctx: Context, budget_bytes: Optional[int] = None, max_jobs: int = 16,
                  max_positions: int = 2048, batched: bool = True, deterministic: bool = False,
-                 keep_state: bool = False, inflight: int = 2, streams: int = 0):
+                 keep_state: bool = False, inflight: int = 2, streams: int = 0, order: str = "fifo",
+                 busy_jobs: Optional[int] = None, busy_queue: int = 4):
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info(ctx.device)
             budget_bytes = int(0.8 * free)
@@ -306,6 +329,31 @@ class Server:
         self.batched, self.deterministic, self.keep_state = batched, deterministic, keep_state
         self.inflight = max(1, inflight)
         self.streams = int(streams)
+        if order not in ("fifo", "sjf"):
+            raise ValueError("order must be 'fifo' or 'sjf'")
+        self.order = order
+        self.max_jobs = int(max_jobs)
+        self.busy_jobs = int(busy_jobs) if busy_jobs is not None else self.max_jobs
+        self.busy_queue = int(busy_queue)
+        if self.busy_jobs < self.max_jobs or self.busy_queue < 1:
+            raise ValueError("busy_jobs must be at least max_jobs and busy_queue at least 1")
+
+    def _admit_next(self, waiting: List[int], requests, foot) -> Optional[int]:
+        """Pop and return the next waiting request to admit, or None."""
+        if not waiting:
+            return None
+        self.adm.max_jobs = self.busy_jobs if len(waiting) >= self.busy_queue else self.max_jobs
+        if self.order == "fifo":
+            i = waiting[0]
+            if not self.adm.try_admit(foot[i], requests[i].template.minibatch):
+                return None
+            return waiting.pop(0)
+        for i in sorted(waiting, key=lambda i: (job_work(requests[i].template, requests[i].iterations),
+                                                requests[i].arrival_s)):
+            if self.adm.try_admit(foot[i], requests[i].template.minibatch):
+                waiting.remove(i)
+                return i
+        return None
 
     def run(self, requests: Sequence[Request], realtime: bool = True) -> dict:
         """Serve every request; arrivals follow ``arrival_s`` on the wall clock
@@ -362,13 +410,12 @@ class Server:
             while nxt < len(order) and (not realtime or requests[order[nxt]].arrival_s <= t):
                 waiting.append(order[nxt])
                 nxt += 1
-            # admission, first come first served (a blocked head blocks the rest)
-            while waiting:
-                i = waiting[0]
-                r = requests[i]
-                if not self.adm.try_admit(foot[i], r.template.minibatch):
+            # admission in the server's order
+            while True:
+                i = self._admit_next(waiting, requests, foot)
+                if i is None:
                     break
-                waiting.pop(0)
+                r = requests[i]
                 active.append(ServedJob(ctx, r.template, i, r.iterations, self.deterministic))
                 records[i].admitted_s = now()
             peak_used = max(peak_used, self.adm.used)
@@ -442,12 +489,11 @@ class Server:
             while nxt < len(order) and (not realtime or requests[order[nxt]].arrival_s <= t):
                 waiting.append(order[nxt])
                 nxt += 1
-            while waiting:
-                i = waiting[0]
-                r = requests[i]
-                if not self.adm.try_admit(foot[i], r.template.minibatch):
+            while True:
+                i = self._admit_next(waiting, requests, foot)
+                if i is None:
                     break
-                waiting.pop(0)
+                r = requests[i]
                 job = ServedJob(ctx, r.template, i, r.iterations, self.deterministic)
                 job.stream = pool[rr % len(pool)]
                 rr += 1
