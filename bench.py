@@ -146,6 +146,8 @@ def main():
                          "with the defocus gradient (single probe mode)")
     ap.add_argument("--jobs", type=int, default=200, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=4.0, help="serving: Poisson arrival rate (jobs/s)")
+    ap.add_argument("--seeds", default="5",
+                    help="serving: arrival seeds, comma-separated; the served and per-job forms run on each trace")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a "

@@ -161,3 +161,23 @@ def test_stream_concurrent_mode_matches_alone_bitwise(ctx, templates):
     for r, q in zip(res["records"], reqs):
         assert len(r.losses) == q.iterations and np.all(np.isfinite(r.losses))
     assert res["positions"] == sum(q.iterations * q.template.minibatch for q in reqs)
+
+
+def test_served_form_of_the_bench_matches_alone_bitwise(ctx, templates):
+    """The bench's served form (four streams, two jobs at a time, four with a
+    deep queue): every job finishes, no more jobs share the device than the
+    slot limits allow, and a job gives the same bits as alone (deterministic
+    mode)."""
+    from paper_2012_12686_amd.serve import SERVED, Request, Server
+    alone = Server(ctx, deterministic=True, keep_state=True).run([Request(0.0, templates["tilt"], 3)],
+                                                                  realtime=False)
+    reqs, idx = _mix(templates, "tilt")
+    reqs = reqs + [Request(0.0, templates[n], 2) for n in ("a64", "b96", "a64")]
+    res = Server(ctx, deterministic=True, keep_state=True, **SERVED).run(reqs, realtime=False)
+    assert 2 <= res["peak_jobs"] <= SERVED["busy_jobs"]
+    assert np.array_equal(res["records"][idx].losses, alone["records"][0].losses)
+    for k in ("a", "b"):
+        assert np.array_equal(res["records"][idx].state[k].cpu().numpy(), alone["records"][0].state[k].cpu().numpy())
+    for r, q in zip(res["records"], reqs):
+        assert len(r.losses) == q.iterations and np.all(np.isfinite(r.losses))
+    assert res["positions"] == sum(q.iterations * q.template.minibatch for q in reqs)
