@@ -593,14 +593,19 @@ __device__ __forceinline__ void wait_stores() {
 }
 
 // The barrier in two halves, so that work that touches no exchanged data can
-// run between the arrival and the wait.
-__device__ __forceinline__ void group_arrive(int* counter) {
+// run between the arrival and the wait.  The arrival returns (in thread 0)
+// whether it was the last one the barrier waits for: that workgroup need
+// not poll the counter at all.
+__device__ __forceinline__ bool group_arrive(int* counter, int target) {
   wait_stores();
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  bool last = false;
+  if (threadIdx.x == 0)
+    last = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 >= target;
+  return last;
 }
-__device__ __forceinline__ void group_wait(int* counter, int target, int* err) {
-  if (threadIdx.x == 0) {
+__device__ __forceinline__ void group_wait(int* counter, int target, int* err, bool last) {
+  if (threadIdx.x == 0 && !last) {
     int spins = 0;
     while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
@@ -613,8 +618,7 @@ __device__ __forceinline__ void group_wait(int* counter, int target, int* err) {
   __syncthreads();
 }
 __device__ __forceinline__ void group_barrier(int* counter, int target, int* err) {
-  group_arrive(counter);
-  group_wait(counter, target, err);
+  group_wait(counter, target, err, group_arrive(counter, target));
 }
 
 // Exchange state of one field group: two alternating N x N halves per field
@@ -628,6 +632,7 @@ struct Exchange {
   int* err;
   int phase;
   bool local;
+  bool last;        // split-phase transpose: this workgroup's arrival completed the barrier
 };
 
 constexpr int kL1Bypass = 1;      // sc0: load misses in the L1, hits in L2
@@ -696,13 +701,13 @@ __device__ __forceinline__ void transpose_begin_impl(const float2 (&v0)[C::R], c
     if (NF == 2) bstore2<ST>(r, v1[m], off, NN * 8);
   }
   ++x.phase;
-  group_arrive(x.counter);
+  x.last = group_arrive(x.counter, C::K * x.phase);
 }
 template <class C, int NF, int LD>
 __device__ __forceinline__ void transpose_end_impl(float2 (&v0)[C::R], float2 (&v1)[C::R], Exchange& x,
                                                    const Lane<C>& ln, bool dst_spec) {
   constexpr int NN = C::N * C::N;
-  group_wait(x.counter, C::K * x.phase, x.err);
+  group_wait(x.counter, C::K * x.phase, x.err, x.last);
   const rsrc_t r = make_rsrc(x.buf + (size_t)((x.phase - 1) & 1) * 2 * NN, 2 * NN * 8);
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
