@@ -129,3 +129,11 @@ def test_slot_limit_rises_with_a_deep_queue():
     assert srv._admit_next(waiting, reqs, foot) is None and srv.adm.max_jobs == 2
     with pytest.raises(ValueError):
         Server(ctx=None, budget_bytes=1000, max_jobs=4, busy_jobs=2)
+
+
+def test_the_served_form_of_the_bench_is_a_valid_configuration():
+    from paper_2012_12686_amd.serve import SERVED, Server
+    srv = Server(ctx=None, budget_bytes=10_000, **SERVED)
+    assert srv.streams == SERVED["streams"] >= 1
+    assert srv.max_jobs <= srv.busy_jobs and srv.busy_queue >= 1
+    assert srv.order == "fifo"                 # the long jobs are the tail: no least-work-first
