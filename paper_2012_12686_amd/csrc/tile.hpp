@@ -380,7 +380,11 @@ __device__ void build_fresnel(Tables<C>& tb, int tid, double chirp /* lambda dz 
     double f = double(kk) / double(C::N);
     const double x = chirp * f * f;          // phase / pi
     const double sh = sinpi(0.5 * x);
-    tb.h[idx] = make_float2(float(-2.0 * sh * sh / C::N), float(sinpi(x) / C::N));
+    // the lane holding slot k1 has logical index q = bitrev(k1); with the
+    // forward transform's last stage fused its output there is negated
+    // when q is odd (propagate_line), so the table holds the negated kernel
+    const double sg = (ADORYM_FUSED_DPP && (bitrev_n(k1, C::LOGL) & 1)) ? -1.0 : 1.0;
+    tb.h[idx] = make_float2(float(sg * -2.0 * sh * sh / C::N), float(sg * sinpi(x) / C::N));
   }
 }
 
@@ -415,7 +419,10 @@ __device__ __forceinline__ void apply_twiddles(float2 (&v)[C::R], const Tables<C
 // 1D DFT along the thread's line: natural order -> spectral order.
 // SIGN = -1: forward DFT (exp(-...)), +1: inverse (unnormalised).
 // ----------------------------------------------------------------------------
-template <class C, int SIGN>
+// SIGNED_OUT: the last stage (span 1) is fused too and the lanes with q odd
+// return the negated output (lane_sign_fft); the caller folds that sign
+// into what it multiplies the spectrum by.
+template <class C, int SIGN, bool SIGNED_OUT = false>
 __device__ __forceinline__ void fft_line(float2 (&v)[C::R], const Tables<C>& tb, const Lane<C>& ln) {
   Dft<C::R, SIGN, 1, 0, C::R>::run(v);
   // twiddle W_N^{q k2}
@@ -427,7 +434,9 @@ __device__ __forceinline__ void fft_line(float2 (&v)[C::R], const Tables<C>& tb,
     const float sgn = top ? 1.f : -1.f;
     // bottom lanes of a pair take W_{2H}^{q mod H}; top lanes W^0 = 1
     const float2 wl = wn_at<C, SIGN>(tb, top ? 0 : (ln.q & (H - 1)) * (C::N / (2 * H)));
-    if constexpr (ADORYM_FUSED_DPP && H > 1) {
+    if constexpr (ADORYM_FUSED_DPP && H == 1 && SIGNED_OUT) {
+      butterfly_fused<C::L, H>(v, sgn);        // sgn (p + sgn v); no twiddle at span 1
+    } else if constexpr (ADORYM_FUSED_DPP && H > 1) {
       // sgn (p + sgn v) in one fused op per value; sgn goes into the twiddle
       butterfly_fused<C::L, H>(v, sgn);
       const float2 ws = make_float2(sgn * wl.x, sgn * wl.y);
@@ -445,8 +454,12 @@ __device__ __forceinline__ void fft_line(float2 (&v)[C::R], const Tables<C>& tb,
   });
 }
 
-// 1D DFT along the line: spectral order -> natural order.
-template <class C, int SIGN>
+// 1D DFT along the line: spectral order -> natural order.  SIGNED_OUT: the
+// last stage (span L/2) is fused too, and the lanes with q & L/2 return the
+// negated output (lane_sign_ifft): every later operation is linear in the
+// lane's values, and rounding is symmetric under negation, so the sign comes
+// out unchanged for the caller to take back.
+template <class C, int SIGN, bool SIGNED_OUT = false>
 __device__ __forceinline__ void ifft_line(float2 (&v)[C::R], const Tables<C>& tb, const Lane<C>& ln) {
   // cross-lane DIT, spans 1 ... L/2 (bit-reversed in, natural out).  The
   // fused stages (all but the last) leave their output times the lane's
@@ -458,7 +471,7 @@ __device__ __forceinline__ void ifft_line(float2 (&v)[C::R], const Tables<C>& tb
     const float sgn = top ? 1.f : -1.f;
     float2 wl = wn_at<C, SIGN>(tb, top ? 0 : (ln.q & (H - 1)) * (C::N / (2 * H)));
     if constexpr (ADORYM_FUSED_DPP && H > 1) wl = make_float2(carry * wl.x, carry * wl.y);
-    if constexpr (ADORYM_FUSED_DPP && 2 * H < C::L) {
+    if constexpr (ADORYM_FUSED_DPP && (2 * H < C::L || SIGNED_OUT)) {
       if constexpr (H > 1) {
 #pragma unroll
         for (int m = 0; m < C::R; ++m) v[m] = cmul(v[m], wl);
@@ -485,26 +498,35 @@ __device__ __forceinline__ void ifft_line(float2 (&v)[C::R], const Tables<C>& tb
 // their float32 rounding is relative to that change rather than to the wave.
 // K == 1 tiles keep the input in the thread's own cells of the LDS transpose
 // buffer (stash: the line's row) instead of registers.
+// The transforms run with both last stages fused (SIGNED_OUT): the Fresnel
+// table already holds each slot's kernel times the sign the forward
+// transform leaves on its lane (build_fresnel), so the product is exact,
+// and the inverse transform's lane sign is taken back in the final sum.
 template <class C, bool CONJ>
 __device__ __forceinline__ void propagate_line(float2 (&v)[C::R], const Tables<C>& tb, const Lane<C>& ln,
                                                float2* stash = nullptr) {
+  constexpr bool SGN = ADORYM_FUSED_DPP;
   float2 v0[C::R];
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
     if (stash) stash[ln.pos_nat(m)] = v[m];
     else v0[m] = v[m];
   }
-  fft_line<C, -1>(v, tb, ln);
+  fft_line<C, -1, SGN>(v, tb, ln);
   if (C::FENCE) sched_fence();
 #pragma unroll
   for (int m = 0; m < C::R; ++m) {
-    float2 h = tb.h[m * C::L + ln.k1];     // kernel - 1 at frequency R*k1 + m
+    float2 h = tb.h[m * C::L + ln.k1];     // kernel - 1 at frequency R*k1 + m (times the lane sign)
     v[m] = CONJ ? cmulc(v[m], h) : cmul(v[m], h);
     if (C::FENCE && (m & 3) == 3) sched_fence();
   }
-  ifft_line<C, +1>(v, tb, ln);
+  ifft_line<C, +1, SGN>(v, tb, ln);
+  const float so = SGN && (ln.q & (C::L / 2)) ? -1.f : 1.f;
 #pragma unroll
-  for (int m = 0; m < C::R; ++m) v[m] = cadd(v[m], stash ? stash[ln.pos_nat(m)] : v0[m]);
+  for (int m = 0; m < C::R; ++m) {
+    const float2 u = stash ? stash[ln.pos_nat(m)] : v0[m];
+    v[m] = make_float2(fmaf(so, v[m].x, u.x), fmaf(so, v[m].y, u.y));
+  }
 }
 
 // ----------------------------------------------------------------------------
