@@ -74,7 +74,7 @@ struct MsParams {
   double* nd_part;         // near field: [B][K] distance-gradient partials
   int n_dist;
   double* gd_part;         // [B][K][S-1] gap-gradient partials (unequal spacing)
-  const float* absorb;     // [S] largest -log|t| of any voxel of each slice (absorb_bound_kernel)
+  const float* absorb;     // [S] largest -log|t| of any voxel of each slice (absorb_bound_part)
   double chirp_per_m;      // lambda / dx^2: the Fresnel phase / pi of gap d is chirp_per_m d f^2
   int B, S, Ly, Lx, ckpt_every, nslots, nrec;
   int loss;                // ADORYM_LOSS_*
@@ -1068,14 +1068,104 @@ static __global__ void __launch_bounds__(kDefocusParts) defocus_finish_kernel(co
   if (threadIdx.x == 0 && g_dist) *g_dist = accumulate ? *g_dist + red[0] : red[0];
 }
 
+// Grid of the one-group probe kernels.  Workgroups are dealt to the eight
+// XCDs in turn, so with K > 1 the grid holds 8 K workgroups and only every
+// eighth works (part = index / 8): the K members then share one XCD and
+// exchange through its L2 (exchange_init checks this; members on several
+// XCDs would still exchange correctly, through memory).
+template <class C>
+constexpr unsigned probe_grid() { return C::K > 1 ? 8u * C::K : 1u; }
+template <class C>
+__device__ __forceinline__ int probe_part() { return C::K > 1 ? (int)(blockIdx.x >> 3) : 0; }
+template <class C>
+__device__ __forceinline__ bool probe_idle() { return C::K > 1 && (blockIdx.x & 7) != 0; }
+
+static __global__ void reset_ints_kernel(int* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// Per slice j, the largest -log|t| over the slice's voxels, i.e. the most a
+// division by t_j can amplify a value (log scale; negative values count as
+// 0): k dz beta for delta/beta objects, -log|O| for real/imaginary ones
+// (infinite where O = 0).  Each of `parts` workgroups of a slice takes one
+// strided share of its voxels; non-negative floats order like their bit
+// patterns, so the shares combine by an integer maximum into out[j]
+// (cleared before).  NaN voxels are ignored.
+template <int REPR>
+__device__ __forceinline__ float absorb_gain(float kdz, float x, float y) {
+  if constexpr (REPR == ADORYM_OBJ_DELTA_BETA) {
+    return kdz * y;
+  } else {
+    const float m2 = x * x + y * y;
+    return m2 > 0.f ? -0.5f * logf(m2) : INFINITY;
+  }
+}
+template <int REPR, int THREADS>
+__device__ void absorb_bound_part(const float* __restrict__ a, const float* __restrict__ b, size_t plane, float kdz,
+                                  unsigned* __restrict__ out, int j, int part, int parts, float* wmax) {
+  const float* pa = a + (size_t)j * plane;
+  const float* pb = b + (size_t)j * plane;
+  float mx = 0.f;
+  const size_t stride = (size_t)parts * THREADS;
+  if ((plane & 3) == 0 && ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0) {
+    // four voxels per load (every slice starts on a 16-byte boundary)
+    const float4* qa = reinterpret_cast<const float4*>(pa);
+    const float4* qb = reinterpret_cast<const float4*>(pb);
+    for (size_t i = (size_t)part * THREADS + threadIdx.x; i < plane / 4; i += stride) {
+      const float4 y = qb[i];
+      const float4 x = REPR == ADORYM_OBJ_DELTA_BETA ? y : qa[i];
+      mx = fmaxf(mx, fmaxf(fmaxf(absorb_gain<REPR>(kdz, x.x, y.x), absorb_gain<REPR>(kdz, x.y, y.y)),
+                           fmaxf(absorb_gain<REPR>(kdz, x.z, y.z), absorb_gain<REPR>(kdz, x.w, y.w))));
+    }
+  } else {
+    for (size_t i = (size_t)part * THREADS + threadIdx.x; i < plane; i += stride)
+      mx = fmaxf(mx, absorb_gain<REPR>(kdz, REPR == ADORYM_OBJ_DELTA_BETA ? 0.f : pa[i], pb[i]));
+  }
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = 0.f;
+    for (int w = 0; w < THREADS / 64; ++w) m = fmaxf(m, wmax[w]);
+    atomicMax(out + j, __float_as_uint(m));
+  }
+}
+
+// The per-slice absorption bounds of one object, computed by workgroups of
+// the probe-spectrum launch (null `out`: none).
+struct AbsorbJob {
+  const float* a;
+  const float* b;
+  size_t plane;             // voxels per slice
+  float kdz;
+  unsigned* out;            // [S], cleared before the launch
+  int parts;                // workgroups per slice
+  int repr;                 // ADORYM_OBJ_*
+};
+
 // Probe spectrum Q = DFT(p) / N^2 (natural [ky][kx]).  One group of K
-// workgroups (block index = part); K > 1 exchanges through xbuf.
+// workgroups (probe_grid); K > 1 exchanges through xbuf.  The workgroups
+// after the group's grid compute the absorption bounds of `ab`, parts
+// workgroups per slice (they need nothing from the spectrum).
 template <class C>
 __global__ void __launch_bounds__(C::THREADS) probe_spectrum_kernel(const float2* __restrict__ probe,
                                                                     float2* __restrict__ q, float2* xbuf,
-                                                                    int* counter, int* xcc, int* err) {
+                                                                    int* counter, int* xcc, int* err,
+                                                                    AbsorbJob ab) {
   __shared__ MsShared<C> sh;
-  const int part = blockIdx.x;
+  if (blockIdx.x >= probe_grid<C>()) {
+    const int i = (int)(blockIdx.x - probe_grid<C>());
+    float* wmax = reinterpret_cast<float*>(sh.red);
+    if (ab.repr == ADORYM_OBJ_DELTA_BETA)
+      absorb_bound_part<ADORYM_OBJ_DELTA_BETA, C::THREADS>(ab.a, ab.b, ab.plane, ab.kdz, ab.out, i / ab.parts,
+                                                            i % ab.parts, ab.parts, wmax);
+    else
+      absorb_bound_part<ADORYM_OBJ_REAL_IMAG, C::THREADS>(ab.a, ab.b, ab.plane, ab.kdz, ab.out, i / ab.parts,
+                                                           i % ab.parts, ab.parts, wmax);
+    return;
+  }
+  if (probe_idle<C>()) return;
+  const int part = probe_part<C>();
   Work<C> wk(threadIdx.x, 0, part);
   wk.x.buf = xbuf; wk.x.counter = counter; wk.x.err = err; wk.x.phase = 0; wk.x.local = false;
   const Lane<C>& ln = wk.ln;
@@ -1094,66 +1184,17 @@ __global__ void __launch_bounds__(C::THREADS) probe_spectrum_kernel(const float2
   for (int m = 0; m < C::R; ++m) q[ln.pos_spec(m) * N + ln.line] = cscale(v[m], s);
 }
 
-static __global__ void reset_ints_kernel(int* p, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
-}
-
-// Per slice j, the largest -log|t| over the slice's voxels, i.e. the most a
-// division by t_j can amplify a value (log scale; negative values count as
-// 0): k dz beta for delta/beta objects, -log|O| for real/imaginary ones
-// (infinite where O = 0).  Non-negative floats order like their bit
-// patterns, so the workgroups of a slice combine by an integer maximum into
-// out[j] (cleared before).  NaN voxels are ignored.
-template <int REPR>
-__device__ __forceinline__ float absorb_gain(float kdz, float x, float y) {
-  if constexpr (REPR == ADORYM_OBJ_DELTA_BETA) {
-    return kdz * y;
-  } else {
-    const float m2 = x * x + y * y;
-    return m2 > 0.f ? -0.5f * logf(m2) : INFINITY;
-  }
-}
-template <int REPR>
-static __global__ void __launch_bounds__(256) absorb_bound_kernel(const float* __restrict__ a,
-                                                                  const float* __restrict__ b, size_t plane,
-                                                                  float kdz, unsigned* __restrict__ out) {
-  __shared__ float wmax[4];
-  const int j = blockIdx.y;
-  const float* pa = a + (size_t)j * plane;
-  const float* pb = b + (size_t)j * plane;
-  float mx = 0.f;
-  const size_t stride = (size_t)gridDim.x * 256;
-  if ((plane & 3) == 0 && ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0) {
-    // four voxels per load (every slice starts on a 16-byte boundary)
-    const float4* qa = reinterpret_cast<const float4*>(pa);
-    const float4* qb = reinterpret_cast<const float4*>(pb);
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < plane / 4; i += stride) {
-      const float4 y = qb[i];
-      const float4 x = REPR == ADORYM_OBJ_DELTA_BETA ? y : qa[i];
-      mx = fmaxf(mx, fmaxf(fmaxf(absorb_gain<REPR>(kdz, x.x, y.x), absorb_gain<REPR>(kdz, x.y, y.y)),
-                           fmaxf(absorb_gain<REPR>(kdz, x.z, y.z), absorb_gain<REPR>(kdz, x.w, y.w))));
-    }
-  } else {
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < plane; i += stride)
-      mx = fmaxf(mx, absorb_gain<REPR>(kdz, REPR == ADORYM_OBJ_DELTA_BETA ? 0.f : pa[i], pb[i]));
-  }
-  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
-  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    atomicMax(out + j, __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]))));
-}
 
 // Sums of the per-position partials: probe-gradient spectrum (natural
-// order, positions in index order), loss (block 0: a fixed-order strided
-// sum per thread, then a fixed-order tree), shift gradients (block 0).
-static __global__ void __launch_bounds__(256) reduce_partials_kernel(
-    const float2* __restrict__ gacc, int nb, int nn, float2* __restrict__ gsum, const double* __restrict__ loss_part,
-    const double* __restrict__ gs_part, int k, double* __restrict__ loss, float* __restrict__ g_shift,
-    int accumulate) {
-  __shared__ double red[256];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gacc && i < nn) {
+// order, positions in index order; workgroup `blk` of `nblk` takes every
+// nblk-th run of 256 elements), loss (workgroup 0: a fixed-order strided sum
+// per thread, then a fixed-order tree), shift gradients (workgroup 0).
+// 256 threads; `red` holds 256 doubles.
+__device__ void sum_partials(int blk, int nblk, const float2* __restrict__ gacc, int nb, int nn,
+                             float2* __restrict__ gsum, const double* __restrict__ loss_part,
+                             const double* __restrict__ gs_part, int k, double* __restrict__ loss,
+                             float* __restrict__ g_shift, int accumulate, double* red) {
+  for (int i = blk * 256 + (int)threadIdx.x; gacc && i < nn; i += nblk * 256) {
     float sx = 0.f, sy = 0.f;
     int bb = 0;
     for (; bb + 8 <= nb; bb += 8) {           // eight loads in flight, added in order
@@ -1170,20 +1211,20 @@ static __global__ void __launch_bounds__(256) reduce_partials_kernel(
     }
     gsum[i] = make_float2(sx, sy);
   }
-  if (blockIdx.x != 0) return;
+  if (blk != 0) return;
   if (loss) {
     double s = 0.0;
-    for (int t = threadIdx.x; t < nb * k; t += blockDim.x) s += loss_part[t];
+    for (int t = threadIdx.x; t < nb * k; t += 256) s += loss_part[t];
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    for (int h = 128; h > 0; h >>= 1) {
       if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
       __syncthreads();
     }
     if (threadIdx.x == 0) *loss = red[0];
   }
   if (g_shift) {
-    for (int bb = threadIdx.x; bb < nb; bb += blockDim.x) {
+    for (int bb = threadIdx.x; bb < nb; bb += 256) {
       double sy = 0.0, sx = 0.0;
       for (int p = 0; p < k; ++p) {
         sy += gs_part[2 * (bb * k + p)];
@@ -1195,14 +1236,34 @@ static __global__ void __launch_bounds__(256) reduce_partials_kernel(
   }
 }
 
+// The arguments of sum_partials for a launch that runs it next to other work.
+struct PartialsJob {
+  const float2* gacc;
+  int nb, nn;
+  float2* gsum;
+  const double* loss_part;
+  const double* gs_part;
+  int k;
+  double* loss;
+  float* g_shift;
+  int accumulate;
+};
+
+static __global__ void __launch_bounds__(256) reduce_partials_kernel(PartialsJob pj) {
+  __shared__ double red[256];
+  sum_partials(blockIdx.x, gridDim.x, pj.gacc, pj.nb, pj.nn, pj.gsum, pj.loss_part, pj.gs_part, pj.k, pj.loss,
+               pj.g_shift, pj.accumulate, red);
+}
+
 // Probe gradient g_p = IDFT(sum_b G_b conj(e_b)) / N^2 from the natural-order
 // sum.  One group of K workgroups, as probe_spectrum_kernel.
 template <class C>
 __global__ void __launch_bounds__(C::THREADS) probe_grad_kernel(const float2* __restrict__ gsum,
                                                                 float2* __restrict__ g_probe, int accumulate,
                                                                 float2* xbuf, int* counter, int* xcc, int* err) {
+  if (probe_idle<C>()) return;
   __shared__ MsShared<C> sh;
-  const int part = blockIdx.x;
+  const int part = probe_part<C>();
   Work<C> wk(threadIdx.x, 0, part);
   wk.x.buf = xbuf; wk.x.counter = counter; wk.x.err = err; wk.x.phase = 0; wk.x.local = false;
   const Lane<C>& ln = wk.ln;
@@ -1227,8 +1288,9 @@ __global__ void __launch_bounds__(C::THREADS) probe_grad_kernel(const float2* __
 }
 
 
-// Object gradient from the staged per-position contributions.  One
-// workgroup per kRedTx x kRedTy voxel tile of one slice: it lists, in index
+// Object gradient from the staged per-position contributions (and, in an
+// extra slab of the grid, the per-position partials).  One workgroup per
+// kRedTx x kRedTy voxel tile of one slice: it lists, in index
 // order, the positions whose chunk overlaps the tile (chunks outside the
 // object are skipped, as in the multislice kernel); every voxel then sums the
 // contributions of those positions in that order in FP64 and is written once,
@@ -1252,9 +1314,17 @@ constexpr uint32_t kRedOutside = 0xFFFFFFF0u;   // beyond any plane: reads 0
 static __global__ void __launch_bounds__(256) grad_reduce_kernel(const float* __restrict__ stage,
                                                                  const int32_t* __restrict__ corner, int n, int B,
                                                                  int S, int Ly, int Lx, float* __restrict__ g_a,
-                                                                 float* __restrict__ g_b, int accumulate) {
+                                                                 float* __restrict__ g_b, int accumulate,
+                                                                 PartialsJob pj) {
   __shared__ int lb[kRedList], lcy[kRedList], lcx[kRedList];
   __shared__ int wave_cnt[4];
+  if ((int)blockIdx.z == S) {
+    // the last slab of the grid sums the per-position partials meanwhile
+    __shared__ double red[256];
+    sum_partials(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, pj.gacc, pj.nb, pj.nn, pj.gsum,
+                 pj.loss_part, pj.gs_part, pj.k, pj.loss, pj.g_shift, pj.accumulate, red);
+    return;
+  }
   constexpr int RY = kRedTy / 4;                  // rows per thread
   constexpr int RX = kRedTx / 64;                 // columns per thread
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1450,37 +1520,43 @@ MsParams make_params(adorym_ctx* ctx, const adorym_geom* g, const float* a, cons
 }
 
 // Tile of the one-group probe kernels: the whole field in one workgroup for
-// small probes, else split over four workgroups (four CUs).
+// small probes, else split over four workgroups (four CUs of one XCD; for
+// N = 128 that is faster than one 1024-thread workgroup with LDS transposes).
 template <int N, int L>
 using ProbeCfg = TileCfg<N, L, (N >= 128 ? 4 : 1)>;
 
 // Per-job work before the multislice kernel: clear the barrier counters,
-// probe spectrum; before a reverse sweep that steps backwards through
-// slices (`reverse`), the per-slice absorption bounds.
+// then one launch for the probe spectrum and, before a reverse sweep that
+// steps backwards through slices (`reverse`), the per-slice absorption
+// bounds.
 template <int N, int L>
 void launch_prologue(const MsParams& P, const float* probe, const adorym_geom* g, hipStream_t st, bool reverse) {
   using PC = ProbeCfg<N, L>;
   const WsLayout w = ws_layout(g, P.B);
   int* aux = reinterpret_cast<int*>(reinterpret_cast<char*>(P.counters) - w.counters + w.aux);
-  hipLaunchKernelGGL(reset_ints_kernel, dim3(1), dim3(256), 0, st, P.counters, P.B + P.S);
+  // the multislice counters and slice bounds, the XCD ids and the probe
+  // kernels' counters lie in one run of the workspace
+  hipLaunchKernelGGL(reset_ints_kernel, dim3(1), dim3(256), 0, st, P.counters,
+                     (int)((w.aux - w.counters) / sizeof(int)) + 64);
+  AbsorbJob ab{};
+  unsigned blocks = probe_grid<PC>();
   if (reverse && P.ckpt_every > 1 && P.S > 2) {
-    const size_t plane = (size_t)P.Ly * P.Lx;
-    const dim3 grid((unsigned)std::min<size_t>(64, (plane + 16383) / 16384), P.S);
-    unsigned* bound = reinterpret_cast<unsigned*>(P.counters + P.B);
-    if (g->obj_repr == ADORYM_OBJ_DELTA_BETA)
-      hipLaunchKernelGGL(absorb_bound_kernel<ADORYM_OBJ_DELTA_BETA>, grid, dim3(256), 0, st, P.a, P.b, plane, P.kdz,
-                         bound);
-    else
-      hipLaunchKernelGGL(absorb_bound_kernel<ADORYM_OBJ_REAL_IMAG>, grid, dim3(256), 0, st, P.a, P.b, plane, P.kdz,
-                         bound);
+    ab.a = P.a;
+    ab.b = P.b;
+    ab.plane = (size_t)P.Ly * P.Lx;
+    ab.kdz = P.kdz;
+    ab.out = reinterpret_cast<unsigned*>(P.counters + P.B);
+    ab.parts = (int)std::min<size_t>(64, (ab.plane + 64 * PC::THREADS - 1) / (64 * PC::THREADS));
+    ab.repr = g->obj_repr;
+    blocks += (unsigned)(ab.parts * P.S);
   }
-  hipLaunchKernelGGL(reset_ints_kernel, dim3(1), dim3(64), 0, st, aux, 64);
-  hipLaunchKernelGGL((probe_spectrum_kernel<PC>), dim3(PC::K), dim3(PC::THREADS), 0, st,
+  hipLaunchKernelGGL((probe_spectrum_kernel<PC>), dim3(blocks), dim3(PC::THREADS), 0, st,
                      reinterpret_cast<const float2*>(probe), const_cast<float2*>(P.q), P.xbuf, aux, aux + 8,
-                     P.err);
+                     P.err, ab);
 }
 
-// Per-job work after it: loss, shift gradients, probe gradient.
+// Per-job work after it: loss, shift gradients, probe gradient; with object
+// gradients the partial sums run in the object-gradient reduction's launch.
 template <int N, int L>
 void launch_epilogue(const MsParams& P, void* ws, const adorym_geom* g, double* loss, float* g_probe,
                      float* g_shift, hipStream_t st, const Defocus* df = nullptr) {
@@ -1490,8 +1566,14 @@ void launch_epilogue(const MsParams& P, void* ws, const adorym_geom* g, double* 
   float2* gsum = reinterpret_cast<float2*>(static_cast<char*>(ws) + w.gsum);
   const int accumulate = (g->flags & ADORYM_ACCUMULATE_GRADS) ? 1 : 0;
   const int nn = N * N;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((nn + 255) / 256), dim3(256), 0, st, P.gacc, P.B, nn, gsum,
-                     P.loss_part, P.gs_part, P.ksplit, loss, g_shift, accumulate);
+  const PartialsJob pj{P.gacc, P.B, nn, gsum, P.loss_part, P.gs_part, P.ksplit, loss, g_shift, accumulate};
+  if (P.gstage) {
+    const dim3 grid((P.Lx + kRedTx - 1) / kRedTx, (P.Ly + kRedTy - 1) / kRedTy, P.S + 1);
+    hipLaunchKernelGGL(grad_reduce_kernel, grid, dim3(256), 0, st, P.gstage, P.corner, N, P.B, P.S, P.Ly, P.Lx,
+                       P.g_a, P.g_b, accumulate, pj);
+  } else {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((nn + 255) / 256), dim3(256), 0, st, pj);
+  }
   if (df && P.gacc) {
     // the per-position probe partials are consumed by now: their first bytes
     // hold the defocus-gradient shares
@@ -1501,13 +1583,8 @@ void launch_epilogue(const MsParams& P, void* ws, const adorym_geom* g, double* 
     hipLaunchKernelGGL(defocus_finish_kernel, dim3(1), dim3(kDefocusParts), 0, st, part, df->g_dist, accumulate);
   }
   if (g_probe)
-    hipLaunchKernelGGL((probe_grad_kernel<PC>), dim3(PC::K), dim3(PC::THREADS), 0, st, gsum,
+    hipLaunchKernelGGL((probe_grad_kernel<PC>), dim3(probe_grid<PC>()), dim3(PC::THREADS), 0, st, gsum,
                        reinterpret_cast<float2*>(g_probe), accumulate, P.xbuf, aux + 1, aux + 16, P.err);
-  if (P.gstage) {
-    const dim3 grid((P.Lx + kRedTx - 1) / kRedTx, (P.Ly + kRedTy - 1) / kRedTy, P.S);
-    hipLaunchKernelGGL(grad_reduce_kernel, grid, dim3(256), 0, st, P.gstage, P.corner, N, P.B, P.S, P.Ly, P.Lx,
-                       P.g_a, P.g_b, accumulate);
-  }
 }
 
 // Lanes per line of the one-group probe kernels and the job parameters: one
