@@ -162,6 +162,30 @@ def test_accumulate_flag_adds(ctx):
         assert rel_l2(acc[k].cpu().numpy(), 2 * g1[k].cpu().numpy()) < 1e-6, k
 
 
+@pytest.mark.parametrize("n,lat", [(64, 90), (128, 140)])
+def test_outputs_left_out_leave_the_others_bitwise_unchanged(ctx, n, lat):
+    """The loss alone, and the loss with only the probe and shift gradients,
+    equal the full call's bit for bit.  Without object gradients the partial
+    sums run in a launch of their own instead of beside the object-gradient
+    reduction."""
+    import torch
+    sc = synth.small_case(seed=33, n=n, n_slices=5, lateral=lat, n_pos=3, strength=30.0)
+    case = Case(sc)
+    inp, i_meas = case.torch_inputs()
+    geom = _geom(case)
+    full = ctx.loss_grad(geom, **inp, i_meas=i_meas)
+    loss_only = ctx.loss_grad(geom, **inp, i_meas=i_meas, grads=False)
+    part = {"g_probe": torch.empty_like(full["g_probe"]), "g_shift": torch.empty_like(full["g_shift"])}
+    probe_only = ctx.loss_grad(geom, **inp, i_meas=i_meas, grads=False, out=part)
+    torch.cuda.synchronize()
+    ctx.sync_error()
+    assert "g_a" not in loss_only and "g_a" not in probe_only
+    assert loss_only["loss"].item() == full["loss"].item()
+    assert probe_only["loss"].item() == full["loss"].item()
+    for k in ("g_probe", "g_shift"):
+        assert torch.equal(probe_only[k], full[k]), k
+
+
 def test_chunk_out_of_range_is_flagged_and_skipped(ctx):
     import torch
     from paper_2012_12686_amd._lib import AdorymError, ERANGE
