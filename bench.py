@@ -466,6 +466,33 @@ def bench_differentiation(args):
     bytes_launch = algorithmic_bytes_per_position(n, s, args.ckpt) * mb
     achieved = bytes_launch / kern_avg_s / 1e9
     flops = algorithmic_flops_per_position(n, s) * mb / kern_avg_s / 1e12
+
+    # The same minibatches through the torch.autograd.Function front end
+    # (default form: loss in forward, the reverse sweep from the kept
+    # checkpoints when backward runs), timed apart from the line's value.
+    from paper_2012_12686_amd import multislice_loss
+    leaves = [t.clone().requires_grad_() for t in (a, b, probe)]
+    pos_all = to_t(sc.eval_positions, torch.float64)
+
+    def ag_step(k):
+        sl = slice((k % n_mb) * mb, (k % n_mb + 1) * mb)
+        pos = pos_all[sl].clone().requires_grad_()
+        for t in leaves:
+            t.grad = None
+        multislice_loss(*leaves, pos, i_meas[sl], geom, ctx).backward()
+
+    n_ag = min(args.steps, 12)
+    for k in range(2):
+        ag_step(k)
+    torch.cuda.synchronize()
+    t_ag = time.perf_counter()
+    for k in range(n_ag):
+        ag_step(k)
+    torch.cuda.synchronize()
+    ag_ms = 1e3 * (time.perf_counter() - t_ag) / n_ag
+    ctx.sync_error()
+    del leaves
+
     line = {
         "metric": "multislice fwd+adjoint positions/s, % HBM roofline (differentiation workload)",
         "value": mb * args.steps / elapsed, "unit": "positions/s", "n_gpus": 1, "steps": args.steps,
@@ -476,6 +503,9 @@ def bench_differentiation(args):
                                "delta, beta, probe and shifts", "global_batch": mb, "seq_len": s,
                    "parallelism": "none"},
         "p50_iter_ms": float(np.percentile(lat, 50)), "p99_iter_ms": float(np.percentile(lat, 99)),
+        "autograd": {"ms_per_step": ag_ms, "positions_per_s": mb / ag_ms * 1e3, "steps": n_ag,
+                     "form": "multislice_loss(...).backward(): adorym_loss_fwd in forward, adorym_loss_bwd "
+                             "in backward"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "multislice_kernel<N=128, delta/beta, Gaussian, loss+adjoint>",

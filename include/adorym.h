@@ -295,8 +295,11 @@ adorym_status adorym_loss_grad_modes(adorym_ctx* ctx, const adorym_geom* g,
  * gradients of grad_scale * L (grad_scale a finite float32 value; the
  * reverse sweep is linear in it).  Gradient pointers and
  * ADORYM_ACCUMULATE_GRADS as in adorym_loss_grad.  Both run with the fixed
- * split of ADORYM_DETERMINISTIC; with grad_scale = 1 the gradients equal,
- * bit for bit, those of adorym_loss_grad with ADORYM_DETERMINISTIC. */
+ * split of ADORYM_DETERMINISTIC, except at N = 128 with more than 128
+ * positions and without that flag, where they use one workgroup per
+ * position, the split adorym_loss_grad chooses there unless adorym_set_split
+ * overrides it.  With grad_scale = 1 the gradients equal, bit for bit, those
+ * of adorym_loss_grad run with the same split. */
 size_t adorym_loss_fwd_workspace_size(const adorym_geom* g, int32_t batch);
 adorym_status adorym_loss_fwd(adorym_ctx* ctx, const adorym_geom* g,
                               const float* obj_a, const float* obj_b, const float* probe,

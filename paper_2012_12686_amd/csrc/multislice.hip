@@ -40,6 +40,7 @@ extern template ADORYM_BATCHED_SIGNATURE(192, 16, 8);
 extern template ADORYM_RUN_SPLIT_SIGNATURE(64, 8, 1);
 extern template ADORYM_RUN_SPLIT_SIGNATURE(96, 8, 1);
 extern template ADORYM_RUN_SPLIT_SIGNATURE(128, 16, 4);
+extern template ADORYM_RUN_SPLIT_SIGNATURE(128, 8, 1);
 extern template ADORYM_RUN_SPLIT_SIGNATURE(192, 16, 6);
 extern template ADORYM_RUN_NF_SIGNATURE(64, 8, 1);
 extern template ADORYM_RUN_NF_SIGNATURE(96, 8, 1);
@@ -605,6 +606,18 @@ FwdLayout fwd_layout(const adorym_geom* g, int batch) {
   return l;
 }
 
+// Split of loss-now / gradients-later: the deterministic split, except at
+// N = 128 with more than 128 positions, where one workgroup per position
+// already covers the CUs and the automatic rule of adorym_loss_grad picks
+// K = 1 as well (the fixed K = 4 would be a quarter slower there).  It
+// depends on N, the batch and the flags only, so adorym_loss_fwd and
+// adorym_loss_bwd on the same arguments agree (the workspace's checkpoint and
+// exit-wave slots are laid out per workgroup).
+int split_pass_k(const adorym_geom* g, int batch) {
+  if (g->n == 128 && !(g->flags & ADORYM_DETERMINISTIC) && 2 * batch > 256) return 1;
+  return det_split(g->n);
+}
+
 adorym_status split_pass(adorym_ctx* ctx, const adorym_geom* g, const float* a, const float* b, const float* probe,
                          const int32_t* corner, const float* shift, int batch, const float* i_meas, void* ws,
                          float2* ckpt, float2* exit_wave, double* loss, float* g_a, float* g_b, float* g_probe,
@@ -615,7 +628,9 @@ adorym_status split_pass(adorym_ctx* ctx, const adorym_geom* g, const float* a, 
   switch (g->n) {
     case 64: ADORYM_RUN_SPLIT(64, 8, 1);
     case 96: ADORYM_RUN_SPLIT(96, 8, 1);
-    case 128: ADORYM_RUN_SPLIT(128, 16, 4);
+    case 128:
+      if (split_pass_k(g, batch) == 1) ADORYM_RUN_SPLIT(128, 8, 1);
+      ADORYM_RUN_SPLIT(128, 16, 4);
     case 192: ADORYM_RUN_SPLIT(192, 16, 6);
   }
 #undef ADORYM_RUN_SPLIT
