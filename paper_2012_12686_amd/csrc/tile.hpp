@@ -314,10 +314,10 @@ struct TileCfg {
   static constexpr int REGS = 512 / WAVES_PER_SIMD;
   // With 256 or fewer registers the scheduler is fenced so that table loads
   // are not hoisted early (they spill otherwise); tiles with the full 512
-  // registers and up to 16 values per lane, or 256 registers and up to 8,
+  // registers and up to 16 values per lane, or 256 registers and up to 12,
   // also prefetch the next slice's chunk.
   static constexpr bool FENCE = REGS <= 256;
-  static constexpr bool PREFETCH = (REGS >= 512 && R <= 16) || (REGS >= 256 && R <= 8);
+  static constexpr bool PREFETCH = (REGS >= 512 && R <= 16) || (REGS >= 256 && R <= 12);
   static_assert(N % L == 0 && LINES % RPW == 0 && WAVES >= 1, "bad tile");
 };
 
